@@ -1,0 +1,479 @@
+/*
+ * ORACLE -- test infrastructure only.  Nothing in the product path may link,
+ * load or call this file; it exists to check the GPU path.
+ *
+ * Plain FP64 McMurchie-Davidson Gaussian integrals (Hermite expansion
+ * coefficients E^{ij}_t and Hermite Coulomb integrals R_{tuv}), the textbook
+ * route of Helgaker, Jorgensen & Olsen, "Molecular Electronic-Structure
+ * Theory", ch. 9.  The paper evaluates electron-repulsion integrals by Rys
+ * quadrature (section "Molecular integrals"); the oracle deliberately uses a
+ * different exact algorithm so that the two share nothing but the definition
+ *
+ *     (ab|c) = int int phi_a(r1) phi_b(r1) |r1 - r2|^-1 phi_c(r2) dr1 dr2 .
+ *
+ * Shells arrive already normalised: coef[k] multiplies the *unnormalised*
+ * Cartesian primitive x^i y^j z^k exp(-alpha r^2), and sph[l] maps Cartesian
+ * monomials (lexicographic order, x-power descending) to real solid harmonics
+ * m = -l..l.  Both tables are made by the Python side of the oracle.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define LMAX 6          /* highest l of any single shell the oracle accepts */
+#define LTOT 24         /* highest total l of an integral (4 * LMAX) */
+
+static const double PI = 3.14159265358979323846264338327950288;
+
+typedef struct {
+  int nsh;
+  const double *ctr;     /* [nsh][3] */
+  const int *l;          /* [nsh] */
+  const int *nprim;      /* [nsh] */
+  const int *poff;       /* [nsh] offset into exps/coef */
+  const double *exps;
+  const double *coef;    /* normalised primitive coefficients */
+  const int *foff;       /* [nsh] first spherical function */
+} obasis;
+
+/* sph tables: for each l, a (2l+1) x ncart(l) row-major matrix */
+static const double *g_sph[LMAX + 1];
+
+void oracle_set_sph(int l, const double *tab) { g_sph[l] = tab; }
+
+static inline int ncart(int l) { return (l + 1) * (l + 2) / 2; }
+
+static void cart_powers(int l, int (*p)[3]) {
+  int n = 0;
+  for (int i = l; i >= 0; --i)
+    for (int j = l - i; j >= 0; --j) {
+      p[n][0] = i; p[n][1] = j; p[n][2] = l - i - j; ++n;
+    }
+}
+
+/* ---- Boys function F_m(T) = int_0^1 t^{2m} exp(-T t^2) dt, m = 0..mmax ---- */
+void oracle_boys(int mmax, double T, double *F) {
+  if (T < 1e-15) {
+    /* F_m(T) = sum_k (-T)^k / (k! (2m+2k+1)); two terms suffice here */
+    for (int m = 0; m <= mmax; ++m) F[m] = 1.0 / (2 * m + 1) - T / (2 * m + 3);
+    return;
+  }
+  const double eT = exp(-T);
+  if (T < 50.0) {
+    /* series: F_m(T) = e^{-T} sum_k (2T)^k / ((2m+1)(2m+3)...(2m+2k+1)),
+       all terms positive; then downward recursion, which is stable */
+    double term = 1.0 / (2 * mmax + 1), sum = term;
+    for (int k = 1; k < 4000; ++k) {
+      term *= 2.0 * T / (2 * mmax + 2 * k + 1);
+      sum += term;
+      if (term < 1e-18 * sum) break;
+    }
+    F[mmax] = eT * sum;
+    for (int m = mmax - 1; m >= 0; --m) F[m] = (2.0 * T * F[m + 1] + eT) / (2 * m + 1);
+  } else {
+    /* F_0 from the error function, then upward recursion (stable for T > m) */
+    F[0] = 0.5 * sqrt(PI / T) * erf(sqrt(T));
+    for (int m = 0; m < mmax; ++m) F[m + 1] = ((2 * m + 1) * F[m] - eT) / (2.0 * T);
+  }
+}
+
+/* ---- Hermite expansion coefficients for one Cartesian direction ----
+ * E[i][j][t], i <= la, j <= lb, t <= i + j, for the product
+ * x_A^i exp(-a x_A^2) x_B^j exp(-b x_B^2), with XAB = A - B.          */
+#define ED (2 * LMAX + 3)
+static void hermite_E(int la, int lb, double a, double b, double XAB,
+                      double E[ED][ED][2 * ED]) {
+  const double p = a + b, mu = a * b / p;
+  const double XPA = -b / p * XAB, XPB = a / p * XAB, h = 0.5 / p;
+  for (int i = 0; i <= la; ++i)
+    for (int j = 0; j <= lb; ++j)
+      for (int t = 0; t <= i + j + 1; ++t) E[i][j][t] = 0.0;
+  E[0][0][0] = exp(-mu * XAB * XAB);
+  for (int i = 0; i <= la; ++i) {
+    for (int j = 0; j <= lb; ++j) {
+      if (i == 0 && j == 0) continue;
+      for (int t = 0; t <= i + j; ++t) {
+        double v;
+        if (i > 0) {
+          v = XPA * E[i - 1][j][t];
+          if (t > 0) v += h * E[i - 1][j][t - 1];
+          if (t + 1 <= i - 1 + j) v += (t + 1) * E[i - 1][j][t + 1];
+        } else {
+          v = XPB * E[i][j - 1][t];
+          if (t > 0) v += h * E[i][j - 1][t - 1];
+          if (t + 1 <= i + j - 1) v += (t + 1) * E[i][j - 1][t + 1];
+        }
+        E[i][j][t] = v;
+      }
+    }
+  }
+}
+
+/* ---- Hermite Coulomb integrals R_{tuv} = R^0_{tuv}(alpha, X,Y,Z), t+u+v <= L ----
+ * R^n_{000} = (-2 alpha)^n F_n(alpha R^2) and
+ * R^n_{t+1,u,v} = t R^{n+1}_{t-1,u,v} + X R^{n+1}_{t,u,v} (likewise u, v). */
+#define RD (LTOT + 1)
+static void hermite_R(int L, double alpha, double X, double Y, double Z, double *R) {
+  double F[LTOT + 1];
+  oracle_boys(L, alpha * (X * X + Y * Y + Z * Z), F);
+  double *cur = (double *)malloc(sizeof(double) * RD * RD * RD);
+  double *nxt = (double *)malloc(sizeof(double) * RD * RD * RD);
+#define IX(t, u, v) (((t) * RD + (u)) * RD + (v))
+  double f = 1.0;
+  for (int n = 0; n < L; ++n) f *= -2.0 * alpha;
+  cur[IX(0, 0, 0)] = f * F[L];
+  for (int n = L - 1; n >= 0; --n) {
+    f /= -2.0 * alpha;
+    nxt[IX(0, 0, 0)] = f * F[n];
+    const int N = L - n;
+    for (int tot = 1; tot <= N; ++tot)
+      for (int t = 0; t <= tot; ++t)
+        for (int u = 0; u <= tot - t; ++u) {
+          const int v = tot - t - u;
+          double r;
+          if (t > 0) {
+            r = X * cur[IX(t - 1, u, v)];
+            if (t > 1) r += (t - 1) * cur[IX(t - 2, u, v)];
+          } else if (u > 0) {
+            r = Y * cur[IX(t, u - 1, v)];
+            if (u > 1) r += (u - 1) * cur[IX(t, u - 2, v)];
+          } else {
+            r = Z * cur[IX(t, u, v - 1)];
+            if (v > 1) r += (v - 1) * cur[IX(t, u, v - 2)];
+          }
+          nxt[IX(t, u, v)] = r;
+        }
+    double *tmp = cur; cur = nxt; nxt = tmp;
+  }
+  for (int t = 0; t <= L; ++t)
+    for (int u = 0; u <= L - t; ++u)
+      for (int v = 0; v <= L - t - u; ++v) R[IX(t, u, v)] = cur[IX(t, u, v)];
+  free(cur);
+  free(nxt);
+#undef IX
+}
+#define RIX(t, u, v) (((t) * RD + (u)) * RD + (v))
+
+/* Hermite expansion of one (bra) product in all three directions */
+typedef struct {
+  double Ex[ED][ED][2 * ED], Ey[ED][ED][2 * ED], Ez[ED][ED][2 * ED];
+  double p, P[3];
+} hprod;
+
+static void make_prod(hprod *h, int la, int lb, double a, const double *A, double b,
+                      const double *B) {
+  h->p = a + b;
+  for (int k = 0; k < 3; ++k) h->P[k] = (a * A[k] + b * B[k]) / h->p;
+  hermite_E(la, lb, a, b, A[0] - B[0], h->Ex);
+  hermite_E(la, lb, a, b, A[1] - B[1], h->Ey);
+  hermite_E(la, lb, a, b, A[2] - B[2], h->Ez);
+}
+
+/* ---- spherical transform of one index of a contracted Cartesian block ----
+ * in:  [pre][ncart(l)][post]   out: [pre][2l+1][post]                      */
+static void sph_index(const double *in, double *out, int pre, int l, int post) {
+  const int nc = ncart(l), ns = 2 * l + 1;
+  const double *T = g_sph[l];
+  for (int i = 0; i < pre; ++i)
+    for (int m = 0; m < ns; ++m)
+      for (int k = 0; k < post; ++k) {
+        double s = 0.0;
+        for (int c = 0; c < nc; ++c) s += T[m * nc + c] * in[(i * nc + c) * post + k];
+        out[(i * ns + m) * post + k] = s;
+      }
+}
+
+/* ---- generic two-electron integral over up to four shells ----
+ * (ab|cd), with b and/or d replaced by an l = 0, alpha = 0 "unit" function
+ * for three- and two-centre integrals.  Result: spherical block
+ * [2la+1][2lb+1][2lc+1][2ld+1] (unit shells count as size 1).           */
+typedef struct { double ctr[3]; int l, nprim, unit; const double *exps, *coef; } oshell;
+
+static oshell get_shell(const obasis *bs, int s) {
+  oshell o;
+  for (int k = 0; k < 3; ++k) o.ctr[k] = bs->ctr[3 * s + k];
+  o.l = bs->l[s];
+  o.nprim = bs->nprim[s];
+  o.exps = bs->exps + bs->poff[s];
+  o.coef = bs->coef + bs->poff[s];
+  o.unit = 0;
+  return o;
+}
+
+static const double UNIT_EXP = 0.0, UNIT_COEF = 1.0;
+static oshell unit_shell(const double *ctr) {
+  oshell o;
+  for (int k = 0; k < 3; ++k) o.ctr[k] = ctr[k];
+  o.l = 0; o.nprim = 1; o.exps = &UNIT_EXP; o.coef = &UNIT_COEF;
+  o.unit = 1;  /* the constant function 1: no solid-harmonic factor */
+  return o;
+}
+
+static void eri_generic(const oshell *A, const oshell *B, const oshell *C, const oshell *D,
+                        double *out) {
+  const int la = A->l, lb = B->l, lc = C->l, ld = D->l;
+  const int na = ncart(la), nb = ncart(lb), nc = ncart(lc), nd = ncart(ld);
+  int pa[28][3], pb[28][3], pc[28][3], pd[28][3];
+  cart_powers(la, pa); cart_powers(lb, pb); cart_powers(lc, pc); cart_powers(ld, pd);
+  const int ntot = na * nb * nc * nd;
+  double *cart = (double *)calloc(ntot, sizeof(double));
+  double *R = (double *)malloc(sizeof(double) * RD * RD * RD);
+  hprod *hb = (hprod *)malloc(sizeof(hprod));
+  hprod *hk = (hprod *)malloc(sizeof(hprod));
+  const int L = la + lb + lc + ld;
+  for (int ia = 0; ia < A->nprim; ++ia)
+    for (int ib = 0; ib < B->nprim; ++ib) {
+      make_prod(hb, la, lb, A->exps[ia], A->ctr, B->exps[ib], B->ctr);
+      const double cab = A->coef[ia] * B->coef[ib];
+      for (int ic = 0; ic < C->nprim; ++ic)
+        for (int id = 0; id < D->nprim; ++id) {
+          make_prod(hk, lc, ld, C->exps[ic], C->ctr, D->exps[id], D->ctr);
+          const double p = hb->p, q = hk->p, alpha = p * q / (p + q);
+          hermite_R(L, alpha, hb->P[0] - hk->P[0], hb->P[1] - hk->P[1], hb->P[2] - hk->P[2], R);
+          const double pref = cab * C->coef[ic] * D->coef[id] * 2.0 * pow(PI, 2.5) /
+                              (p * q * sqrt(p + q));
+          int idx = 0;
+          for (int a = 0; a < na; ++a)
+            for (int b = 0; b < nb; ++b)
+              for (int c = 0; c < nc; ++c)
+                for (int d = 0; d < nd; ++d, ++idx) {
+                  const int ax = pa[a][0] + 0, ay = pa[a][1], az = pa[a][2];
+                  const int bx = pb[b][0], by = pb[b][1], bz = pb[b][2];
+                  const int cx = pc[c][0], cy = pc[c][1], cz = pc[c][2];
+                  const int dx = pd[d][0], dy = pd[d][1], dz = pd[d][2];
+                  double s = 0.0;
+                  for (int t = 0; t <= ax + bx; ++t)
+                    for (int u = 0; u <= ay + by; ++u)
+                      for (int v = 0; v <= az + bz; ++v) {
+                        const double eb = hb->Ex[ax][bx][t] * hb->Ey[ay][by][u] * hb->Ez[az][bz][v];
+                        if (eb == 0.0) continue;
+                        double sk = 0.0;
+                        for (int tt = 0; tt <= cx + dx; ++tt)
+                          for (int uu = 0; uu <= cy + dy; ++uu)
+                            for (int vv = 0; vv <= cz + dz; ++vv) {
+                              const double ek = hk->Ex[cx][dx][tt] * hk->Ey[cy][dy][uu] *
+                                                hk->Ez[cz][dz][vv];
+                              const double sg = ((tt + uu + vv) & 1) ? -1.0 : 1.0;
+                              sk += sg * ek * R[RIX(t + tt, u + uu, v + vv)];
+                            }
+                        s += eb * sk;
+                      }
+                  cart[idx] += pref * s;
+                }
+        }
+    }
+  /* spherical transforms, index by index */
+  const int sa = 2 * la + 1, sb = 2 * lb + 1, sc = 2 * lc + 1, sd = 2 * ld + 1;
+  double *t1 = (double *)malloc(sizeof(double) * ntot);
+  double *t2 = (double *)malloc(sizeof(double) * ntot);
+  sph_index(cart, t1, 1, la, nb * nc * nd);
+  if (B->unit) memcpy(t2, t1, sizeof(double) * sa * nc * nd);
+  else sph_index(t1, t2, sa, lb, nc * nd);
+  sph_index(t2, t1, sa * sb, lc, nd);
+  if (D->unit) memcpy(out, t1, sizeof(double) * sa * sb * sc);
+  else sph_index(t1, out, sa * sb * sc, ld, 1);
+  free(t1); free(t2); free(cart); free(R); free(hb); free(hk);
+}
+
+/* ---- public entry points (blocks and whole matrices) ---- */
+
+/* (ab|cd) spherical block */
+void oracle_eri4_block(const obasis *bs, int a, int b, int c, int d, double *out) {
+  oshell A = get_shell(bs, a), B = get_shell(bs, b), C = get_shell(bs, c), D = get_shell(bs, d);
+  eri_generic(&A, &B, &C, &D, out);
+}
+
+/* (ab|P) spherical block [na][nb][nP] */
+void oracle_eri3_block(const obasis *bs, int a, int b, const obasis *ax, int c, double *out) {
+  oshell A = get_shell(bs, a), B = get_shell(bs, b), C = get_shell(ax, c);
+  oshell D = unit_shell(C.ctr);
+  eri_generic(&A, &B, &C, &D, out);
+}
+
+/* (P|Q) spherical block */
+void oracle_eri2_block(const obasis *ax, int p, int q, double *out) {
+  oshell A = get_shell(ax, p), C = get_shell(ax, q);
+  oshell B = unit_shell(A.ctr), D = unit_shell(C.ctr);
+  eri_generic(&A, &B, &C, &D, out);
+}
+
+static int nsph_of(const obasis *bs, int s) { return 2 * bs->l[s] + 1; }
+
+/* full metric (P|Q), naux x naux row-major */
+void oracle_eri2(const obasis *ax, int naux, double *J) {
+#pragma omp parallel for schedule(dynamic)
+  for (int p = 0; p < ax->nsh; ++p) {
+    double blk[81 * 4];
+    for (int q = 0; q <= p; ++q) {
+      oracle_eri2_block(ax, p, q, blk);
+      const int np = nsph_of(ax, p), nq = nsph_of(ax, q);
+      for (int i = 0; i < np; ++i)
+        for (int j = 0; j < nq; ++j) {
+          const double v = blk[i * nq + j];
+          J[(size_t)(ax->foff[p] + i) * naux + ax->foff[q] + j] = v;
+          J[(size_t)(ax->foff[q] + j) * naux + ax->foff[p] + i] = v;
+        }
+    }
+  }
+}
+
+/* raw (mu nu|P) for a list of shell pairs, packed aux-major:
+ * out[P][col_off[k] + i*nb + j] for pair k = (a_k, b_k).  Pairs whose
+ * triplet (a,b,C) is screened (skip[k*nauxsh + C] != 0) are left as zero. */
+void oracle_eri3_packed(const obasis *bs, const obasis *ax, int npairs, const int *pa,
+                        const int *pb, const long long *col_off, long long ncols,
+                        const unsigned char *skip, double *out) {
+#pragma omp parallel for schedule(dynamic)
+  for (int k = 0; k < npairs; ++k) {
+    const int a = pa[k], b = pb[k];
+    const int na = nsph_of(bs, a), nb = nsph_of(bs, b);
+    double *blk = (double *)malloc(sizeof(double) * na * nb * 13 * 13);
+    for (int C = 0; C < ax->nsh; ++C) {
+      if (skip && skip[(size_t)k * ax->nsh + C]) continue;
+      const int nc = nsph_of(ax, C);
+      oracle_eri3_block(bs, a, b, ax, C, blk);
+      for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j)
+          for (int m = 0; m < nc; ++m)
+            out[(size_t)(ax->foff[C] + m) * ncols + col_off[k] + i * nb + j] =
+                blk[(i * nb + j) * nc + m];
+    }
+    free(blk);
+  }
+}
+
+/* Schwarz factors: Qab[a*nsh+b] = sqrt(max_{mu in a, nu in b} (mu nu|mu nu)),
+ * QC[C] = sqrt(max_{P in C} (P|P)). */
+void oracle_schwarz(const obasis *bs, const obasis *ax, double *Qab, double *QC) {
+#pragma omp parallel for schedule(dynamic)
+  for (int a = 0; a < bs->nsh; ++a) {
+    const int na = nsph_of(bs, a);
+    for (int b = 0; b <= a; ++b) {
+      const int nb = nsph_of(bs, b);
+      double *blk = (double *)malloc(sizeof(double) * na * nb * na * nb);
+      oracle_eri4_block(bs, a, b, a, b, blk);
+      double mx = 0.0;
+      for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j) {
+          const double v = blk[((i * nb + j) * na + i) * nb + j];
+          if (v > mx) mx = v;
+        }
+      Qab[a * bs->nsh + b] = Qab[b * bs->nsh + a] = sqrt(mx);
+      free(blk);
+    }
+  }
+#pragma omp parallel for schedule(dynamic)
+  for (int c = 0; c < ax->nsh; ++c) {
+    const int nc = nsph_of(ax, c);
+    double blk[81 * 4];
+    oracle_eri2_block(ax, c, c, blk);
+    double mx = 0.0;
+    for (int i = 0; i < nc; ++i)
+      if (blk[i * nc + i] > mx) mx = blk[i * nc + i];
+    QC[c] = sqrt(mx);
+  }
+}
+
+/* full 4-index (mu nu|la si), nbf^4 -- tiny systems only */
+void oracle_eri4(const obasis *bs, int nbf, double *G) {
+  const int n = bs->nsh;
+#pragma omp parallel for schedule(dynamic)
+  for (int a = 0; a < n; ++a) {
+    double *blk = (double *)malloc(sizeof(double) * 13 * 13 * 13 * 13);
+    for (int b = 0; b < n; ++b)
+      for (int c = 0; c < n; ++c)
+        for (int d = 0; d < n; ++d) {
+          oracle_eri4_block(bs, a, b, c, d, blk);
+          const int na = nsph_of(bs, a), nb = nsph_of(bs, b), nc = nsph_of(bs, c),
+                    nd = nsph_of(bs, d);
+          for (int i = 0; i < na; ++i)
+            for (int j = 0; j < nb; ++j)
+              for (int k = 0; k < nc; ++k)
+                for (int l = 0; l < nd; ++l)
+                  G[(((size_t)(bs->foff[a] + i) * nbf + bs->foff[b] + j) * nbf + bs->foff[c] + k) *
+                        nbf + bs->foff[d] + l] = blk[((i * nb + j) * nc + k) * nd + l];
+        }
+    free(blk);
+  }
+}
+
+/* ---- one-electron integrals: overlap, kinetic, nuclear attraction ---- */
+static void onee_block(const oshell *A, const oshell *B, int natom, const double *xyz,
+                       const double *Z, double *S, double *T, double *V) {
+  const int la = A->l, lb = B->l, na = ncart(la), nb = ncart(lb);
+  int pa[28][3], pb[28][3];
+  cart_powers(la, pa); cart_powers(lb, pb);
+  double *cs = (double *)calloc(na * nb, sizeof(double));
+  double *ct = (double *)calloc(na * nb, sizeof(double));
+  double *cv = (double *)calloc(na * nb, sizeof(double));
+  double *R = (double *)malloc(sizeof(double) * RD * RD * RD);
+  hprod *h = (hprod *)malloc(sizeof(hprod));
+  for (int ia = 0; ia < A->nprim; ++ia)
+    for (int ib = 0; ib < B->nprim; ++ib) {
+      const double a = A->exps[ia], b = B->exps[ib], p = a + b;
+      const double w = A->coef[ia] * B->coef[ib];
+      /* E up to lb + 2 for the kinetic energy */
+      make_prod(h, la, lb + 2, a, A->ctr, b, B->ctr);
+      const double s1 = sqrt(PI / p);
+      for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j) {
+          const int *e = pa[i], *f = pb[j];
+          double S1[3], D1[3];
+          for (int k = 0; k < 3; ++k) {
+            double (*E)[ED][2 * ED] = k == 0 ? h->Ex : (k == 1 ? h->Ey : h->Ez);
+            const int ii = e[k], jj = f[k];
+            S1[k] = E[ii][jj][0] * s1;
+            /* <i| d^2/dx^2 |j> = 4b^2 S(i,j+2) - 2b(2j+1) S(i,j) + j(j-1) S(i,j-2) */
+            double d = 4.0 * b * b * E[ii][jj + 2][0] * s1 - 2.0 * b * (2 * jj + 1) * S1[k];
+            if (jj >= 2) d += jj * (jj - 1) * E[ii][jj - 2][0] * s1;
+            D1[k] = d;
+          }
+          cs[i * nb + j] += w * S1[0] * S1[1] * S1[2];
+          ct[i * nb + j] += w * -0.5 *
+                            (D1[0] * S1[1] * S1[2] + S1[0] * D1[1] * S1[2] + S1[0] * S1[1] * D1[2]);
+        }
+      for (int C = 0; C < natom; ++C) {
+        hermite_R(la + lb, p, h->P[0] - xyz[3 * C], h->P[1] - xyz[3 * C + 1],
+                  h->P[2] - xyz[3 * C + 2], R);
+        const double pref = -Z[C] * 2.0 * PI / p * w;
+        for (int i = 0; i < na; ++i)
+          for (int j = 0; j < nb; ++j) {
+            const int *e = pa[i], *f = pb[j];
+            double s = 0.0;
+            for (int t = 0; t <= e[0] + f[0]; ++t)
+              for (int u = 0; u <= e[1] + f[1]; ++u)
+                for (int v = 0; v <= e[2] + f[2]; ++v)
+                  s += h->Ex[e[0]][f[0]][t] * h->Ey[e[1]][f[1]][u] * h->Ez[e[2]][f[2]][v] *
+                       R[RIX(t, u, v)];
+            cv[i * nb + j] += pref * s;
+          }
+      }
+    }
+  const int sa = 2 * la + 1;
+  double *tmp = (double *)malloc(sizeof(double) * na * nb);
+  sph_index(cs, tmp, 1, la, nb); sph_index(tmp, S, sa, lb, 1);
+  sph_index(ct, tmp, 1, la, nb); sph_index(tmp, T, sa, lb, 1);
+  sph_index(cv, tmp, 1, la, nb); sph_index(tmp, V, sa, lb, 1);
+  free(tmp); free(cs); free(ct); free(cv); free(R); free(h);
+}
+
+void oracle_int1e(const obasis *bs, int nbf, int natom, const double *xyz, const double *Z,
+                  double *S, double *T, double *V) {
+#pragma omp parallel for schedule(dynamic)
+  for (int a = 0; a < bs->nsh; ++a) {
+    double s[169], t[169], v[169];
+    oshell A = get_shell(bs, a);
+    for (int b = 0; b <= a; ++b) {
+      oshell B = get_shell(bs, b);
+      onee_block(&A, &B, natom, xyz, Z, s, t, v);
+      const int na = nsph_of(bs, a), nb = nsph_of(bs, b);
+      for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j) {
+          const size_t r = bs->foff[a] + i, c = bs->foff[b] + j;
+          S[r * nbf + c] = S[c * nbf + r] = s[i * nb + j];
+          T[r * nbf + c] = T[c * nbf + r] = t[i * nb + j];
+          V[r * nbf + c] = V[c * nbf + r] = v[i * nb + j];
+        }
+    }
+  }
+}
