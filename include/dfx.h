@@ -1,0 +1,241 @@
+/*
+ * dfx -- density-fitted restricted Hartree-Fock hot path on AMD MI355X (gfx950).
+ *
+ * C-ABI of libdfx.so.  Plain pointers and sizes only.  The operations follow
+ * the paper (T. Shiozaki, "BAGEL: Brilliantly Advanced General
+ * Electronic-structure Library", arXiv:1707.03771):
+ *   - three-index integrals kept in memory, Rys-quadrature ERIs
+ *     (section "Molecular integrals"; "Introduction" on in-memory storage);
+ *   - the density-fitting tensor operations of section "Density fitting
+ *     utilities", Eqs. (1)-(3);
+ *   - a DF-based restricted Hartree-Fock Fock builder (section "Standard
+ *     algorithms").
+ *
+ * Conventions (all entry points):
+ *   units       bohr and hartree.
+ *   basis       spherical (real solid harmonic) functions; within a shell
+ *               m = -l..l; m > 0 ~ cos(m phi), m < 0 ~ sin(|m| phi), no
+ *               Condon-Shortley phase; function order = caller's shell order.
+ *   shells      exps/coefs are host arrays of length nprim; coefs multiply
+ *               normalised primitives and the contracted function is
+ *               renormalised to unit norm.  Orbital shells: l <= 3; auxiliary
+ *               shells: l <= 4.
+ *   matrices    row-major FP64.  D, J, K, S, T, V: nbf x nbf.  C_occ: nbf x nocc.
+ *   streams     `stream` is a hipStream_t (NULL = default stream); calls
+ *               enqueue work on it and return, except where stated.
+ *   errors      every call returns 0 (DFX_OK) or a negative DFX_E* code;
+ *               dfx_last_error() returns the message of the calling thread's
+ *               last failure.  No C++ exception crosses this boundary.
+ *   ownership   device pointers passed in are owned by the caller and never
+ *               freed by the library.  A dfx_B owns the device memory it
+ *               allocates (B, pair lists, metric) until dfx_B_free.
+ */
+#ifndef DFX_H
+#define DFX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define DFX_OK 0
+#define DFX_EINVAL (-1)        /* bad argument (null pointer, negative size, ...) */
+#define DFX_ENOMEM (-2)        /* device allocation failed, or caller buffer too small */
+#define DFX_EHIP (-3)          /* a HIP runtime call failed */
+#define DFX_ENOTPOSDEF (-4)    /* fitting metric not positive definite */
+#define DFX_ENOCONV (-5)       /* SCF did not converge (outputs still written) */
+#define DFX_EUNSUPPORTED (-6)  /* angular momentum beyond the compiled classes */
+
+/* ---- precisions / kinds ---------------------------------------------------- */
+#define DFX_FP64 0   /* B as hi + lo (FP64-equivalent), FP64 MFMA */
+#define DFX_FP32 1   /* B hi word only, FP32 MFMA, FP32 accumulation */
+#define DFX_BF16 2   /* B hi word rounded to BF16, BF16 MFMA, FP32 accumulation */
+
+#define DFX_DENSITY 0  /* dfx_jk input is D (nbf x nbf) */
+#define DFX_COCC 1     /* dfx_jk input is C_occ (nbf x nocc); D = C_occ C_occ^T */
+
+/* ---- inputs ------------------------------------------------------------------ */
+typedef struct {
+  double xyz[3];         /* centre (bohr) */
+  int32_t l;             /* angular momentum */
+  int32_t nprim;         /* number of primitives */
+  const double* exps;    /* [nprim] host */
+  const double* coefs;   /* [nprim] host */
+} dfx_shell;
+
+typedef struct {
+  int32_t natom;
+  const double* xyz;     /* [natom][3] host, bohr */
+  const int32_t* Z;      /* [natom] host, nuclear charges */
+  int32_t charge;        /* total molecular charge */
+} dfx_geom;
+
+/* ---- the fitted three-index tensor ---------------------------------------- */
+typedef struct dfx_B dfx_B;
+
+#define DFX_KEEP_RAW 1      /* keep the raw (mu nu|P) after the transform (tests) */
+#define DFX_KEEP_METRIC 2   /* keep J_PQ and L (tests) */
+
+typedef struct {
+  double tau;            /* Schwarz threshold: (a,b,C) evaluated iff Q_ab Q_C >= tau */
+  int32_t flags;         /* DFX_KEEP_* */
+} dfx_eri3_opts;
+
+typedef struct {
+  int32_t nbf, naux;     /* basis and auxiliary function counts */
+  int32_t nsh, nauxsh;   /* shell counts */
+  int32_t npairs;        /* kept shell pairs a >= b */
+  int64_t ncols;         /* canonical packed columns = sum over kept pairs of n_a n_b */
+  int64_t ncols_tiled;   /* internal storage columns */
+  int64_t ntriplets;     /* evaluated (a, b, C) triplets */
+  int64_t nintegrals;    /* unique evaluated integrals: sum over triplets of n_a n_b n_C (a > b), n_a (n_a + 1)/2 n_C (a = b) */
+  double eri_seconds;    /* GPU time of the three-index ERI kernels */
+  double metric_seconds; /* metric + Cholesky + inverse */
+  double trsm_seconds;   /* B = L^-1 raw with FP32 split */
+  double kappa_lb;       /* lower bound (max L_ii / min L_ii)^2 of cond(J_PQ) */
+} dfx_B_info;
+
+/*
+ * dfx_eri3 -- raw integrals (mu nu|P) (section "Molecular integrals", Rys
+ * quadrature), metric J_PQ = (P|Q), J_PQ = L L^T (plain Cholesky), and the
+ * fitted tensor B_Q = sum_P (L^-1)_QP (mu nu|P) (Eq. (1c) with M' = L^-1),
+ * stored as two FP32 words per element (hi = fl32(B), lo = fl32(B - hi)).
+ *
+ *   shells/nsh, aux/nauxsh   orbital and auxiliary shells (host)
+ *   opts                     may be NULL (tau = 1e-12, flags = 0)
+ *   stream                   hipStream_t; the call synchronises it
+ *   out                      receives a new handle (free with dfx_B_free)
+ *
+ * Screening: Q_ab = sqrt(max_{mu in a, nu in b} (mu nu|mu nu)), Q_C =
+ * sqrt(max_{P in C} (P|P)); pair a >= b kept iff Q_ab max_C Q_C >= tau; its
+ * block with C evaluated iff Q_ab Q_C >= tau, else zero.
+ * Errors: DFX_EINVAL, DFX_EUNSUPPORTED, DFX_ENOTPOSDEF (no handle returned),
+ * DFX_ENOMEM, DFX_EHIP.
+ */
+int dfx_eri3(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
+             const dfx_eri3_opts* opts, void* stream, dfx_B** out);
+
+int dfx_B_info_get(const dfx_B* b, dfx_B_info* info);
+
+/*
+ * Integer lists of the screening (host buffers, the bit-exact contract):
+ *   pairs   [2 * npairs]  (a, b) of each kept pair, canonical order a = 0..,
+ *                         b = 0..a, a-major
+ *   col_off [npairs + 1]  prefix sums of n_a n_b (int64)
+ *   keep    [npairs * nauxsh] (may be NULL) 1 iff triplet (a, b, C) evaluated
+ *   Qab     [nsh * nsh] (may be NULL) Schwarz factors, symmetric
+ *   QC      [nauxsh]    (may be NULL)
+ */
+int dfx_B_lists(const dfx_B* b, int32_t* pairs, int64_t* col_off, uint8_t* keep, double* Qab,
+                double* QC);
+
+#define DFX_EXPORT_B 0     /* hi + lo (FP64 value) */
+#define DFX_EXPORT_BHI 1   /* hi word only */
+#define DFX_EXPORT_RAW 2   /* raw (mu nu|P), needs DFX_KEEP_RAW */
+/*
+ * Rows q0..q1-1 of B (or raw) in the canonical packed column order (pair
+ * blocks n_a x n_b row-major in kept-pair order) into dev_out
+ * [(q1 - q0) * ncols] FP64, device memory.
+ */
+int dfx_B_export(const dfx_B* b, int what, int q0, int q1, double* dev_out, void* stream);
+
+/* J_PQ (what = 0) or L (what = 1), naux x naux, into dev_out; needs DFX_KEEP_METRIC. */
+int dfx_B_metric(const dfx_B* b, int what, double* dev_out, void* stream);
+
+int dfx_B_free(dfx_B* b);
+
+/*
+ * dfx_jk -- Coulomb and exchange matrices from B (section "Density fitting
+ * utilities"): J = sum_Q B_Q gamma_Q with gamma_Q = sum B_Q D (Eqs. 3a, 3b);
+ * K = sum_Q X_Q X_Q^T with X_Q = B_Q C_occ (Eqs. 1a, 2a).
+ *   dev_in     kind = DFX_COCC: C_occ [nbf][nocc]; DFX_DENSITY: D [nbf][nbf]
+ *              (K for a density input needs DFX_COCC in this version)
+ *   precision  DFX_FP64 | DFX_FP32 | DFX_BF16
+ *   dev_J, dev_K  nbf x nbf outputs, either may be NULL
+ * Errors: DFX_EINVAL, DFX_ENOMEM, DFX_EHIP, DFX_EUNSUPPORTED.
+ */
+int dfx_jk(const dfx_B* b, const double* dev_in, int kind, int nocc, int precision, double* dev_J,
+           double* dev_K, void* stream);
+
+/*
+ * dfx_int1e -- overlap S, kinetic T and nuclear attraction
+ * V = -sum_A Z_A <mu| 1/|r - R_A| |nu> (device outputs, nbf x nbf).
+ */
+int dfx_int1e(const dfx_shell* shells, int nsh, const dfx_geom* geom, double* dev_S, double* dev_T,
+              double* dev_V, void* stream);
+
+/*
+ * dfx_metric -- the two-centre Coulomb metric J_PQ = (P|Q) of the auxiliary
+ * basis (naux x naux, device output), by the same Rys kernels as dfx_eri3.
+ */
+int dfx_metric(const dfx_shell* aux, int nauxsh, double* dev_J, void* stream);
+
+/*
+ * dfx_cholesky -- J = L L^T for a symmetric positive definite n x n matrix
+ * (device, row-major; only its lower triangle is read).  On return dev_A
+ * holds L (upper triangle zeroed) and dev_Linv holds L^-1.  Plain blocked
+ * Cholesky, no pivoting.  DFX_ENOTPOSDEF if a pivot falls below 1e-14 of its
+ * original diagonal element.  Synchronises the stream.
+ */
+int dfx_cholesky(double* dev_A, int n, double* dev_Linv, void* stream);
+
+/* ---- SCF ---------------------------------------------------------------------- */
+#define DFX_GUESS_CORE 0
+#define DFX_GUESS_CINIT 1     /* start from C_init */
+#define DFX_GUESS_DENSITY 2   /* start from D_init (projected to its top nocc natural orbitals) */
+
+#define DFX_SCHED_FP64 0      /* every iteration in FP64 */
+#define DFX_SCHED_MIXED 1     /* FP32/BF16 K until switch_err, then FP64 */
+
+typedef struct {
+  double tau;            /* Schwarz threshold (1e-12) */
+  double conv_dE;        /* |E_k - E_k-1| threshold (1e-10) */
+  double conv_err;       /* max |X^T (FDS - SDF) X| threshold (1e-7) */
+  double ortho_thresh;   /* drop eigenvalues of S below this (1e-8) */
+  double switch_err;     /* mixed schedule: go to FP64 when the DIIS error is below (1e-5) */
+  int32_t max_iter;      /* 100 */
+  int32_t diis_size;     /* 8 */
+  int32_t schedule;      /* DFX_SCHED_* */
+  int32_t mixed_prec;    /* DFX_FP32 or DFX_BF16 for the mixed phase */
+  int32_t guess;         /* DFX_GUESS_* */
+  int32_t verbose;
+} dfx_scf_opts;
+
+#define DFX_MAXHIST 256
+typedef struct {
+  int32_t niter;         /* Fock builds performed */
+  int32_t converged;
+  int32_t n_mixed;       /* iterations in the reduced-precision phase */
+  int32_t ndropped;      /* orthogonaliser eigenvalues dropped */
+  int32_t nbf, naux, nocc;
+  double E_nuc;
+  double err_max;        /* final DIIS error */
+  double t_setup;        /* seconds: integrals + fitting + one-electron + guess */
+  double t_scf;          /* seconds: the iterations */
+  double t_total;
+  double E_hist[DFX_MAXHIST];
+  double err_hist[DFX_MAXHIST];
+} dfx_scf_info;
+
+void dfx_scf_default_opts(dfx_scf_opts* o);
+
+/*
+ * dfx_scf -- DF-RHF: D = C_occ C_occ^T, F = h + 2J - K, E = tr D (h + F) + E_nn,
+ * Pulay DIIS on e = X^T (F D S - S D F) X, aufbau on the lowest nocc levels.
+ *   init    host [nbf][nbf] C (guess = CINIT) or D (guess = DENSITY), else NULL
+ *   E       host scalar out; C host [nbf][nbf] out (may be NULL); eps [nbf] (may be NULL)
+ * Synchronous.  DFX_ENOCONV: not converged within max_iter (E, C written).
+ */
+int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
+            const dfx_scf_opts* opts, const double* init, double* E, double* C, double* eps,
+            dfx_scf_info* info);
+
+const char* dfx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFX_H */

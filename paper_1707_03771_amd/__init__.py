@@ -1,0 +1,283 @@
+"""dfx: density-fitted restricted Hartree-Fock hot path for AMD MI355X (gfx950).
+
+Thin Python binding over the C-ABI of ``libdfx.so`` (include/dfx.h).  Every
+step of the computation runs in the library's HIP kernels; this module only
+marshals arguments.  PyTorch supplies device memory and the current stream.
+Importing fails loudly if the library has not been built
+(``python -m paper_1707_03771_amd.build``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdfx.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1707_03771_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+OK, EINVAL, ENOMEM, EHIP, ENOTPOSDEF, ENOCONV, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32, BF16 = 0, 1, 2
+DENSITY, COCC = 0, 1
+KEEP_RAW, KEEP_METRIC = 1, 2
+EXPORT_B, EXPORT_BHI, EXPORT_RAW = 0, 1, 2
+GUESS_CORE, GUESS_CINIT, GUESS_DENSITY = 0, 1, 2
+SCHED_FP64, SCHED_MIXED = 0, 1
+MAXHIST = 256
+
+
+class DfxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dfx error {code}: {msg}")
+        self.code = code
+
+
+class Shell(ctypes.Structure):
+    _fields_ = [("xyz", ctypes.c_double * 3), ("l", ctypes.c_int32), ("nprim", ctypes.c_int32),
+                ("exps", ctypes.c_void_p), ("coefs", ctypes.c_void_p)]
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("natom", ctypes.c_int32), ("xyz", ctypes.c_void_p), ("Z", ctypes.c_void_p),
+                ("charge", ctypes.c_int32)]
+
+
+class Eri3Opts(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("flags", ctypes.c_int32)]
+
+
+class BInfo(ctypes.Structure):
+    _fields_ = [("nbf", ctypes.c_int32), ("naux", ctypes.c_int32), ("nsh", ctypes.c_int32),
+                ("nauxsh", ctypes.c_int32), ("npairs", ctypes.c_int32), ("ncols", ctypes.c_int64),
+                ("ncols_tiled", ctypes.c_int64), ("ntriplets", ctypes.c_int64),
+                ("nintegrals", ctypes.c_int64), ("eri_seconds", ctypes.c_double),
+                ("metric_seconds", ctypes.c_double), ("trsm_seconds", ctypes.c_double),
+                ("kappa_lb", ctypes.c_double)]
+
+
+class ScfOpts(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("conv_dE", ctypes.c_double), ("conv_err", ctypes.c_double),
+                ("ortho_thresh", ctypes.c_double), ("switch_err", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("diis_size", ctypes.c_int32), ("schedule", ctypes.c_int32),
+                ("mixed_prec", ctypes.c_int32), ("guess", ctypes.c_int32), ("verbose", ctypes.c_int32)]
+
+
+class ScfInfo(ctypes.Structure):
+    _fields_ = [("niter", ctypes.c_int32), ("converged", ctypes.c_int32), ("n_mixed", ctypes.c_int32),
+                ("ndropped", ctypes.c_int32), ("nbf", ctypes.c_int32), ("naux", ctypes.c_int32),
+                ("nocc", ctypes.c_int32), ("E_nuc", ctypes.c_double), ("err_max", ctypes.c_double),
+                ("t_setup", ctypes.c_double), ("t_scf", ctypes.c_double), ("t_total", ctypes.c_double),
+                ("E_hist", ctypes.c_double * MAXHIST), ("err_hist", ctypes.c_double * MAXHIST)]
+
+
+_vp, _i, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
+_SIGS = {
+    "dfx_eri3": [_vp, _i, _vp, _i, _vp, _vp, _vp],
+    "dfx_B_info_get": [_vp, _vp],
+    "dfx_B_lists": [_vp, _vp, _vp, _vp, _vp, _vp],
+    "dfx_B_export": [_vp, _i, _i, _i, _vp, _vp],
+    "dfx_B_metric": [_vp, _i, _vp, _vp],
+    "dfx_B_free": [_vp],
+    "dfx_jk": [_vp, _vp, _i, _i, _i, _vp, _vp, _vp],
+    "dfx_int1e": [_vp, _i, _vp, _vp, _vp, _vp, _vp],
+    "dfx_scf": [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp],
+    "dfx_scf_default_opts": [_vp],
+    "dfx_metric": [_vp, _i, _vp, _vp],
+    "dfx_cholesky": [_vp, _i, _vp, _vp],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(_lib, _name, None)
+    if _f is not None:
+        _f.argtypes = _args
+        _f.restype = None if _name == "dfx_scf_default_opts" else ctypes.c_int
+_lib.dfx_last_error.restype = ctypes.c_char_p
+_lib.dfx_last_error.argtypes = []
+
+
+def last_error():
+    return _lib.dfx_last_error().decode()
+
+
+def _check(code):
+    if code != OK:
+        raise DfxError(code, last_error())
+    return code
+
+
+def _stream(stream=None):
+    if stream is not None:
+        return ctypes.c_void_p(int(stream))
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class _ShellArray:
+    """dfx_shell[] over shell dicts (center, l, exps, coefs); keeps the arrays alive."""
+
+    def __init__(self, shells):
+        self.keep = []
+        self.arr = (Shell * max(1, len(shells)))()
+        for i, s in enumerate(shells):
+            e = np.ascontiguousarray(s["exps"], dtype=np.float64)
+            c = np.ascontiguousarray(s["coefs"], dtype=np.float64)
+            self.keep += [e, c]
+            sh = self.arr[i]
+            for k in range(3):
+                sh.xyz[k] = float(s["center"][k])
+            sh.l, sh.nprim = int(s["l"]), len(e)
+            sh.exps, sh.coefs = e.ctypes.data, c.ctypes.data
+        self.n = len(shells)
+
+
+class _GeomC:
+    def __init__(self, xyz, Z, charge=0):
+        self.xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+        self.Z = np.ascontiguousarray(np.asarray(Z, dtype=np.int32))
+        self.g = Geom(len(self.Z), self.xyz.ctypes.data, self.Z.ctypes.data, int(charge))
+
+
+class DFTensor:
+    """Owns a dfx_B handle: the fitted three-index tensor resident in HBM."""
+
+    def __init__(self, handle):
+        self.h = handle
+        inf = BInfo()
+        _check(_lib.dfx_B_info_get(self.h, ctypes.byref(inf)))
+        self.info = {k: getattr(inf, k) for k, _ in BInfo._fields_}
+        self.nbf, self.naux = inf.nbf, inf.naux
+
+    def lists(self, keep=False):
+        """Integer screening lists and Schwarz factors (host copies)."""
+        inf = self.info
+        pairs = np.zeros((inf["npairs"], 2), np.int32)
+        off = np.zeros(inf["npairs"] + 1, np.int64)
+        kp = np.zeros((inf["npairs"], inf["nauxsh"]), np.uint8) if keep else None
+        Qab = np.zeros((inf["nsh"], inf["nsh"]))
+        QC = np.zeros(inf["nauxsh"])
+        _check(_lib.dfx_B_lists(self.h, pairs.ctypes.data, off.ctypes.data,
+                                kp.ctypes.data if keep else None, Qab.ctypes.data, QC.ctypes.data))
+        return pairs, off, kp, Qab, QC
+
+    def export(self, what=EXPORT_B, q0=0, q1=None, stream=None):
+        import torch
+        q1 = self.naux if q1 is None else q1
+        out = torch.empty((q1 - q0, self.info["ncols"]), dtype=torch.float64, device="cuda")
+        _check(_lib.dfx_B_export(self.h, what, q0, q1, _ptr(out), _stream(stream)))
+        return out
+
+    def metric(self, what=0, stream=None):
+        import torch
+        out = torch.empty((self.naux, self.naux), dtype=torch.float64, device="cuda")
+        _check(_lib.dfx_B_metric(self.h, what, _ptr(out), _stream(stream)))
+        return out
+
+    def free(self):
+        if self.h:
+            _check(_lib.dfx_B_free(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def eri3(shells, aux, tau=1e-12, flags=0, stream=None):
+    """dfx_eri3: Rys (mu nu|P), metric, Cholesky and B = L^-1 (mu nu|P) in HBM."""
+    s, a = _ShellArray(shells), _ShellArray(aux)
+    h = ctypes.c_void_p()
+    _check(_lib.dfx_eri3(s.arr, s.n, a.arr, a.n, ctypes.byref(Eri3Opts(tau, flags)), _stream(stream),
+                         ctypes.byref(h)))
+    return DFTensor(h)
+
+
+def jk(B, x, kind=COCC, nocc=None, precision=FP64, want_j=True, want_k=True, stream=None):
+    """dfx_jk: J (Eqs. 3a, 3b) and K (Eqs. 1a, 2a) as (nbf, nbf) float64 cuda tensors."""
+    import torch
+    x = x.contiguous()
+    if x.dtype != torch.float64 or not x.is_cuda:
+        raise ValueError("jk: input must be a float64 cuda tensor")
+    n = B.nbf
+    if nocc is None:
+        nocc = x.shape[1] if kind == COCC else 0
+    J = torch.empty((n, n), dtype=torch.float64, device=x.device) if want_j else None
+    K = torch.empty((n, n), dtype=torch.float64, device=x.device) if want_k else None
+    _check(_lib.dfx_jk(B.h, _ptr(x), kind, nocc, precision, _ptr(J) if want_j else None,
+                       _ptr(K) if want_k else None, _stream(stream)))
+    return J, K
+
+
+def int1e(shells, xyz, Z, stream=None):
+    """dfx_int1e: overlap, kinetic and nuclear-attraction matrices (cuda tensors)."""
+    import torch
+    s = _ShellArray(shells)
+    g = _GeomC(xyz, Z)
+    n = sum(2 * int(q["l"]) + 1 for q in shells)
+    S, T, V = (torch.empty((n, n), dtype=torch.float64, device="cuda") for _ in range(3))
+    _check(_lib.dfx_int1e(s.arr, s.n, ctypes.byref(g.g), _ptr(S), _ptr(T), _ptr(V), _stream(stream)))
+    return S, T, V
+
+
+def metric(aux, stream=None):
+    """dfx_metric: the Coulomb metric (P|Q) as an (naux, naux) cuda tensor."""
+    import torch
+    a = _ShellArray(aux)
+    n = sum(2 * int(q["l"]) + 1 for q in aux)
+    J = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    _check(_lib.dfx_metric(a.arr, a.n, _ptr(J), _stream(stream)))
+    return J
+
+
+def cholesky(A, stream=None):
+    """dfx_cholesky: returns (L, L^-1) of a symmetric positive definite cuda tensor."""
+    import torch
+    L = A.detach().clone().contiguous()
+    Linv = torch.empty_like(L)
+    _check(_lib.dfx_cholesky(_ptr(L), L.shape[0], _ptr(Linv), _stream(stream)))
+    return L, Linv
+
+
+def scf_default_opts():
+    o = ScfOpts()
+    _lib.dfx_scf_default_opts(ctypes.byref(o))
+    return o
+
+
+def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, **opts):
+    """dfx_scf: DF-RHF.  Returns (E, C, eps, info dict); C and eps are numpy arrays."""
+    o = scf_default_opts()
+    for k, v in opts.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown SCF option {k!r}")
+        setattr(o, k, v)
+    s, a = _ShellArray(shells), _ShellArray(aux)
+    g = _GeomC(xyz, Z, charge)
+    n = sum(2 * int(q["l"]) + 1 for q in shells)
+    E = ctypes.c_double()
+    C = np.zeros((n, n)) if want_c else None
+    eps = np.zeros(n)
+    inf = ScfInfo()
+    ini = None
+    if init is not None:
+        ini = np.ascontiguousarray(init, dtype=np.float64)
+        assert ini.shape == (n, n)
+    code = _lib.dfx_scf(ctypes.byref(g.g), s.arr, s.n, a.arr, a.n, ctypes.byref(o),
+                        ini.ctypes.data if ini is not None else None, ctypes.byref(E),
+                        C.ctypes.data if want_c else None, eps.ctypes.data, ctypes.byref(inf))
+    if code not in (OK, ENOCONV):
+        _check(code)
+    info = {k: getattr(inf, k) for k, _ in ScfInfo._fields_ if not k.endswith("_hist")}
+    info["E_hist"] = list(inf.E_hist)[: inf.niter]
+    info["err_hist"] = list(inf.err_hist)[: inf.niter]
+    info["status"] = code
+    return E.value, C, eps, info

@@ -1,0 +1,123 @@
+// Host-side runtime of the dfx library: shells, device buffers, screening lists.
+#pragma once
+#include <memory>
+#include <vector>
+
+#include "../../include/dfx.h"
+#include "kernels.h"
+
+namespace dfx {
+
+// ---- device memory ---------------------------------------------------------
+struct DevMem {
+  void* p = nullptr;
+  size_t n = 0;
+  DevMem() = default;
+  explicit DevMem(size_t bytes) { alloc(bytes); }
+  DevMem(const DevMem&) = delete;
+  DevMem& operator=(const DevMem&) = delete;
+  DevMem(DevMem&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevMem& operator=(DevMem&& o) noexcept {
+    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    return *this;
+  }
+  ~DevMem() { release(); }
+  void alloc(size_t bytes);
+  void release();
+  template <class T> T* as() const { return reinterpret_cast<T*>(p); }
+};
+
+template <class T>
+DevMem upload(const std::vector<T>& v, hipStream_t st) {
+  DevMem m(std::max<size_t>(v.size(), 1) * sizeof(T));
+  if (!v.empty()) DFX_HIP(hipMemcpyAsync(m.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st));
+  return m;
+}
+
+// ---- shells ------------------------------------------------------------------
+struct HostShells {
+  int nsh = 0, nbf = 0, lmax = 0;
+  std::vector<double> ctr;
+  std::vector<int> l, nprim, poff, foff;
+  std::vector<double> exps, coef;  // coef multiplies x^i y^j z^k exp(-a r^2)
+};
+HostShells make_shells(const dfx_shell* s, int n, int lmax_allowed, const char* what);
+
+struct DevShellSet {
+  DevMem ctr, l, nprim, poff, foff, exps, coef;
+  int nsh = 0;
+  void upload(const HostShells& h, hipStream_t st);
+  DevShells view() const {
+    return DevShells{ctr.as<double>(), l.as<int>(), nprim.as<int>(), poff.as<int>(), foff.as<int>(),
+                     exps.as<double>(), coef.as<double>(), nsh};
+  }
+};
+
+const double* rys_table_device();  // per current device, built on first use
+
+// ---- timing ---------------------------------------------------------------------
+struct GpuTimer {
+  hipEvent_t a{}, b{};
+  hipStream_t st;
+  explicit GpuTimer(hipStream_t s) : st(s) {
+    DFX_HIP(hipEventCreate(&a));
+    DFX_HIP(hipEventCreate(&b));
+  }
+  ~GpuTimer() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
+  void start() { DFX_HIP(hipEventRecord(a, st)); }
+  void stop() { DFX_HIP(hipEventRecord(b, st)); }
+  double seconds() {
+    DFX_HIP(hipEventSynchronize(b));
+    float ms = 0;
+    DFX_HIP(hipEventElapsedTime(&ms, a, b));
+    return ms * 1e-3;
+  }
+};
+
+}  // namespace dfx
+
+// ---- the fitted tensor handle -------------------------------------------------------
+struct dfx_B {
+  int device = 0;
+  dfx::HostShells bas, aux;
+  dfx::DevShellSet dbas, daux;
+  int nbf = 0, naux = 0;
+  int64_t ncols_t = 0, ncols_p = 0;
+  double tau = 1e-12;
+  std::vector<int> pa, pb;          // kept pairs (canonical)
+  std::vector<int64_t> col_off;     // [npairs + 1]
+  std::vector<double> Qab, QC;      // host copies
+  dfx::DevMem hi, lo, raw, J2, L;   // device tensors
+  dfx::DevMem work;                 // grow-only scratch for dfx_jk
+  dfx::DevMem toff;                 // packed column -> tile offset (built on demand)
+  dfx_B_info info{};
+  void* ensure_work(size_t bytes);
+};
+
+namespace dfx {
+// internal builders shared by the C-ABI entry points and the SCF driver
+std::unique_ptr<dfx_B> build_B(HostShells bas, HostShells aux, double tau, int flags, hipStream_t st);
+void int1e_build(const HostShells& h, const dfx_geom* geom, double* S, double* T, double* V,
+                 hipStream_t st);
+
+// run f, turning exceptions into a status code and a thread-local message
+template <class F>
+int guard(F&& f) {
+  try {
+    f();
+    return DFX_OK;
+  } catch (const Error& e) {
+    set_last_error(e.what());
+    return e.code;
+  } catch (const std::bad_alloc&) {
+    set_last_error("host allocation failed");
+    return DFX_ENOMEM;
+  } catch (const std::exception& e) {
+    set_last_error(e.what());
+    return DFX_EINVAL;
+  } catch (...) {
+    set_last_error("unknown error");
+    return DFX_EINVAL;
+  }
+}
+}  // namespace dfx

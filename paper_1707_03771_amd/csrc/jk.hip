@@ -1,0 +1,303 @@
+// Coulomb and exchange builds from the fitted tensor B (section "Density
+// fitting utilities"):
+//   J: gamma_Q = sum_{mu nu} B_Q,mu nu D_mu nu       (Eq. 3a)
+//      J_mu nu = sum_Q gamma_Q B_Q,mu nu             (Eq. 3b)
+//   K: X_Q = B_Q C                                   (Eq. 1a, half transform)
+//      K_mu nu = sum_Q sum_i X_Q,mu i X_Q,nu i       (Eq. 2a)
+// B is stored as two FP32 words (hi, lo) per element in the packed 32x32 tile
+// layout (common.h).  The FP64 path reads hi + lo; the mixed path reads hi.
+#include "kernels.h"
+
+namespace dfx {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// tile index -> (I, J), I >= J
+__device__ __forceinline__ void tile_ij(int t, int& I, int& J) {
+  int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  while (i * (i + 1) / 2 > t) --i;
+  I = i;
+  J = t - i * (i + 1) / 2;
+}
+
+// weighted density in the tile layout: off-diagonal tiles count twice
+__global__ void pack_density_kernel(const double* __restrict__ D, int nbf, double* __restrict__ d) {
+  const int t = blockIdx.x;
+  int I, J;
+  tile_ij(t, I, J);
+  const double w = (I == J) ? 1.0 : 2.0;
+  for (int e = threadIdx.x; e < TILE2; e += blockDim.x) {
+    const int r = I * TILE + (e >> 5), c = J * TILE + (e & 31);
+    d[(int64_t)t * TILE2 + e] = (r < nbf && c < nbf) ? w * D[(int64_t)r * nbf + c] : 0.0;
+  }
+}
+
+// gamma_Q = sum_c B[Q][c] d[c], FP64 accumulation, one workgroup per Q
+template <bool LO>
+__global__ void __launch_bounds__(256) j_gamma_kernel(const float* __restrict__ hi,
+                                                      const float* __restrict__ lo, int64_t ncols,
+                                                      const double* __restrict__ d, double* gam) {
+  const int Q = blockIdx.x;
+  const float4* h4 = reinterpret_cast<const float4*>(hi + (int64_t)Q * ncols);
+  const float4* l4 = reinterpret_cast<const float4*>((LO ? lo : hi) + (int64_t)Q * ncols);
+  const double4* d4 = reinterpret_cast<const double4*>(d);
+  const int64_t n4 = ncols >> 2;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n4; i += blockDim.x) {
+    const float4 h = h4[i];
+    const double4 dd = d4[i];
+    if (LO) {
+      const float4 l = l4[i];
+      s += ((double)h.x + (double)l.x) * dd.x + ((double)h.y + (double)l.y) * dd.y +
+           ((double)h.z + (double)l.z) * dd.z + ((double)h.w + (double)l.w) * dd.w;
+    } else {
+      s += (double)h.x * dd.x + (double)h.y * dd.y + (double)h.z * dd.z + (double)h.w * dd.w;
+    }
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gam[Q] = red[0];
+}
+
+// Jvec[c] = sum_Q B[Q][c] gamma_Q, four columns per thread, fixed Q order
+template <bool LO>
+__global__ void __launch_bounds__(256) j_back_kernel(const float* __restrict__ hi,
+                                                     const float* __restrict__ lo, int64_t ncols,
+                                                     int naux, const double* __restrict__ gam,
+                                                     double* __restrict__ jv) {
+  const int64_t c4 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c4 >= (ncols >> 2)) return;
+  double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
+  const float4* h4 = reinterpret_cast<const float4*>(hi) + c4;
+  const float4* l4 = reinterpret_cast<const float4*>(LO ? lo : hi) + c4;
+  const int64_t stride = ncols >> 2;
+  for (int Q = 0; Q < naux; ++Q) {
+    const double g = gam[Q];
+    const float4 h = h4[Q * stride];
+    if (LO) {
+      const float4 l = l4[Q * stride];
+      a0 = fma((double)h.x + (double)l.x, g, a0);
+      a1 = fma((double)h.y + (double)l.y, g, a1);
+      a2 = fma((double)h.z + (double)l.z, g, a2);
+      a3 = fma((double)h.w + (double)l.w, g, a3);
+    } else {
+      a0 = fma((double)h.x, g, a0);
+      a1 = fma((double)h.y, g, a1);
+      a2 = fma((double)h.z, g, a2);
+      a3 = fma((double)h.w, g, a3);
+    }
+  }
+  reinterpret_cast<double4*>(jv)[c4] = double4{a0, a1, a2, a3};
+}
+
+// tile layout -> dense symmetric matrix
+__global__ void unpack_sym_kernel(const double* __restrict__ v, int nbf, double* __restrict__ M) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nbf * nbf) return;
+  int r = (int)(idx / nbf), c = (int)(idx % nbf);
+  if (r < c) {
+    const int t = r;
+    r = c;
+    c = t;
+  }
+  M[idx] = v[tile_base(r >> 5, c >> 5) + ((r & 31) << 5) + (c & 31)];
+}
+
+void j_build(const JKArgs& a, const double* D, double* J, double* work, hipStream_t st) {
+  const int nt = ntiles_for(a.nbf);
+  double* dvec = work;                       // ncols
+  double* gam = work + a.ncols;              // naux
+  double* jv = gam + ((a.naux + 3) & ~3);    // ncols
+  hipLaunchKernelGGL(pack_density_kernel, dim3(nt * (nt + 1) / 2), dim3(256), 0, st, D, a.nbf, dvec);
+  const bool lo = (a.prec == PREC_FP64);
+  if (lo)
+    hipLaunchKernelGGL(j_gamma_kernel<true>, dim3(a.naux), dim3(256), 0, st, a.hi, a.lo, a.ncols, dvec, gam);
+  else
+    hipLaunchKernelGGL(j_gamma_kernel<false>, dim3(a.naux), dim3(256), 0, st, a.hi, a.lo, a.ncols, dvec, gam);
+  const unsigned gb = (unsigned)(((a.ncols >> 2) + 255) / 256);
+  if (lo)
+    hipLaunchKernelGGL(j_back_kernel<true>, dim3(gb), dim3(256), 0, st, a.hi, a.lo, a.ncols, a.naux, gam, jv);
+  else
+    hipLaunchKernelGGL(j_back_kernel<false>, dim3(gb), dim3(256), 0, st, a.hi, a.lo, a.ncols, a.naux, gam, jv);
+  const int64_t n2 = (int64_t)a.nbf * a.nbf;
+  hipLaunchKernelGGL(unpack_sym_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, jv, a.nbf, J);
+}
+
+// ---------------------------------------------------------------------------
+// K, FP64: X_Q[mu][i] = sum_nu B_Q[mu][nu] C[nu][i] on v_mfma_f64_16x16x4, with
+// B_Q read from the packed tiles (each tile serves (mu, nu) and, transposed,
+// (nu, mu)).  X is stored as Xm[mu][(Q - q0) nocc + i].
+constexpr int KM = 128, KN = 64, KK = 16, KT = 256;
+
+__device__ __forceinline__ double b_elem(const float* hi, const float* lo, int64_t rowoff, int mu,
+                                         int nu) {
+  int r = mu, c = nu;
+  if (r < c) {
+    r = nu;
+    c = mu;
+  }
+  const int64_t o = rowoff + tile_base(r >> 5, c >> 5) + ((r & 31) << 5) + (c & 31);
+  return (double)hi[o] + (double)lo[o];
+}
+
+__global__ void __launch_bounds__(KT) kx_f64_kernel(const float* __restrict__ hi,
+                                                    const float* __restrict__ lo, int64_t ncols,
+                                                    int nbf, int q0, const double* __restrict__ C,
+                                                    int nocc, double* __restrict__ X, int64_t ldx) {
+  __shared__ double As[KK][KM + 2];
+  __shared__ double Bs[KK][KN + 2];
+  const int Q = q0 + blockIdx.z;
+  const int m0 = blockIdx.x * KM, n0 = blockIdx.y * KN;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = w * 32;  // each wave: 32 rows x 64 columns = 2 x 4 MFMA blocks
+  const int li = lane & 15, lk = lane >> 4;
+  const int64_t rowoff = (int64_t)Q * ncols;
+  v4d acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0, 0, 0, 0};
+  for (int k0 = 0; k0 < nbf; k0 += KK) {
+    double ra[8], rb[4];
+    {
+      const int i = tid >> 1, kb = (tid & 1) * 8, mu = m0 + i;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int nu = k0 + kb + j;
+        ra[j] = (mu < nbf && nu < nbf) ? b_elem(hi, lo, rowoff, mu, nu) : 0.0;
+      }
+    }
+    {
+      const int k = tid >> 4, nb = (tid & 15) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int nu = k0 + k, i = n0 + nb + j;
+        rb[j] = (nu < nbf && i < nocc) ? C[(int64_t)nu * nocc + i] : 0.0;
+      }
+    }
+    __syncthreads();
+    {
+      const int i = tid >> 1, kb = (tid & 1) * 8;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) As[kb + j][i] = ra[j];
+      const int k = tid >> 4, nb = (tid & 15) * 4;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) Bs[k][nb + j] = rb[j];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KK; kk += 4) {
+      double fa[2], fb[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) fa[i] = As[kk + lk][wm + i * 16 + li];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fb[j] = Bs[kk + lk][j * 16 + li];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int mu = m0 + wm + i * 16 + r * 4 + lk;  // f64 MFMA output layout
+        const int col = n0 + j * 16 + li;
+        if (mu < nbf && col < nocc) X[(int64_t)mu * ldx + (int64_t)blockIdx.z * nocc + col] = acc[i][j][r];
+      }
+}
+
+// K_lower = sum_s P_s  (partial SYRKs of the Q slices), then mirrored
+__global__ void k_reduce_kernel(const double* __restrict__ P, int ns, int nbf, double* __restrict__ K,
+                                int accumulate) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n2 = (int64_t)nbf * nbf;
+  if (idx >= n2) return;
+  const int r = (int)(idx / nbf), c = (int)(idx % nbf);
+  if (c > r) return;
+  double s = accumulate ? K[idx] : 0.0;
+  for (int k = 0; k < ns; ++k) s += P[k * n2 + idx];
+  K[idx] = s;
+}
+
+struct KPlan {
+  int qc;      // Q per chunk
+  int ns;      // slices per chunk
+  int qs;      // Q per slice
+  size_t x_elems, p_elems;
+};
+static KPlan k_plan(const JKArgs& a, int nocc) {
+  KPlan p{};
+  const size_t per_q = (size_t)a.nbf * (size_t)nocc;
+  size_t cap = ((size_t)2 << 30) / (per_q * sizeof(double));  // ~2 GiB of X per chunk
+  if (cap < 1) cap = 1;
+  p.qc = (int)std::min<size_t>(cap, (size_t)a.naux);
+  p.ns = std::min(8, p.qc);
+  p.qs = (p.qc + p.ns - 1) / p.ns;
+  p.x_elems = (size_t)a.nbf * (size_t)p.ns * p.qs * nocc;
+  p.p_elems = (size_t)p.ns * a.nbf * a.nbf;
+  return p;
+}
+
+size_t k_work_bytes(const JKArgs& a, int nocc) {
+  const KPlan p = k_plan(a, nocc);
+  return (p.x_elems + p.p_elems) * sizeof(double) + 256;
+}
+
+void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st) {
+  if (a.prec != PREC_FP64) throw Error(-6, "k_build: precision not available yet");
+  const KPlan p = k_plan(a, nocc);
+  double* X = reinterpret_cast<double*>(work);
+  double* P = X + p.x_elems;
+  const int64_t ldx = (int64_t)p.ns * p.qs * nocc;
+  const int64_t n2 = (int64_t)a.nbf * a.nbf;
+  for (int q0 = 0; q0 < a.naux; q0 += p.qc) {
+    const int nq = std::min(p.qc, a.naux - q0);
+    if (nq < p.ns * p.qs) fill_f64(X, p.x_elems, 0.0, st);
+    const dim3 g1((a.nbf + KM - 1) / KM, (nocc + KN - 1) / KN, nq);
+    hipLaunchKernelGGL(kx_f64_kernel, g1, dim3(KT), 0, st, a.hi, a.lo, a.ncols, a.nbf, q0, C, nocc, X, ldx);
+    GemmF64 g{};
+    g.M = a.nbf; g.N = a.nbf; g.K = p.qs * nocc;
+    g.A = X; g.lda = ldx; g.sA = (int64_t)p.qs * nocc;
+    g.B = X; g.ldb = ldx; g.sB = (int64_t)p.qs * nocc; g.tb = true;
+    g.C = P; g.ldc = a.nbf; g.sC = n2;
+    g.alpha = 1.0; g.beta = 0.0; g.batch = p.ns; g.lowerC = true;
+    dgemm(g, st);
+    hipLaunchKernelGGL(k_reduce_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, P, p.ns,
+                       a.nbf, K, q0 > 0 ? 1 : 0);
+  }
+  sym_from_lower(K, a.nbf, st);
+}
+
+// ---------------------------------------------------------------------------
+// canonical packed export: out[q - q0][c] = B[q][tileoff[c]]  (hi + lo, or raw)
+__global__ void export_kernel(const float* __restrict__ hi, const float* __restrict__ lo,
+                              const double* __restrict__ raw, int64_t ncols_t,
+                              const int64_t* __restrict__ toff, int64_t ncols_p, int q0,
+                              double* __restrict__ out) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols_p) return;
+  const int q = q0 + blockIdx.y;
+  const int64_t o = (int64_t)q * ncols_t + toff[c];
+  out[(int64_t)blockIdx.y * ncols_p + c] = raw ? raw[o] : (double)hi[o] + (lo ? (double)lo[o] : 0.0);
+}
+
+void export_rows(const float* hi, const float* lo, const double* raw, int64_t ncols_t, int q0, int q1,
+                 const int64_t* toff, int64_t ncols_p, double* out, hipStream_t st) {
+  if (q1 <= q0 || ncols_p <= 0) return;
+  const dim3 g((unsigned)((ncols_p + 255) / 256), q1 - q0);
+  hipLaunchKernelGGL(export_kernel, g, dim3(256), 0, st, hi, lo, raw, ncols_t, toff, ncols_p, q0, out);
+}
+
+}  // namespace dfx

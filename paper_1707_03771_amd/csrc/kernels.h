@@ -1,0 +1,102 @@
+// Internal launch interface of the dfx kernels (not part of the C-ABI).
+#pragma once
+#include "common.h"
+
+namespace dfx {
+
+enum { STORE_TILED = 0, STORE_DENSE = 1 };
+
+struct Eri3Args {
+  DevShells F, S, K;         // shells of the first and second bra index and of the ket
+  const int* pf;             // [npairs] first bra shell (angular momentum LA)
+  const int* ps;             // [npairs] second bra shell (LB); unused with UNITB
+  const unsigned char* rowfirst;  // [npairs] 1: first shell indexes rows of B
+  const double* pq;          // [npairs] Schwarz factor of the pair, or null
+  int npairs;
+  const int* kl;             // [nk] ket shells of angular momentum LC
+  const double* kq;          // [nk] their Schwarz factors
+  int nk;
+  int kchunk;                // ket shells per workgroup
+  double tau;                // screening threshold: evaluate iff Q_ab Q_C >= tau
+  double* out;
+  int64_t ld;                // row stride of out (elements)
+  const double* rys;         // device Rys table
+};
+
+struct SchwarzArgs {
+  DevShells sh;
+  const int* pf;   // [npairs] shell with the larger l
+  const int* ps;   // [npairs] shell with the smaller l
+  int npairs;
+  double* q;       // [npairs] out: sqrt(max (mu nu|mu nu))
+  const double* rys;
+};
+
+struct OneEArgs {
+  DevShells sh;
+  const int* pf;
+  const int* ps;
+  int npairs;
+  int n;           // nbf (row stride of S, T, V)
+  double *S, *T, *V;
+  const double* xyz;  // [natom][3]
+  const double* Z;    // [natom]
+  int natom;
+  const double* rys;
+};
+
+void eri3_dispatch(int LA, int LB, int LC, bool unitb, int mode, Eri3Args a, hipStream_t st);
+void metric_dispatch(int LA, int LC, Eri3Args a, hipStream_t st);
+void schwarz_dispatch(int LA, int LB, SchwarzArgs a, hipStream_t st);
+void onee_dispatch(int LA, int LB, OneEArgs a, hipStream_t st);
+void aux_schwarz(const double* J, int64_t ld, DevShells aux, double* q, hipStream_t st);
+
+// ---- dense FP64 linear algebra (linalg.hip) --------------------------------
+// C = alpha op(A) op(B) + beta C, row-major, strided batch over blockIdx.z.
+struct GemmF64 {
+  int M, N, K;
+  const double* A; int64_t lda; int64_t sA;
+  const double* B; int64_t ldb; int64_t sB;
+  double* C; int64_t ldc; int64_t sC;
+  double alpha, beta;
+  int batch;
+  bool ta, tb;     // op(A) = A^T, op(B) = B^T
+  bool lowerA;     // A is lower triangular (skip zero k-blocks)
+  bool lowerC;     // only the lower triangle of C is needed (skip blocks above)
+};
+void dgemm(const GemmF64& g, hipStream_t st);
+
+// B-transform: out = L^-1 * raw with lower-triangular Linv [n x n], raw [n x ncols],
+// written as hi = fl32(out), lo = fl32(out - hi).
+void trsm_split(const double* Linv, int n, const double* raw, int64_t ncols, float* hi, float* lo,
+                hipStream_t st);
+
+// Blocked Cholesky J = L L^T in place (lower), then Linv = L^-1.  Returns via
+// *info (device int) the first non-positive pivot + 1, or 0; a pivot below
+// 1e-14 of its original diagonal element counts as non-positive.
+// work: n * 65 doubles.
+void cholesky_inverse(double* J, int n, double* Linv, double* work, int* info, hipStream_t st);
+
+// ---- J / K (jk.hip) ----------------------------------------------------------
+enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2 };
+struct JKArgs {
+  const float* hi;
+  const float* lo;
+  int naux, nbf;
+  int64_t ncols;   // tiled columns
+  int prec;
+};
+void j_build(const JKArgs& a, const double* D, double* J, double* work, hipStream_t st);
+// K from the occupied block C [nbf][nocc] (row-major); work >= k_work_bytes
+size_t k_work_bytes(const JKArgs& a, int nocc);
+void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st);
+// canonical packed rows [q1 - q0][ncols_p] (FP64) from the tiled storage;
+// toff[c] is the tile offset of packed column c
+void export_rows(const float* hi, const float* lo, const double* raw, int64_t ncols_t, int q0, int q1,
+                 const int64_t* toff, int64_t ncols_p, double* out, hipStream_t st);
+
+// ---- small dense helpers (linalg.hip) ----------------------------------------
+void fill_f64(double* p, size_t n, double v, hipStream_t st);
+void sym_from_lower(double* A, int n, hipStream_t st);
+
+}  // namespace dfx

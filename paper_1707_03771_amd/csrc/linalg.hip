@@ -1,0 +1,337 @@
+// Dense FP64 linear algebra on gfx950 MFMA: a tiled DGEMM (v_mfma_f64_16x16x4),
+// the blocked Cholesky factorisation of the fitting metric J_PQ = L L^T, the
+// inverse L^-1, and the transform B = L^-1 (mu nu|P) of Eq. (1c) with
+// M' = L^-1, whose epilogue splits B into two FP32 words.
+#include "kernels.h"
+
+namespace dfx {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+constexpr int GM = 128, GN = 128, GK = 16, GT = 256;
+constexpr int LDS_PAD = 2;
+enum { EPI_F64 = 0, EPI_SPLIT = 1 };
+
+// Workgroup -> tile map.  Workgroups are dealt round-robin to the 8 XCDs; give
+// each XCD a contiguous range of tiles (M-block fastest) so that the tiles that
+// share a B panel also share an L2.
+__device__ __forceinline__ int xcd_tile(int bid, int tiles) {
+  const int q = tiles >> 3, r = tiles & 7;
+  const int x = bid & 7, slot = bid >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
+}
+
+template <bool TA, bool TB, int EPI>
+__global__ void __launch_bounds__(GT) dgemm_kernel(GemmF64 g, float* __restrict__ hi,
+                                                   float* __restrict__ lo) {
+  __shared__ double As[GK][GM + LDS_PAD];
+  __shared__ double Bs[GK][GN + LDS_PAD];
+  const int MB = (g.M + GM - 1) / GM, NB = (g.N + GN - 1) / GN;
+  const int t = xcd_tile(blockIdx.x, MB * NB);
+  const int m0 = (t % MB) * GM, n0 = (t / MB) * GN;
+  if (g.lowerC && n0 > m0 + GM - 1) return;
+  const int z = blockIdx.z;
+  const double* __restrict__ A = g.A + z * g.sA;
+  const double* __restrict__ B = g.B + z * g.sB;
+  double* __restrict__ C = g.C + z * g.sC;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+  const int li = lane & 15, lk = lane >> 4;
+
+  v4d acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0.0, 0.0, 0.0, 0.0};
+
+  int kmax = g.K;
+  if (g.lowerA && m0 + GM < kmax) kmax = m0 + GM;
+
+  for (int k0 = 0; k0 < kmax; k0 += GK) {
+    double ra[8], rb[8];
+    // ---- global -> registers
+    if (!TA) {
+      const int i = tid >> 1, kb = (tid & 1) * 8;
+      const int m = m0 + i;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + kb + j;
+        ra[j] = (m < g.M && k < kmax) ? A[(int64_t)m * g.lda + k] : 0.0;
+      }
+    } else {
+      const int k = k0 + (tid >> 4), mb = (tid & 15) * 8;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int m = m0 + mb + j;
+        ra[j] = (m < g.M && k < kmax) ? A[(int64_t)k * g.lda + m] : 0.0;
+      }
+    }
+    if (!TB) {
+      const int k = k0 + (tid >> 4), nb = (tid & 15) * 8;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int n = n0 + nb + j;
+        rb[j] = (n < g.N && k < kmax) ? B[(int64_t)k * g.ldb + n] : 0.0;
+      }
+    } else {
+      const int n = n0 + (tid >> 1), kb = (tid & 1) * 8;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const int k = k0 + kb + j;
+        rb[j] = (n < g.N && k < kmax) ? B[(int64_t)n * g.ldb + k] : 0.0;
+      }
+    }
+    __syncthreads();
+    // ---- registers -> LDS (k-major)
+    if (!TA) {
+      const int i = tid >> 1, kb = (tid & 1) * 8;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) As[kb + j][i] = ra[j];
+    } else {
+      const int k = tid >> 4, mb = (tid & 15) * 8;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) As[k][mb + j] = ra[j];
+    }
+    if (!TB) {
+      const int k = tid >> 4, nb = (tid & 15) * 8;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) Bs[k][nb + j] = rb[j];
+    } else {
+      const int n = tid >> 1, kb = (tid & 1) * 8;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) Bs[kb + j][n] = rb[j];
+    }
+    __syncthreads();
+    // ---- MFMA
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 4) {
+      double fa[4], fb[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) fa[i] = As[kk + lk][wm + i * 16 + li];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) fb[j] = Bs[kk + lk][wn + j * 16 + li];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
+    }
+  }
+
+  // ---- epilogue.  v_mfma_f64_16x16x4 leaves element (row, col) of its 16x16
+  // block in lane col + 16 (row % 4), register row / 4, so
+  // acc[i][j][r] is C[wm + 16 i + 4 r + lk][wn + 16 j + li]
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + i * 16 + r * 4 + lk;
+        const int n = n0 + wn + j * 16 + li;
+        if (m < g.M && n < g.N) {
+          const int64_t o = (int64_t)m * g.ldc + n;
+          if (EPI == EPI_F64) {
+            double v = g.alpha * acc[i][j][r];
+            if (g.beta != 0.0) v = fma(g.beta, C[o], v);
+            C[o] = v;
+          } else {
+            const double v = acc[i][j][r];
+            const float h = (float)v;
+            hi[o] = h;
+            lo[o] = (float)(v - (double)h);
+          }
+        }
+      }
+}
+
+static int gemm_tiles(int M, int N) { return ((M + GM - 1) / GM) * ((N + GN - 1) / GN); }
+
+void dgemm(const GemmF64& g, hipStream_t st) {
+  if (g.M <= 0 || g.N <= 0) return;
+  const dim3 grid(gemm_tiles(g.M, g.N), 1, g.batch > 0 ? g.batch : 1);
+  GemmF64 a = g;
+  if (g.K <= 0) {  // C = beta C
+    a.K = 0;
+  }
+#define L(TA_, TB_) \
+  hipLaunchKernelGGL((dgemm_kernel<TA_, TB_, EPI_F64>), grid, dim3(GT), 0, st, a, nullptr, nullptr)
+  if (!g.ta && !g.tb) L(false, false);
+  else if (!g.ta && g.tb) L(false, true);
+  else if (g.ta && !g.tb) L(true, false);
+  else L(true, true);
+#undef L
+}
+
+void trsm_split(const double* Linv, int n, const double* raw, int64_t ncols, float* hi, float* lo,
+                hipStream_t st) {
+  // columns in slabs so that the grid stays within one launch's int range
+  const int64_t slab = (int64_t)GN * 65536;
+  for (int64_t c0 = 0; c0 < ncols; c0 += slab) {
+    const int nc = (int)std::min<int64_t>(slab, ncols - c0);
+    GemmF64 g{};
+    g.M = n; g.N = nc; g.K = n;
+    g.A = Linv; g.lda = n;
+    g.B = raw + c0; g.ldb = ncols;
+    g.C = nullptr; g.ldc = ncols;
+    g.alpha = 1.0; g.beta = 0.0; g.batch = 1;
+    g.lowerA = true;
+    const dim3 grid(gemm_tiles(g.M, g.N));
+    hipLaunchKernelGGL((dgemm_kernel<false, false, EPI_SPLIT>), grid, dim3(GT), 0, st, g, hi + c0, lo + c0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Cholesky of one diagonal block (nb <= 64) in LDS, plus its lower-triangular
+// inverse.  A non-positive pivot records its global index + 1 in *info.
+constexpr int CB = 64;
+__global__ void __launch_bounds__(64) potrf_diag_kernel(double* J, int n, int k0, int kb,
+                                                        double* Linv, int* info,
+                                                        const double* __restrict__ diag0) {
+  __shared__ double a[CB][CB + 1];
+  __shared__ double x[CB][CB + 1];
+  const int t = threadIdx.x;
+  for (int i = 0; i < kb; ++i)
+    if (t < kb) a[i][t] = (t <= i) ? J[(int64_t)(k0 + i) * n + k0 + t] : 0.0;
+  __syncthreads();
+  for (int j = 0; j < kb; ++j) {
+    if (t == 0) {
+      // a pivot that lost all but rounding noise of the original diagonal
+      // counts as non-positive: the metric is not numerically positive definite
+      const double d = a[j][j];
+      if (!(d > 1e-14 * diag0[k0 + j])) {
+        if (*info == 0) *info = k0 + j + 1;
+        a[j][j] = __builtin_nan("");
+      } else {
+        a[j][j] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    if (t > j && t < kb) a[t][j] /= a[j][j];
+    __syncthreads();
+    if (t > j && t < kb)
+      for (int c = j + 1; c <= t; ++c) a[t][c] -= a[t][j] * a[c][j];
+    __syncthreads();
+  }
+  // inverse, one column per thread: X[c][c] = 1/L[c][c],
+  // X[i][c] = -(sum_{k=c}^{i-1} L[i][k] X[k][c]) / L[i][i]
+  if (t < kb) {
+    const int c = t;
+    for (int i = 0; i < kb; ++i) x[i][c] = 0.0;
+    x[c][c] = 1.0 / a[c][c];
+    for (int i = c + 1; i < kb; ++i) {
+      double s = 0.0;
+      for (int k = c; k < i; ++k) s += a[i][k] * x[k][c];
+      x[i][c] = -s / a[i][i];
+    }
+  }
+  __syncthreads();
+  for (int i = 0; i < kb; ++i)
+    if (t < kb) {
+      J[(int64_t)(k0 + i) * n + k0 + t] = (t <= i) ? a[i][t] : 0.0;
+      Linv[(int64_t)(k0 + i) * n + k0 + t] = x[i][t];
+    }
+}
+
+__global__ void copy2d_kernel(const double* src, int64_t lds, double* dst, int64_t ldd, int rows,
+                              int cols) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)rows * cols) return;
+  const int r = (int)(idx / cols), c = (int)(idx % cols);
+  dst[r * ldd + c] = src[r * lds + c];
+}
+static void copy2d(const double* src, int64_t lds, double* dst, int64_t ldd, int rows, int cols,
+                   hipStream_t st) {
+  const int64_t n = (int64_t)rows * cols;
+  if (n <= 0) return;
+  hipLaunchKernelGGL(copy2d_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src, lds, dst,
+                     ldd, rows, cols);
+}
+
+__global__ void fill_kernel(double* p, size_t n, double v) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+void fill_f64(double* p, size_t n, double v, hipStream_t st) {
+  if (!n) return;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, p, n, v);
+}
+
+__global__ void sym_lower_kernel(double* A, int n) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  const int r = (int)(idx / n), c = (int)(idx % n);
+  if (c > r) A[idx] = A[(int64_t)c * n + r];
+}
+void sym_from_lower(double* A, int n, hipStream_t st) {
+  const int64_t t = (int64_t)n * n;
+  hipLaunchKernelGGL(sym_lower_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, A, n);
+}
+
+__global__ void zero_upper_kernel(double* A, int n) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)n * n) return;
+  if ((int)(idx % n) > (int)(idx / n)) A[idx] = 0.0;
+}
+
+__global__ void diag_kernel(const double* A, int n, double* d) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) d[i] = A[(int64_t)i * n + i];
+}
+
+// J (n x n, lower part used) -> L in place (upper zeroed), Linv = L^-1.
+// work: at least n * (CB + 1) doubles.
+void cholesky_inverse(double* J, int n, double* Linv, double* work, int* info, hipStream_t st) {
+  fill_f64(Linv, (size_t)n * n, 0.0, st);
+  DFX_HIP(hipMemsetAsync(info, 0, sizeof(int), st));
+  double* diag0 = work + (size_t)n * CB;
+  hipLaunchKernelGGL(diag_kernel, dim3((n + 255) / 256), dim3(256), 0, st, J, n, diag0);
+  for (int k0 = 0; k0 < n; k0 += CB) {
+    const int kb = std::min(CB, n - k0);
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(64), 0, st, J, n, k0, kb, Linv, info, diag0);
+    const int r0 = k0 + kb, rows = n - r0;
+    if (rows <= 0) break;
+    // panel: L21 = A21 inv(L11)^T
+    GemmF64 g{};
+    g.M = rows; g.N = kb; g.K = kb;
+    g.A = J + (int64_t)r0 * n + k0; g.lda = n;
+    g.B = Linv + (int64_t)k0 * n + k0; g.ldb = n; g.tb = true;
+    g.C = work; g.ldc = kb;
+    g.alpha = 1.0; g.beta = 0.0; g.batch = 1;
+    dgemm(g, st);
+    copy2d(work, kb, J + (int64_t)r0 * n + k0, n, rows, kb, st);
+    // trailing update of the lower triangle: A22 -= L21 L21^T
+    GemmF64 u{};
+    u.M = rows; u.N = rows; u.K = kb;
+    u.A = work; u.lda = kb;
+    u.B = work; u.ldb = kb; u.tb = true;
+    u.C = J + (int64_t)r0 * n + r0; u.ldc = n;
+    u.alpha = -1.0; u.beta = 1.0; u.batch = 1; u.lowerC = true;
+    dgemm(u, st);
+  }
+  {
+    const int64_t t = (int64_t)n * n;
+    hipLaunchKernelGGL(zero_upper_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, J, n);
+  }
+  // off-diagonal blocks of L^-1, block row by block row:
+  // X_i,0:i = -inv(L_ii) (L_i,0:i X_0:i,0:i)
+  for (int i0 = CB; i0 < n; i0 += CB) {
+    const int ib = std::min(CB, n - i0);
+    GemmF64 g{};
+    g.M = ib; g.N = i0; g.K = i0;
+    g.A = J + (int64_t)i0 * n; g.lda = n;
+    g.B = Linv; g.ldb = n;
+    g.C = work; g.ldc = i0;
+    g.alpha = 1.0; g.beta = 0.0; g.batch = 1;
+    dgemm(g, st);
+    GemmF64 h{};
+    h.M = ib; h.N = i0; h.K = ib;
+    h.A = Linv + (int64_t)i0 * n + i0; h.lda = n;
+    h.B = work; h.ldb = i0;
+    h.C = Linv + (int64_t)i0 * n; h.ldc = n;
+    h.alpha = -1.0; h.beta = 0.0; h.batch = 1;
+    dgemm(h, st);
+  }
+}
+
+}  // namespace dfx

@@ -1,0 +1,466 @@
+// Restricted Hartree-Fock with density-fitted J and K (section "Standard
+// algorithms": the Fock builder is built on the density-fitting operations).
+//
+//   D = C_occ C_occ^T,  F = h + 2 J[D] - K[D],  E = tr D (h + F) + E_nn,
+//   DIIS (Pulay) on e = X^T (F D S - S D F) X, X the canonical orthogonaliser,
+//   aufbau on the lowest nocc eigenvalues of X^T F X.
+//
+// Everything lives on the GPU; per iteration only E, max|e| and the DIIS
+// overlaps (a few doubles) travel to the host, where the (m+1)x(m+1) DIIS
+// system is solved.  The eigensolver is rocSOLVER's dsyevd.
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+
+#include "host.h"
+
+namespace dfx {
+
+// ---- element-wise and reduction kernels ----------------------------------------
+__global__ void fock_kernel(const double* h, const double* J, const double* K, double* F, int64_t n2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n2) F[i] = h[i] + 2.0 * J[i] - K[i];
+}
+
+__global__ void add_kernel(const double* a, const double* b, double* c, int64_t n2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n2) c[i] = a[i] + b[i];
+}
+
+// partial sums of a . b (or of a . (b + c) when c != null), fixed order
+__global__ void dot_partial_kernel(const double* a, const double* b, const double* c, int64_t n,
+                                   double* part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s += a[i] * (c ? b[i] + c[i] : b[i]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void maxabs_partial_kernel(const double* a, int64_t n, double* part) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    s = fmax(s, fabs(a[i]));
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + o]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+// E = A - A^T
+__global__ void antisym_kernel(const double* A, double* E, int n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * n) return;
+  const int r = (int)(i / n), c = (int)(i % n);
+  E[i] = A[i] - A[(int64_t)c * n + r];
+}
+
+struct Comb {
+  const double* F[16];
+  double c[16];
+  int m;
+};
+__global__ void lincomb_kernel(Comb cb, double* out, int64_t n2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n2) return;
+  double s = 0.0;
+  for (int k = 0; k < cb.m; ++k) s += cb.c[k] * cb.F[k][i];
+  out[i] = s;
+}
+
+// X[mu][k] = W[ndrop + k][mu] / sqrt(s[ndrop + k]); rows of W are eigenvectors of S
+__global__ void build_x_kernel(const double* W, const double* s, int n, int ndrop, int m, double* X) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * m) return;
+  const int mu = (int)(i / m), k = (int)(i % m);
+  X[i] = W[(int64_t)(ndrop + k) * n + mu] / sqrt(s[ndrop + k]);
+}
+
+__global__ void copy_cols_kernel(const double* A, int lda, int rows, int cols, double* B, int ldb) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)rows * cols) return;
+  const int r = (int)(i / cols), c = (int)(i % cols);
+  B[(int64_t)r * ldb + c] = A[(int64_t)r * lda + c];
+}
+
+static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+// ---- driver ---------------------------------------------------------------------------
+struct Scf {
+  hipStream_t st{};
+  rocblas_handle rb{};
+  int n = 0, m = 0, nocc = 0;
+  DevMem part, eig_e, eig_info;
+  std::vector<double> hpart;
+
+  double reduce_sum(const double* a, const double* b, const double* c, int64_t cnt) {
+    const int nb = 512;
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(nb), dim3(256), 0, st, a, b, c, cnt, part.as<double>());
+    hpart.resize(nb);
+    DFX_HIP(hipMemcpyAsync(hpart.data(), part.p, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    DFX_HIP(hipStreamSynchronize(st));
+    double s = 0.0;
+    for (double v : hpart) s += v;
+    return s;
+  }
+  double reduce_max(const double* a, int64_t cnt) {
+    const int nb = 512;
+    hipLaunchKernelGGL(maxabs_partial_kernel, dim3(nb), dim3(256), 0, st, a, cnt, part.as<double>());
+    hpart.resize(nb);
+    DFX_HIP(hipMemcpyAsync(hpart.data(), part.p, sizeof(double) * nb, hipMemcpyDeviceToHost, st));
+    DFX_HIP(hipStreamSynchronize(st));
+    double s = 0.0;
+    for (double v : hpart) s = std::max(s, v);
+    return s;
+  }
+  void gemm(int M, int N, int K, const double* A, int lda, bool ta, const double* B, int ldb, bool tb,
+            double* C, int ldc, double alpha = 1.0, double beta = 0.0) {
+    GemmF64 g{};
+    g.M = M; g.N = N; g.K = K;
+    g.A = A; g.lda = lda; g.ta = ta;
+    g.B = B; g.ldb = ldb; g.tb = tb;
+    g.C = C; g.ldc = ldc;
+    g.alpha = alpha; g.beta = beta; g.batch = 1;
+    dgemm(g, st);
+  }
+  // symmetric eigen-decomposition in place: A (k x k) -> rows are eigenvectors, w ascending
+  void syevd(double* A, int k, double* w) {
+    if (eig_e.n < sizeof(double) * k) eig_e.alloc(sizeof(double) * k);
+    if (rocsolver_dsyevd(rb, rocblas_evect_original, rocblas_fill_upper, k, A, k, w, eig_e.as<double>(),
+                         eig_info.as<rocblas_int>()) != rocblas_status_success)
+      throw Error(DFX_EHIP, "rocsolver_dsyevd failed");
+    int info = 0;
+    DFX_HIP(hipMemcpyAsync(&info, eig_info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+    DFX_HIP(hipStreamSynchronize(st));
+    if (info != 0) throw Error(DFX_EHIP, "rocsolver_dsyevd did not converge");
+  }
+};
+
+// Solve the bordered DIIS system  [B -1; -1 0] [c; l] = [0; -1]  (Gaussian elimination
+// with partial pivoting).  Returns false if it is singular to working precision.
+static bool diis_solve(const std::vector<double>& Bm, int m, std::vector<double>& c) {
+  const int N = m + 1;
+  std::vector<double> A((size_t)N * N, 0.0), r(N, 0.0);
+  // scale the error overlaps for conditioning
+  double sc = 0.0;
+  for (int i = 0; i < m; ++i) sc = std::max(sc, std::fabs(Bm[i * m + i]));
+  if (!(sc > 0.0)) return false;
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) A[i * N + j] = Bm[i * m + j] / sc;
+  for (int i = 0; i < m; ++i) A[i * N + m] = A[m * N + i] = -1.0;
+  r[m] = -1.0;
+  double amax = 0.0, amin = 1e300;
+  for (int k = 0; k < N; ++k) {
+    int p = k;
+    for (int i = k + 1; i < N; ++i)
+      if (std::fabs(A[i * N + k]) > std::fabs(A[p * N + k])) p = i;
+    if (p != k) {
+      for (int j = 0; j < N; ++j) std::swap(A[k * N + j], A[p * N + j]);
+      std::swap(r[k], r[p]);
+    }
+    const double piv = A[k * N + k];
+    amax = std::max(amax, std::fabs(piv));
+    amin = std::min(amin, std::fabs(piv));
+    if (piv == 0.0) return false;
+    for (int i = k + 1; i < N; ++i) {
+      const double f = A[i * N + k] / piv;
+      for (int j = k; j < N; ++j) A[i * N + j] -= f * A[k * N + j];
+      r[i] -= f * r[k];
+    }
+  }
+  if (amin < 1e-14 * amax) return false;
+  std::vector<double> x(N);
+  for (int k = N - 1; k >= 0; --k) {
+    double s = r[k];
+    for (int j = k + 1; j < N; ++j) s -= A[k * N + j] * x[j];
+    x[k] = s / A[k * N + k];
+  }
+  c.assign(x.begin(), x.begin() + m);
+  return true;
+}
+
+}  // namespace dfx
+
+using namespace dfx;
+
+extern "C" {
+
+void dfx_scf_default_opts(dfx_scf_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof(*o));
+  o->tau = 1e-12;
+  o->conv_dE = 1e-10;
+  o->conv_err = 1e-7;
+  o->ortho_thresh = 1e-8;
+  o->switch_err = 1e-5;
+  o->max_iter = 100;
+  o->diis_size = 8;
+  o->schedule = DFX_SCHED_FP64;
+  o->mixed_prec = DFX_FP32;
+  o->guess = DFX_GUESS_CORE;
+  o->verbose = 0;
+}
+
+int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
+            const dfx_scf_opts* opts_in, const double* init, double* E_out, double* C_out, double* eps_out,
+            dfx_scf_info* info) {
+  int status = DFX_OK;
+  const int rc = guard([&] {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    if (!geom || !E_out) throw Error(DFX_EINVAL, "dfx_scf: NULL argument");
+    if (geom->natom <= 0 || !geom->xyz || !geom->Z) throw Error(DFX_EINVAL, "dfx_scf: bad geometry");
+    dfx_scf_opts o;
+    dfx_scf_default_opts(&o);
+    if (opts_in) o = *opts_in;
+    if (o.diis_size < 1 || o.diis_size > 16 || o.max_iter < 1) throw Error(DFX_EINVAL, "dfx_scf: bad options");
+    if ((o.guess == DFX_GUESS_CINIT || o.guess == DFX_GUESS_DENSITY) && !init)
+      throw Error(DFX_EINVAL, "dfx_scf: guess needs init");
+    int nelec = -geom->charge;
+    for (int a = 0; a < geom->natom; ++a) nelec += geom->Z[a];
+    if (nelec <= 0 || nelec % 2) throw Error(DFX_EINVAL, "dfx_scf: closed shell needs an even, positive electron count");
+    const int nocc = nelec / 2;
+    HostShells hb = make_shells(shells, nsh, 3, "orbital basis");
+    HostShells ha = make_shells(aux, nauxsh, 4, "auxiliary basis");
+    const int n = hb.nbf;
+    if (nocc > n) throw Error(DFX_EINVAL, "dfx_scf: more occupied orbitals than basis functions");
+
+    Scf S;
+    DFX_HIP(hipStreamCreate(&S.st));
+    struct Cleanup {
+      Scf& s;
+      ~Cleanup() {
+        if (s.rb) rocblas_destroy_handle(s.rb);
+        if (s.st) (void)hipStreamDestroy(s.st);
+      }
+    } cleanup{S};
+    if (rocblas_create_handle(&S.rb) != rocblas_status_success) throw Error(DFX_EHIP, "rocblas_create_handle failed");
+    rocblas_set_stream(S.rb, S.st);
+    hipStream_t st = S.st;
+    S.n = n;
+    S.nocc = nocc;
+    S.part.alloc(sizeof(double) * 512);
+    S.eig_info.alloc(sizeof(int));
+    const int64_t n2 = (int64_t)n * n;
+
+    // ---- setup: fitted integrals, one-electron matrices, E_nn, orthogonaliser
+    std::unique_ptr<dfx_B> B = build_B(std::move(hb), std::move(ha), o.tau, 0, st);
+    DevMem Sm(8 * n2), Tm(8 * n2), Vm(8 * n2), h(8 * n2);
+    int1e_build(B->bas, geom, Sm.as<double>(), Tm.as<double>(), Vm.as<double>(), st);
+    hipLaunchKernelGGL(add_kernel, dim3(nblk(n2)), dim3(256), 0, st, Tm.as<double>(), Vm.as<double>(),
+                       h.as<double>(), n2);
+    Tm.release();
+    Vm.release();
+    double Enuc = 0.0;
+    for (int a = 0; a < geom->natom; ++a)
+      for (int b = 0; b < a; ++b) {
+        const double* A = geom->xyz + 3 * a;
+        const double* Bx = geom->xyz + 3 * b;
+        const double r = std::sqrt((A[0] - Bx[0]) * (A[0] - Bx[0]) + (A[1] - Bx[1]) * (A[1] - Bx[1]) +
+                                   (A[2] - Bx[2]) * (A[2] - Bx[2]));
+        Enuc += (double)geom->Z[a] * geom->Z[b] / r;
+      }
+    DevMem W(8 * n2), sv(8 * (size_t)n);
+    DFX_HIP(hipMemcpyAsync(W.p, Sm.p, 8 * n2, hipMemcpyDeviceToDevice, st));
+    S.syevd(W.as<double>(), n, sv.as<double>());
+    std::vector<double> s_h(n);
+    DFX_HIP(hipMemcpyAsync(s_h.data(), sv.p, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+    DFX_HIP(hipStreamSynchronize(st));
+    int ndrop = 0;
+    while (ndrop < n && s_h[ndrop] < o.ortho_thresh) ++ndrop;
+    const int m = n - ndrop;
+    if (m < nocc) throw Error(DFX_EINVAL, "dfx_scf: basis too linearly dependent");
+    S.m = m;
+    DevMem X(8 * (size_t)n * m);
+    hipLaunchKernelGGL(build_x_kernel, dim3(nblk((int64_t)n * m)), dim3(256), 0, st, W.as<double>(),
+                       sv.as<double>(), n, ndrop, m, X.as<double>());
+    W.release();
+
+    DevMem F(8 * n2), D(8 * n2), Jm(8 * n2), Km(8 * n2), t1(8 * n2), t2(8 * n2);
+    DevMem Fp(8 * (size_t)m * m), eps(8 * (size_t)m), Cm(8 * (size_t)n * m), Cocc(8 * (size_t)n * nocc);
+    const int dsz = o.diis_size;
+    std::vector<DevMem> Fh(dsz), Eh(dsz);
+    for (int k = 0; k < dsz; ++k) {
+      Fh[k].alloc(8 * n2);
+      Eh[k].alloc(8 * (size_t)m * m);
+    }
+
+    // diagonalise a Fock-like matrix: C = X eig(X^T F X), Cocc = C[:, :nocc], D = Cocc Cocc^T
+    auto diag = [&](const double* Fx) {
+      S.gemm(m, n, n, X.as<double>(), m, true, Fx, n, false, t1.as<double>(), n);        // X^T F
+      S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Fp.as<double>(), m);
+      S.syevd(Fp.as<double>(), m, eps.as<double>());
+      S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm.as<double>(), m);  // X V
+      hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc)), dim3(256), 0, st, Cm.as<double>(), m,
+                         n, nocc, Cocc.as<double>(), nocc);
+      S.gemm(n, n, nocc, Cocc.as<double>(), nocc, false, Cocc.as<double>(), nocc, true, D.as<double>(), n);
+    };
+
+    // ---- guess
+    if (o.guess == DFX_GUESS_CORE) {
+      diag(h.as<double>());
+    } else if (o.guess == DFX_GUESS_CINIT) {
+      DevMem Ci(8 * n2);
+      DFX_HIP(hipMemcpyAsync(Ci.p, init, 8 * n2, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc)), dim3(256), 0, st, Ci.as<double>(), n, n,
+                         nocc, Cocc.as<double>(), nocc);
+      S.gemm(n, n, nocc, Cocc.as<double>(), nocc, false, Cocc.as<double>(), nocc, true, D.as<double>(), n);
+    } else if (o.guess == DFX_GUESS_DENSITY) {
+      // orthonormal-basis density X^T S D S X; its top nocc eigenvectors give C_occ
+      DevMem Di(8 * n2);
+      DFX_HIP(hipMemcpyAsync(Di.p, init, 8 * n2, hipMemcpyHostToDevice, st));
+      S.gemm(n, n, n, Sm.as<double>(), n, false, Di.as<double>(), n, false, t1.as<double>(), n);     // S D
+      S.gemm(n, n, n, t1.as<double>(), n, false, Sm.as<double>(), n, false, t2.as<double>(), n);     // S D S
+      S.gemm(m, n, n, X.as<double>(), m, true, t2.as<double>(), n, false, t1.as<double>(), n);       // X^T SDS
+      S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Fp.as<double>(), m);
+      S.syevd(Fp.as<double>(), m, eps.as<double>());
+      // eigenvectors of the largest nocc eigenvalues are the last nocc rows
+      S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm.as<double>(), m);
+      hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc)), dim3(256), 0, st,
+                         Cm.as<double>() + (m - nocc), m, n, nocc, Cocc.as<double>(), nocc);
+      S.gemm(n, n, nocc, Cocc.as<double>(), nocc, false, Cocc.as<double>(), nocc, true, D.as<double>(), n);
+    } else {
+      throw Error(DFX_EINVAL, "dfx_scf: unknown guess");
+    }
+    DFX_HIP(hipStreamSynchronize(st));
+    const auto t1c = clk::now();
+
+    // ---- iterations
+    JKArgs ja{B->hi.as<float>(), B->lo.as<float>(), B->naux, n, B->ncols_t, PREC_FP64};
+    const bool mixed = (o.schedule == DFX_SCHED_MIXED);
+    int prec = mixed ? o.mixed_prec : DFX_FP64;
+    int nfp64 = 0, it = 0, hcount = 0, hpos = 0, n_mixed = 0;
+    double E = 0.0, Eold = 0.0, emax = 0.0;
+    bool converged = false;
+    std::vector<double> Bdiis((size_t)dsz * dsz, 0.0);
+    dfx_scf_info inf{};
+    for (it = 1; it <= o.max_iter; ++it) {
+      ja.prec = prec;
+      const size_t need = std::max(sizeof(double) * (2 * (size_t)B->ncols_t + B->naux + 8), k_work_bytes(ja, nocc));
+      void* w = B->ensure_work(need);
+      j_build(ja, D.as<double>(), Jm.as<double>(), reinterpret_cast<double*>(w), st);
+      k_build(ja, Cocc.as<double>(), nocc, Km.as<double>(), w, st);
+      hipLaunchKernelGGL(fock_kernel, dim3(nblk(n2)), dim3(256), 0, st, h.as<double>(), Jm.as<double>(),
+                         Km.as<double>(), F.as<double>(), n2);
+      E = S.reduce_sum(D.as<double>(), h.as<double>(), F.as<double>(), n2) + Enuc;
+      // e = X^T (F D S - S D F) X
+      S.gemm(n, n, n, F.as<double>(), n, false, D.as<double>(), n, false, t1.as<double>(), n);
+      S.gemm(n, n, n, t1.as<double>(), n, false, Sm.as<double>(), n, false, t2.as<double>(), n);
+      hipLaunchKernelGGL(antisym_kernel, dim3(nblk(n2)), dim3(256), 0, st, t2.as<double>(), t1.as<double>(), n);
+      S.gemm(m, n, n, X.as<double>(), m, true, t1.as<double>(), n, false, t2.as<double>(), n);
+      double* e_new = Eh[hpos].as<double>();
+      S.gemm(m, m, n, t2.as<double>(), n, false, X.as<double>(), m, false, e_new, m);
+      emax = S.reduce_max(e_new, (int64_t)m * m);
+      if (it <= DFX_MAXHIST) {
+        inf.E_hist[it - 1] = E;
+        inf.err_hist[it - 1] = emax;
+      }
+      if (o.verbose)
+        std::fprintf(stderr, "dfx_scf it %3d  %s  E = %.12f  dE = %.3e  err = %.3e\n", it,
+                     prec == DFX_FP64 ? "fp64" : (prec == DFX_FP32 ? "fp32" : "bf16"), E, E - Eold, emax);
+      if (prec == DFX_FP64) {
+        ++nfp64;
+        const bool dE_ok = (mixed ? nfp64 >= 2 : it >= 2) && std::fabs(E - Eold) < o.conv_dE;
+        if (dE_ok && emax < o.conv_err) {
+          converged = true;
+          break;
+        }
+      } else {
+        ++n_mixed;
+      }
+      Eold = E;
+      // switch to FP64: the DIIS history restarts with FP64 Fock matrices only
+      if (prec != DFX_FP64 && emax < o.switch_err) {
+        prec = DFX_FP64;
+        hcount = 0;
+        hpos = 0;
+        diag(F.as<double>());
+        continue;
+      }
+      // DIIS history (ring buffer)
+      DFX_HIP(hipMemcpyAsync(Fh[hpos].p, F.p, 8 * n2, hipMemcpyDeviceToDevice, st));
+      hcount = std::min(hcount + 1, dsz);
+      // overlaps of the new error with every stored one
+      std::vector<double> Bn(dsz, 0.0);
+      for (int k = 0; k < hcount; ++k) Bn[k] = S.reduce_sum(Eh[k].as<double>(), e_new, nullptr, (int64_t)m * m);
+      for (int k = 0; k < hcount; ++k) Bdiis[(size_t)hpos * dsz + k] = Bdiis[(size_t)k * dsz + hpos] = Bn[k];
+      const double* Fuse = F.as<double>();
+      if (hcount > 1) {
+        // slots in age order (oldest first) for dropping when ill-conditioned
+        std::vector<int> slots;
+        for (int k = 0; k < hcount; ++k) slots.push_back((hpos + 1 + k + (dsz - hcount)) % dsz);
+        while (slots.size() > 1) {
+          const int mm = (int)slots.size();
+          std::vector<double> Bm((size_t)mm * mm), c;
+          for (int i = 0; i < mm; ++i)
+            for (int j = 0; j < mm; ++j) Bm[i * mm + j] = Bdiis[(size_t)slots[i] * dsz + slots[j]];
+          if (diis_solve(Bm, mm, c)) {
+            Comb cb{};
+            cb.m = mm;
+            for (int i = 0; i < mm; ++i) {
+              cb.F[i] = Fh[slots[i]].as<double>();
+              cb.c[i] = c[i];
+            }
+            hipLaunchKernelGGL(lincomb_kernel, dim3(nblk(n2)), dim3(256), 0, st, cb, t2.as<double>(), n2);
+            Fuse = t2.as<double>();
+            break;
+          }
+          slots.erase(slots.begin());
+        }
+      }
+      hpos = (hpos + 1) % dsz;
+      diag(Fuse);
+    }
+    DFX_HIP(hipStreamSynchronize(st));
+    const auto t2c = clk::now();
+
+    *E_out = E;
+    if (C_out) {
+      // full C (n x n): the first m columns from X C', the rest zero
+      std::vector<double> Ch((size_t)n * m), Cf((size_t)n * n, 0.0);
+      DFX_HIP(hipMemcpy(Ch.data(), Cm.p, 8 * (size_t)n * m, hipMemcpyDeviceToHost));
+      for (int r = 0; r < n; ++r)
+        for (int c = 0; c < m; ++c) Cf[(size_t)r * n + c] = Ch[(size_t)r * m + c];
+      std::memcpy(C_out, Cf.data(), 8 * n2);
+    }
+    if (eps_out) {
+      std::vector<double> e(m);
+      DFX_HIP(hipMemcpy(e.data(), eps.p, 8 * (size_t)m, hipMemcpyDeviceToHost));
+      for (int i = 0; i < n; ++i) eps_out[i] = i < m ? e[i] : 0.0;
+    }
+    inf.niter = std::min(it, o.max_iter);
+    inf.converged = converged ? 1 : 0;
+    inf.n_mixed = n_mixed;
+    inf.ndropped = ndrop;
+    inf.nbf = n;
+    inf.naux = B->naux;
+    inf.nocc = nocc;
+    inf.E_nuc = Enuc;
+    inf.err_max = emax;
+    inf.t_setup = std::chrono::duration<double>(t1c - t0).count();
+    inf.t_scf = std::chrono::duration<double>(t2c - t1c).count();
+    inf.t_total = std::chrono::duration<double>(clk::now() - t0).count();
+    if (info) *info = inf;
+    if (!converged) {
+      status = DFX_ENOCONV;
+      set_last_error("dfx_scf: not converged in " + std::to_string(o.max_iter) + " iterations");
+    }
+  });
+  return rc != DFX_OK ? rc : status;
+}
+
+}  // extern "C"

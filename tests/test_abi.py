@@ -1,0 +1,63 @@
+"""CPU checks of the C-ABI boundary: the library loads, exports every symbol
+include/dfx.h declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HDR = os.path.join(ROOT, "include", "dfx.h")
+LIB = os.path.join(ROOT, "paper_1707_03771_amd", "libdfx.so")
+
+
+def declared():
+    txt = open(HDR).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char\*)\s+(dfx_\w+)\s*\(", txt, re.M)))
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("dfx_eri3", "dfx_jk", "dfx_scf", "dfx_int1e", "dfx_last_error", "dfx_B_free"):
+        assert must in names
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdfx.so not built")
+def test_library_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    missing = [n for n in declared() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdfx.so not built")
+def test_argument_errors_are_status_codes():
+    import paper_1707_03771_amd as dfx
+    lib = dfx._lib
+    out = ctypes.c_void_p()
+    # empty basis
+    assert lib.dfx_eri3(None, 0, None, 0, None, None, ctypes.byref(out)) == dfx.EINVAL
+    assert "empty" in dfx.last_error()
+    # NULL output handle
+    assert lib.dfx_eri3(None, 1, None, 1, None, None, None) == dfx.EINVAL
+    # l beyond the compiled classes is reported before any device work
+    e = np.array([1.0]); c = np.array([1.0])
+    sh = (dfx.Shell * 1)()
+    sh[0].l, sh[0].nprim, sh[0].exps, sh[0].coefs = 4, 1, e.ctypes.data, c.ctypes.data
+    ax = (dfx.Shell * 1)()
+    ax[0].l, ax[0].nprim, ax[0].exps, ax[0].coefs = 0, 1, e.ctypes.data, c.ctypes.data
+    assert lib.dfx_eri3(sh, 1, ax, 1, None, None, ctypes.byref(out)) == dfx.EUNSUPPORTED
+    sh[0].l = 1
+    ax[0].l = 5
+    assert lib.dfx_eri3(sh, 1, ax, 1, None, None, ctypes.byref(out)) == dfx.EUNSUPPORTED
+    # malformed shells
+    sh[0].nprim = 0
+    ax[0].l = 0
+    assert lib.dfx_eri3(sh, 1, ax, 1, None, None, ctypes.byref(out)) == dfx.EINVAL
+    sh[0].nprim = 1
+    neg = np.array([-1.0])
+    sh[0].exps = neg.ctypes.data
+    assert lib.dfx_eri3(sh, 1, ax, 1, None, None, ctypes.byref(out)) == dfx.EINVAL
+    # jk / B calls on a NULL handle
+    assert lib.dfx_jk(None, None, 1, 1, 0, None, None, None) == dfx.EINVAL
+    assert lib.dfx_B_info_get(None, None) == dfx.EINVAL

@@ -1,0 +1,139 @@
+"""GPU path (through the C-ABI) against the CPU oracle, element by element.
+
+Tolerances (FP64): integrals agree to 1e-13 relative to the block scale plus
+1e-15 absolute (two exact algorithms, Rys vs McMurchie-Davidson); screening
+lists and offsets are bit-exact; B, J and K meet 1e-9 absolute.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+import systems
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dfx():
+    import paper_1707_03771_amd as m
+    return m
+
+
+def _np(t):
+    return t.detach().cpu().numpy()
+
+
+def _ref_df(sh, ax, tau=1e-12):
+    bas, aux = O.Basis(sh), O.Basis(ax)
+    Qab, QC = O.schwarz(bas, aux)
+    scr = O.screen(bas, aux, Qab, QC, tau)
+    raw = O.eri3_packed(bas, aux, scr)
+    J2 = O.eri2(aux)
+    L, B = O.fit(raw, J2)
+    return bas, aux, Qab, QC, scr, raw, J2, L, B
+
+
+SYSTEMS = {
+    "h4": lambda: systems.h4()[2:4],
+    "mixed": lambda: systems.mixed_molecule()[2:4],
+    "mixed_d": lambda: systems.mixed_molecule(seed=3, natom=6, lorb=2, laux=3)[2:4],
+}
+
+
+@pytest.fixture(scope="module", params=list(SYSTEMS))
+def case(request, dfx):
+    sh, ax = SYSTEMS[request.param]()
+    ref = _ref_df(sh, ax)
+    B = dfx.eri3(sh, ax, tau=1e-12, flags=dfx.KEEP_RAW | dfx.KEEP_METRIC)
+    torch.cuda.synchronize()
+    yield request.param, sh, ax, ref, B
+    B.free()
+
+
+def test_schwarz_factors_and_lists_bit_exact(case):
+    name, sh, ax, ref, B = case
+    bas, aux, Qab, QC, scr = ref[:5]
+    pairs, off, keep, gQab, gQC = B.lists(keep=True)
+    assert np.abs(gQab - Qab).max() <= 1e-13 * Qab.max()
+    assert np.abs(gQC - QC).max() <= 1e-13 * QC.max()
+    # bit-exact integer contract, unless a product sits on the threshold
+    if scr.margin > 1e-12:
+        assert np.array_equal(pairs, scr.pairs)
+        assert np.array_equal(off, scr.col_off)
+        assert np.array_equal(keep.astype(bool), scr.keep)
+    assert B.info["npairs"] == len(scr.pairs) and B.info["ncols"] == scr.col_off[-1]
+    assert B.info["ntriplets"] == int(scr.keep.sum())
+
+
+def test_raw_three_index_integrals(case):
+    name, sh, ax, ref, B = case
+    raw = ref[5]
+    g = _np(B.export(what=2))
+    scale = np.abs(raw).max()
+    err = np.abs(g - raw)
+    assert err.max() <= 1e-13 * scale + 1e-15, (name, err.max(), scale)
+
+
+def test_metric_cholesky_and_B(case):
+    name, sh, ax, ref, B = case
+    J2, L, Bref = ref[6], ref[7], ref[8]
+    gJ = _np(B.metric(0))
+    assert np.abs(np.tril(gJ) - np.tril(J2)).max() <= 1e-13 * np.abs(J2).max()
+    gL = _np(B.metric(1))
+    assert np.abs(gL - L).max() <= 1e-11 * np.abs(L).max() * max(1.0, B.info["kappa_lb"] ** 0.5 * 1e-4)
+    gB = _np(B.export(what=0))
+    assert np.abs(gB - Bref).max() <= 1e-9, np.abs(gB - Bref).max()
+    ghi = _np(B.export(what=1))
+    assert np.abs(ghi - Bref).max() <= 2 ** -23 * np.abs(Bref).max() * 1.01
+
+
+def test_jk_fp64(case, dfx):
+    name, sh, ax, ref, B = case
+    bas, aux, Qab, QC, scr, raw, J2, L, Bref = ref
+    df = O.DF(bas, aux, scr, Bref, L)
+    rng = np.random.default_rng(1)
+    nocc = max(2, min(12, bas.nbf // 5))
+    C = np.linalg.qr(rng.normal(size=(bas.nbf, nocc)))[0]
+    Jr, Kr = O.jk(df, C=C)
+    Cg = torch.tensor(C, device="cuda")
+    J, K = dfx.jk(B, Cg, kind=dfx.COCC, precision=dfx.FP64)
+    assert np.abs(_np(J) - Jr).max() <= 1e-9
+    assert np.abs(_np(K) - Kr).max() <= 1e-9
+    # J from an explicit density
+    Dg = Cg @ Cg.T
+    J2g, _ = dfx.jk(B, Dg, kind=dfx.DENSITY, want_k=False)
+    assert np.abs(_np(J2g) - Jr).max() <= 1e-9
+
+
+def test_one_electron(case, dfx):
+    name, sh, ax, ref, B = case
+    rng = np.random.default_rng(2)
+    xyz = np.array([s["center"] for s in sh])[::3][:5] + rng.normal(0, 0.3, size=(1, 3))
+    Z = np.arange(1, len(xyz) + 1, dtype=np.int32)
+    S, T, V = O.int1e(O.Basis(sh), xyz, Z)
+    gS, gT, gV = dfx.int1e(sh, xyz, Z)
+    for g, r in ((gS, S), (gT, T), (gV, V)):
+        assert np.abs(_np(g) - r).max() <= 1e-12 * np.abs(r).max()
+
+
+def test_repeatable_bitwise(dfx):
+    """No atomics on the path: two runs give identical B, J and K bits."""
+    sh, ax = SYSTEMS["mixed"]()
+    B1 = dfx.eri3(sh, ax)
+    B2 = dfx.eri3(sh, ax)
+    assert torch.equal(B1.export(0), B2.export(0))
+    C = torch.tensor(np.linalg.qr(np.random.default_rng(0).normal(size=(B1.nbf, 7)))[0], device="cuda")
+    J1, K1 = dfx.jk(B1, C)
+    J2, K2 = dfx.jk(B2, C)
+    assert torch.equal(J1, J2) and torch.equal(K1, K2)
+
+
+def test_not_positive_definite_metric_is_reported(dfx):
+    """A duplicated aux shell makes J_PQ singular: ENOTPOSDEF, no handle."""
+    sh, ax = SYSTEMS["h4"]()
+    ax = ax + [dict(ax[0])]
+    with pytest.raises(dfx.DfxError) as e:
+        dfx.eri3(sh, ax)
+    assert e.value.code == dfx.ENOTPOSDEF

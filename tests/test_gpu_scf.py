@@ -1,0 +1,84 @@
+"""End-to-end DF-RHF on the GPU (dfx_scf through the C-ABI) against the oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+import systems
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dfx():
+    import paper_1707_03771_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def h4_ref():
+    xyz, Z, sh, ax, nocc = systems.h4()
+    res, df = O.df_rhf(Z, xyz, sh, ax, nocc)
+    assert res.converged
+    return xyz, Z, sh, ax, nocc, res
+
+
+def test_h4_fp64_matches_oracle(dfx, h4_ref):
+    xyz, Z, sh, ax, nocc, ref = h4_ref
+    E, C, eps, info = dfx.scf(xyz, Z, sh, ax, conv_dE=1e-10, conv_err=1e-8)
+    assert info["converged"] and info["status"] == dfx.OK
+    assert abs(E - ref.E) <= 1e-8, (E, ref.E)
+    D = C[:, :nocc] @ C[:, :nocc].T
+    assert np.abs(D - ref.D).max() <= 1e-6
+    assert np.allclose(eps[:nocc], ref.eps[:nocc], atol=1e-6)
+
+
+def test_restart_from_converged_orbitals(dfx, h4_ref):
+    xyz, Z, sh, ax, nocc, ref = h4_ref
+    E, C, _, info = dfx.scf(xyz, Z, sh, ax)
+    E2, _, _, info2 = dfx.scf(xyz, Z, sh, ax, init=C, guess=dfx.GUESS_CINIT)
+    assert abs(E2 - E) <= 1e-10 and info2["niter"] <= 3
+
+
+def test_density_guess(dfx, h4_ref):
+    xyz, Z, sh, ax, nocc, ref = h4_ref
+    E, _, _, info = dfx.scf(xyz, Z, sh, ax, init=ref.D, guess=dfx.GUESS_DENSITY)
+    assert abs(E - ref.E) <= 1e-8 and info["niter"] <= 3
+
+
+def test_not_converged_is_reported_with_outputs(dfx, h4_ref):
+    xyz, Z, sh, ax, nocc, ref = h4_ref
+    E, C, _, info = dfx.scf(xyz, Z, sh, ax, max_iter=1)
+    assert info["status"] == dfx.ENOCONV and not info["converged"]
+    assert np.isfinite(E) and np.abs(C).max() > 0
+
+
+@pytest.mark.parametrize("prec", ["FP32"])
+def test_mixed_schedule_recovers_fp64_energy(dfx, h4_ref, prec):
+    xyz, Z, sh, ax, nocc, ref = h4_ref
+    E, _, _, info = dfx.scf(xyz, Z, sh, ax, schedule=dfx.SCHED_MIXED, mixed_prec=getattr(dfx, prec),
+                            switch_err=1e-5)
+    assert info["converged"] and info["n_mixed"] >= 1
+    assert abs(E - ref.E) <= 1e-8
+
+
+def test_rotation_invariance_on_gpu(dfx, h4_ref):
+    xyz, Z, sh, ax, nocc, ref = h4_ref
+    rng = np.random.default_rng(9)
+    q = np.linalg.qr(rng.normal(size=(3, 3)))[0]
+    if np.linalg.det(q) < 0:
+        q[:, 0] *= -1
+    new = xyz @ q.T + rng.normal(size=3)
+    E, _, _, info = dfx.scf(new, Z, W.shells_at(sh, xyz, new), W.shells_at(ax, xyz, new))
+    assert info["converged"] and abs(E - ref.E) <= 1e-9
+
+
+def test_multi_class_molecule(dfx):
+    """s..d orbital / s..f auxiliary classes, contracted shells, several tiles."""
+    xyz, Z, sh, ax = systems.mixed_molecule(seed=3, natom=6, lorb=2, laux=3)
+    Z = np.array([1] * len(Z), np.int32)  # six H-like centres: 3 occupied orbitals
+    res, df = O.df_rhf(Z, xyz, sh, ax, 3, max_iter=200)
+    E, C, _, info = dfx.scf(xyz, Z, sh, ax, max_iter=200)
+    assert res.converged and info["converged"]
+    assert abs(E - res.E) <= 1e-8
