@@ -216,6 +216,18 @@ typedef struct {
   double t_setup;        /* seconds: integrals + fitting + one-electron + guess */
   double t_scf;          /* seconds: the iterations */
   double t_total;
+  /* GPU time per phase (HIP events on the SCF stream), seconds */
+  double t_eri;          /* three-index ERI kernels */
+  double t_metric;       /* metric, Schwarz, Cholesky and L^-1 */
+  double t_trsm;         /* B = L^-1 (mu nu|P) with the FP32 split */
+  double t_j;            /* all J builds */
+  double t_kx;           /* all K half-transforms X_Q = B_Q C_occ */
+  double t_ksyrk;        /* all K contractions sum_Q X_Q X_Q^T (incl. reduction) */
+  double t_eig;          /* all eigensolves */
+  int32_t n_jk;          /* J/K builds performed */
+  int32_t n_kx_launch;   /* half-transform kernel launches */
+  int64_t nintegrals;    /* unique evaluated three-index integrals */
+  int64_t ncols;         /* packed pair columns of B */
   double E_hist[DFX_MAXHIST];
   double err_hist[DFX_MAXHIST];
 } dfx_scf_info;

@@ -72,6 +72,10 @@ class ScfInfo(ctypes.Structure):
                 ("ndropped", ctypes.c_int32), ("nbf", ctypes.c_int32), ("naux", ctypes.c_int32),
                 ("nocc", ctypes.c_int32), ("E_nuc", ctypes.c_double), ("err_max", ctypes.c_double),
                 ("t_setup", ctypes.c_double), ("t_scf", ctypes.c_double), ("t_total", ctypes.c_double),
+                ("t_eri", ctypes.c_double), ("t_metric", ctypes.c_double), ("t_trsm", ctypes.c_double),
+                ("t_j", ctypes.c_double), ("t_kx", ctypes.c_double), ("t_ksyrk", ctypes.c_double),
+                ("t_eig", ctypes.c_double), ("n_jk", ctypes.c_int32), ("n_kx_launch", ctypes.c_int32),
+                ("nintegrals", ctypes.c_int64), ("ncols", ctypes.c_int64),
                 ("E_hist", ctypes.c_double * MAXHIST), ("err_hist", ctypes.c_double * MAXHIST)]
 
 

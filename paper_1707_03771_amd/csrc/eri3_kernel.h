@@ -13,7 +13,7 @@
 // second bra function replaced by the constant 1 (UNITB).
 #pragma once
 #include "common.h"
-#include "kernels.h"
+#include "eri_args.h"
 #include "rys.h"
 #include "sph_tables.inc"
 
@@ -237,6 +237,9 @@ inline dim3 eri3_grid(Eri3Args& a) {
   const int gy = (a.nk + chunk - 1) / chunk;
   return dim3(gx, gy, 1);
 }
+
+void eri3_dispatch(int LA, int LB, int LC, bool unitb, int mode, Eri3Args a, hipStream_t st);
+void metric_dispatch(int LA, int LC, Eri3Args a, hipStream_t st);
 
 // class dispatch (eri3_dispatch.hip); one translation unit per (LA, LB)
 template <int LA, int LB>

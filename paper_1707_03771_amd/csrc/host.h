@@ -74,6 +74,43 @@ struct GpuTimer {
   }
 };
 
+// Accumulates GPU time of repeated intervals: events are recorded on the
+// stream and only read once, after the final synchronisation.
+struct EventSpans {
+  hipStream_t st{};
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> spans;
+  bool open = false;
+  void begin() {
+    hipEvent_t a, b;
+    DFX_HIP(hipEventCreate(&a));
+    DFX_HIP(hipEventCreate(&b));
+    DFX_HIP(hipEventRecord(a, st));
+    spans.emplace_back(a, b);
+    open = true;
+  }
+  void end() {
+    DFX_HIP(hipEventRecord(spans.back().second, st));
+    open = false;
+  }
+  double seconds() {
+    double t = 0.0;
+    for (auto& p : spans) {
+      float ms = 0.0f;
+      DFX_HIP(hipEventSynchronize(p.second));
+      DFX_HIP(hipEventElapsedTime(&ms, p.first, p.second));
+      t += ms * 1e-3;
+    }
+    return t;
+  }
+  int count() const { return (int)spans.size(); }
+  ~EventSpans() {
+    for (auto& p : spans) {
+      (void)hipEventDestroy(p.first);
+      (void)hipEventDestroy(p.second);
+    }
+  }
+};
+
 }  // namespace dfx
 
 // ---- the fitted tensor handle -------------------------------------------------------

@@ -255,7 +255,8 @@ size_t k_work_bytes(const JKArgs& a, int nocc) {
   return (p.x_elems + p.p_elems) * sizeof(double) + 256;
 }
 
-void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st) {
+void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st,
+             KTimer* timer) {
   if (a.prec != PREC_FP64) throw Error(-6, "k_build: precision not available yet");
   const KPlan p = k_plan(a, nocc);
   double* X = reinterpret_cast<double*>(work);
@@ -266,7 +267,10 @@ void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, 
     const int nq = std::min(p.qc, a.naux - q0);
     if (nq < p.ns * p.qs) fill_f64(X, p.x_elems, 0.0, st);
     const dim3 g1((a.nbf + KM - 1) / KM, (nocc + KN - 1) / KN, nq);
+    if (timer) timer->begin_x();
     hipLaunchKernelGGL(kx_f64_kernel, g1, dim3(KT), 0, st, a.hi, a.lo, a.ncols, a.nbf, q0, C, nocc, X, ldx);
+    if (timer) timer->end_x();
+    if (timer) timer->begin_syrk();
     GemmF64 g{};
     g.M = a.nbf; g.N = a.nbf; g.K = p.qs * nocc;
     g.A = X; g.lda = ldx; g.sA = (int64_t)p.qs * nocc;
@@ -276,6 +280,7 @@ void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, 
     dgemm(g, st);
     hipLaunchKernelGGL(k_reduce_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, P, p.ns,
                        a.nbf, K, q0 > 0 ? 1 : 0);
+    if (timer) timer->end_syrk();
   }
   sym_from_lower(K, a.nbf, st);
 }

@@ -1,27 +1,9 @@
 // Internal launch interface of the dfx kernels (not part of the C-ABI).
 #pragma once
 #include "common.h"
+#include "eri_args.h"
 
 namespace dfx {
-
-enum { STORE_TILED = 0, STORE_DENSE = 1 };
-
-struct Eri3Args {
-  DevShells F, S, K;         // shells of the first and second bra index and of the ket
-  const int* pf;             // [npairs] first bra shell (angular momentum LA)
-  const int* ps;             // [npairs] second bra shell (LB); unused with UNITB
-  const unsigned char* rowfirst;  // [npairs] 1: first shell indexes rows of B
-  const double* pq;          // [npairs] Schwarz factor of the pair, or null
-  int npairs;
-  const int* kl;             // [nk] ket shells of angular momentum LC
-  const double* kq;          // [nk] their Schwarz factors
-  int nk;
-  int kchunk;                // ket shells per workgroup
-  double tau;                // screening threshold: evaluate iff Q_ab Q_C >= tau
-  double* out;
-  int64_t ld;                // row stride of out (elements)
-  const double* rys;         // device Rys table
-};
 
 struct SchwarzArgs {
   DevShells sh;
@@ -89,7 +71,16 @@ struct JKArgs {
 void j_build(const JKArgs& a, const double* D, double* J, double* work, hipStream_t st);
 // K from the occupied block C [nbf][nocc] (row-major); work >= k_work_bytes
 size_t k_work_bytes(const JKArgs& a, int nocc);
-void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st);
+// optional GPU timers around the two K phases (events are recorded on st)
+struct KTimer {
+  virtual void begin_x() = 0;
+  virtual void end_x() = 0;
+  virtual void begin_syrk() = 0;
+  virtual void end_syrk() = 0;
+  virtual ~KTimer() = default;
+};
+void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st,
+             KTimer* timer = nullptr);
 // canonical packed rows [q1 - q0][ncols_p] (FP64) from the tiled storage;
 // toff[c] is the tile offset of packed column c
 void export_rows(const float* hi, const float* lo, const double* raw, int64_t ncols_t, int q0, int q1,

@@ -106,6 +106,7 @@ struct Scf {
   int n = 0, m = 0, nocc = 0;
   DevMem part, eig_e, eig_info;
   std::vector<double> hpart;
+  EventSpans* eig_spans = nullptr;
 
   double reduce_sum(const double* a, const double* b, const double* c, int64_t cnt) {
     const int nb = 512;
@@ -140,9 +141,11 @@ struct Scf {
   // symmetric eigen-decomposition in place: A (k x k) -> rows are eigenvectors, w ascending
   void syevd(double* A, int k, double* w) {
     if (eig_e.n < sizeof(double) * k) eig_e.alloc(sizeof(double) * k);
+    if (eig_spans) eig_spans->begin();
     if (rocsolver_dsyevd(rb, rocblas_evect_original, rocblas_fill_upper, k, A, k, w, eig_e.as<double>(),
                          eig_info.as<rocblas_int>()) != rocblas_status_success)
       throw Error(DFX_EHIP, "rocsolver_dsyevd failed");
+    if (eig_spans) eig_spans->end();
     int info = 0;
     DFX_HIP(hipMemcpyAsync(&info, eig_info.p, sizeof(int), hipMemcpyDeviceToHost, st));
     DFX_HIP(hipStreamSynchronize(st));
@@ -254,6 +257,9 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     S.n = n;
     S.nocc = nocc;
     S.part.alloc(sizeof(double) * 512);
+    EventSpans sp_eig_all;
+    sp_eig_all.st = S.st;
+    S.eig_spans = &sp_eig_all;
     S.eig_info.alloc(sizeof(int));
     const int64_t n2 = (int64_t)n * n;
 
@@ -340,6 +346,17 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     const auto t1c = clk::now();
 
     // ---- iterations
+    EventSpans sp_j, sp_kx, sp_ks;
+    sp_j.st = sp_kx.st = sp_ks.st = st;
+    struct Timer : KTimer {
+      EventSpans *x, *s;
+      void begin_x() override { x->begin(); }
+      void end_x() override { x->end(); }
+      void begin_syrk() override { s->begin(); }
+      void end_syrk() override { s->end(); }
+    } ktimer;
+    ktimer.x = &sp_kx;
+    ktimer.s = &sp_ks;
     JKArgs ja{B->hi.as<float>(), B->lo.as<float>(), B->naux, n, B->ncols_t, PREC_FP64};
     const bool mixed = (o.schedule == DFX_SCHED_MIXED);
     int prec = mixed ? o.mixed_prec : DFX_FP64;
@@ -352,8 +369,10 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
       ja.prec = prec;
       const size_t need = std::max(sizeof(double) * (2 * (size_t)B->ncols_t + B->naux + 8), k_work_bytes(ja, nocc));
       void* w = B->ensure_work(need);
+      sp_j.begin();
       j_build(ja, D.as<double>(), Jm.as<double>(), reinterpret_cast<double*>(w), st);
-      k_build(ja, Cocc.as<double>(), nocc, Km.as<double>(), w, st);
+      sp_j.end();
+      k_build(ja, Cocc.as<double>(), nocc, Km.as<double>(), w, st, &ktimer);
       hipLaunchKernelGGL(fock_kernel, dim3(nblk(n2)), dim3(256), 0, st, h.as<double>(), Jm.as<double>(),
                          Km.as<double>(), F.as<double>(), n2);
       E = S.reduce_sum(D.as<double>(), h.as<double>(), F.as<double>(), n2) + Enuc;
@@ -454,6 +473,17 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     inf.t_setup = std::chrono::duration<double>(t1c - t0).count();
     inf.t_scf = std::chrono::duration<double>(t2c - t1c).count();
     inf.t_total = std::chrono::duration<double>(clk::now() - t0).count();
+    inf.t_eri = B->info.eri_seconds;
+    inf.t_metric = B->info.metric_seconds;
+    inf.t_trsm = B->info.trsm_seconds;
+    inf.t_j = sp_j.seconds();
+    inf.t_kx = sp_kx.seconds();
+    inf.t_ksyrk = sp_ks.seconds();
+    inf.t_eig = S.eig_spans ? S.eig_spans->seconds() : 0.0;
+    inf.n_jk = sp_j.count();
+    inf.n_kx_launch = sp_kx.count();
+    inf.nintegrals = B->info.nintegrals;
+    inf.ncols = B->info.ncols;
     if (info) *info = inf;
     if (!converged) {
       status = DFX_ENOCONV;
