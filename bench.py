@@ -39,26 +39,32 @@ def log(*a):
 
 def roofline(info, nbf, naux, nocc):
     """Roofline of the kernel with the largest GPU time, from the live HIP-event
-    timings the library reports (algorithmic FLOPs / average launch time)."""
-    n_jk = max(1, info["n_jk"])
-    cands = {
-        # B = L^-1 raw over the packed pair columns: sum_Q 2 (Q + 1) ncols
-        "trsm_split (B = L^-1 raw, FP64 MFMA)": (info["t_trsm"], naux * (naux + 1.0) * info["ncols"], 1),
+    timings the library reports per kernel and precision: algorithmic FLOPs per
+    launch / average launch time, against the peak of the precision used."""
+    peaks = {0: ("FP64", PEAK_FP64), 1: ("FP32", PEAK_FP32_MFMA), 2: ("BF16", PEAK_BF16_MFMA)}
+    cands = {"trsm_split (B = L^-1 raw), FP64 MFMA":
+             (info["t_trsm"], naux * (naux + 1.0) * info["ncols"], 1, PEAK_FP64)}
+    for p, (pname, peak) in peaks.items():
+        nj = info["n_jk_p"][p]
+        nl = info["n_kx_launch_p"][p]
+        if nj == 0:
+            continue
         # X_Q = B_Q C_occ for every Q, per K build
-        "kx_f64 (K half-transform, FP64 MFMA)": (info["t_kx"], 2.0 * nbf * nbf * nocc * naux * n_jk,
-                                                 info["n_kx_launch"]),
+        cands[f"K half-transform X_Q = B_Q C, {pname} MFMA"] = (info["t_kx_p"][p], 2.0 * nbf * nbf * nocc * naux * nj,
+                                                               nl, peak)
         # sum_Q X_Q X_Q^T, lower triangle, per K build
-        "dgemm NT (K contraction, FP64 MFMA)": (info["t_ksyrk"], nbf * (nbf + 1.0) * nocc * naux * n_jk,
-                                                info["n_kx_launch"]),
-    }
-    name, (t, flops, launches) = max(cands.items(), key=lambda kv: kv[1][0])
+        cands[f"K contraction sum_Q X_Q X_Q^T, {pname} MFMA"] = (info["t_ksyrk_p"][p],
+                                                                nbf * (nbf + 1.0) * nocc * naux * nj, nl, peak)
+    name, (t, flops, launches, peak) = max(cands.items(), key=lambda kv: kv[1][0])
     if t <= 0:
         return None
     launches = max(1, launches)
     achieved = (flops / launches) / (t / launches)
-    return {"kernel": name, "bound": "mfma", "achieved": achieved / 1e12, "peak": PEAK_FP64 / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / PEAK_FP64, "traffic": None,
-            "flops_per_launch": flops / launches, "avg_launch_ms": 1e3 * t / launches}
+    return {"kernel": name, "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "flops_per_launch": flops / launches, "avg_launch_ms": 1e3 * t / launches,
+            "all": {k: {"s": round(v[0], 4), "TFLOP/s": round(v[1] / v[0] / 1e12, 2) if v[0] > 0 else None,
+                        "frac": round(v[1] / v[0] / v[3], 4) if v[0] > 0 else None} for k, v in cands.items()}}
 
 
 def cpu_baseline(elems, xyz, sh, ax, niter, budget_pairs=250, q_rows=16, seed=0):
@@ -128,7 +134,7 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="water4")
-    ap.add_argument("--schedule", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--schedule", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--mixed-prec", default="fp32", choices=["fp32", "bf16"])
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 reference run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -159,6 +165,8 @@ def main():
         log(f"{tag}: E = {E:.10f}  iters {info['niter']} (mixed {info['n_mixed']})  "
             f"wall {dt:.2f} s  eri {info['t_eri']:.3f} trsm {info['t_trsm']:.3f} "
             f"j {info['t_j']:.3f} kx {info['t_kx']:.3f} ksyrk {info['t_ksyrk']:.3f} eig {info['t_eig']:.3f}")
+        pn = {0: "d", 1: "s", 2: "b"}
+        log("   history: " + " ".join(f"{pn.get(p, '?')}{e:.1e}" for p, e in zip(info["prec_hist"], info["err_hist"])))
         return E, info, dt
 
     for w in range(a.warmup):

@@ -226,10 +226,16 @@ typedef struct {
   double t_eig;          /* all eigensolves */
   int32_t n_jk;          /* J/K builds performed */
   int32_t n_kx_launch;   /* half-transform kernel launches */
+  /* the same K figures split by precision, index DFX_FP64 / DFX_FP32 / DFX_BF16 */
+  double t_kx_p[3];
+  double t_ksyrk_p[3];
+  int32_t n_jk_p[3];
+  int32_t n_kx_launch_p[3];
   int64_t nintegrals;    /* unique evaluated three-index integrals */
   int64_t ncols;         /* packed pair columns of B */
   double E_hist[DFX_MAXHIST];
   double err_hist[DFX_MAXHIST];
+  int8_t prec_hist[DFX_MAXHIST];  /* DFX_FP64 / DFX_FP32 / DFX_BF16 of each Fock build */
 } dfx_scf_info;
 
 void dfx_scf_default_opts(dfx_scf_opts* o);

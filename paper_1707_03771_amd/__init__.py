@@ -75,8 +75,11 @@ class ScfInfo(ctypes.Structure):
                 ("t_eri", ctypes.c_double), ("t_metric", ctypes.c_double), ("t_trsm", ctypes.c_double),
                 ("t_j", ctypes.c_double), ("t_kx", ctypes.c_double), ("t_ksyrk", ctypes.c_double),
                 ("t_eig", ctypes.c_double), ("n_jk", ctypes.c_int32), ("n_kx_launch", ctypes.c_int32),
+                ("t_kx_p", ctypes.c_double * 3), ("t_ksyrk_p", ctypes.c_double * 3),
+                ("n_jk_p", ctypes.c_int32 * 3), ("n_kx_launch_p", ctypes.c_int32 * 3),
                 ("nintegrals", ctypes.c_int64), ("ncols", ctypes.c_int64),
-                ("E_hist", ctypes.c_double * MAXHIST), ("err_hist", ctypes.c_double * MAXHIST)]
+                ("E_hist", ctypes.c_double * MAXHIST), ("err_hist", ctypes.c_double * MAXHIST),
+                ("prec_hist", ctypes.c_int8 * MAXHIST)]
 
 
 _vp, _i, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
@@ -281,7 +284,10 @@ def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, **opts):
     if code not in (OK, ENOCONV):
         _check(code)
     info = {k: getattr(inf, k) for k, _ in ScfInfo._fields_ if not k.endswith("_hist")}
+    for k in ("t_kx_p", "t_ksyrk_p", "n_jk_p", "n_kx_launch_p"):
+        info[k] = list(getattr(inf, k))
     info["E_hist"] = list(inf.E_hist)[: inf.niter]
     info["err_hist"] = list(inf.err_hist)[: inf.niter]
+    info["prec_hist"] = list(inf.prec_hist)[: inf.niter]
     info["status"] = code
     return E.value, C, eps, info

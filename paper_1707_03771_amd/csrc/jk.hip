@@ -251,13 +251,17 @@ static KPlan k_plan(const JKArgs& a, int nocc) {
 }
 
 size_t k_work_bytes(const JKArgs& a, int nocc) {
+  if (a.prec != PREC_FP64) return k_work_bytes_mixed(a, nocc);
   const KPlan p = k_plan(a, nocc);
   return (p.x_elems + p.p_elems) * sizeof(double) + 256;
 }
 
 void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st,
              KTimer* timer) {
-  if (a.prec != PREC_FP64) throw Error(-6, "k_build: precision not available yet");
+  if (a.prec != PREC_FP64) {
+    k_build_mixed(a, C, nocc, K, work, st, timer);
+    return;
+  }
   const KPlan p = k_plan(a, nocc);
   double* X = reinterpret_cast<double*>(work);
   double* P = X + p.x_elems;

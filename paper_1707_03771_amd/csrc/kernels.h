@@ -81,6 +81,10 @@ struct KTimer {
 };
 void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st,
              KTimer* timer = nullptr);
+// reduced-precision K (jk_mixed.hip), dispatched by k_build for PREC_FP32 / PREC_BF16
+size_t k_work_bytes_mixed(const JKArgs& a, int nocc);
+void k_build_mixed(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st,
+                   KTimer* timer);
 // canonical packed rows [q1 - q0][ncols_p] (FP64) from the tiled storage;
 // toff[c] is the tile offset of packed column c
 void export_rows(const float* hi, const float* lo, const double* raw, int64_t ncols_t, int q0, int q1,

@@ -11,6 +11,7 @@
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -346,8 +347,9 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     const auto t1c = clk::now();
 
     // ---- iterations
-    EventSpans sp_j, sp_kx, sp_ks;
-    sp_j.st = sp_kx.st = sp_ks.st = st;
+    EventSpans sp_j, sp_kx[3], sp_ks[3];
+    sp_j.st = st;
+    for (int k = 0; k < 3; ++k) sp_kx[k].st = sp_ks[k].st = st;
     struct Timer : KTimer {
       EventSpans *x, *s;
       void begin_x() override { x->begin(); }
@@ -355,11 +357,26 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
       void begin_syrk() override { s->begin(); }
       void end_syrk() override { s->end(); }
     } ktimer;
-    ktimer.x = &sp_kx;
-    ktimer.s = &sp_ks;
+    int n_jk_p[3] = {0, 0, 0};
     JKArgs ja{B->hi.as<float>(), B->lo.as<float>(), B->naux, n, B->ncols_t, PREC_FP64};
     const bool mixed = (o.schedule == DFX_SCHED_MIXED);
-    int prec = mixed ? o.mixed_prec : DFX_FP64;
+    // precision stages: reduced precision first, FP64 last.  A stage ends when the
+    // DIIS error falls below its threshold or stops improving.
+    std::vector<int> stages;
+    std::vector<double> stage_thr;
+    if (mixed && o.mixed_prec == DFX_BF16) {
+      stages = {DFX_BF16, DFX_FP32, DFX_FP64};
+      stage_thr = {std::max(o.switch_err, 1e-2), o.switch_err, 0.0};
+    } else if (mixed) {
+      stages = {DFX_FP32, DFX_FP64};
+      stage_thr = {o.switch_err, 0.0};
+    } else {
+      stages = {DFX_FP64};
+      stage_thr = {0.0};
+    }
+    int stage = 0, stage_it = 0;
+    std::vector<double> stage_errs;
+    int prec = stages[0];
     int nfp64 = 0, it = 0, hcount = 0, hpos = 0, n_mixed = 0;
     double E = 0.0, Eold = 0.0, emax = 0.0;
     bool converged = false;
@@ -372,6 +389,9 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
       sp_j.begin();
       j_build(ja, D.as<double>(), Jm.as<double>(), reinterpret_cast<double*>(w), st);
       sp_j.end();
+      ktimer.x = &sp_kx[prec];
+      ktimer.s = &sp_ks[prec];
+      ++n_jk_p[prec];
       k_build(ja, Cocc.as<double>(), nocc, Km.as<double>(), w, st, &ktimer);
       hipLaunchKernelGGL(fock_kernel, dim3(nblk(n2)), dim3(256), 0, st, h.as<double>(), Jm.as<double>(),
                          Km.as<double>(), F.as<double>(), n2);
@@ -387,13 +407,18 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
       if (it <= DFX_MAXHIST) {
         inf.E_hist[it - 1] = E;
         inf.err_hist[it - 1] = emax;
+        inf.prec_hist[it - 1] = (int8_t)prec;
       }
       if (o.verbose)
         std::fprintf(stderr, "dfx_scf it %3d  %s  E = %.12f  dE = %.3e  err = %.3e\n", it,
                      prec == DFX_FP64 ? "fp64" : (prec == DFX_FP32 ? "fp32" : "bf16"), E, E - Eold, emax);
+      ++stage_it;
       if (prec == DFX_FP64) {
         ++nfp64;
-        const bool dE_ok = (mixed ? nfp64 >= 2 : it >= 2) && std::fabs(E - Eold) < o.conv_dE;
+        // after a reduced-precision stage the first FP64 build has no FP64 predecessor
+        // to difference against; its commutator with the exact Fock matrix decides
+        const bool dE_ok = mixed ? (nfp64 == 1 || std::fabs(E - Eold) < o.conv_dE)
+                                 : (it >= 2 && std::fabs(E - Eold) < o.conv_dE);
         if (dE_ok && emax < o.conv_err) {
           converged = true;
           break;
@@ -402,9 +427,23 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
         ++n_mixed;
       }
       Eold = E;
-      // switch to FP64: the DIIS history restarts with FP64 Fock matrices only
-      if (prec != DFX_FP64 && emax < o.switch_err) {
-        prec = DFX_FP64;
+      // next precision stage once the error is below the stage threshold, or the
+      // stage has stalled (no factor-2 gain of its best error over 8 iterations).
+      // The DIIS history restarts: Fock matrices of the coarser precision would pin
+      // the extrapolation at their own error level.
+      stage_errs.push_back(emax);
+      bool stalled = false;
+      constexpr int WIN = 8;
+      if (stage_it > WIN) {
+        const double recent = *std::min_element(stage_errs.end() - WIN, stage_errs.end());
+        const double before = *std::min_element(stage_errs.begin(), stage_errs.end() - WIN);
+        stalled = recent > 0.5 * before;
+      }
+      if (prec != DFX_FP64 && (emax < stage_thr[stage] || stalled)) {
+        ++stage;
+        prec = stages[stage];
+        stage_it = 0;
+        stage_errs.clear();
         hcount = 0;
         hpos = 0;
         diag(F.as<double>());
@@ -477,11 +516,19 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     inf.t_metric = B->info.metric_seconds;
     inf.t_trsm = B->info.trsm_seconds;
     inf.t_j = sp_j.seconds();
-    inf.t_kx = sp_kx.seconds();
-    inf.t_ksyrk = sp_ks.seconds();
+    inf.t_kx = inf.t_ksyrk = 0.0;
+    inf.n_kx_launch = 0;
+    for (int k = 0; k < 3; ++k) {
+      inf.t_kx_p[k] = sp_kx[k].seconds();
+      inf.t_ksyrk_p[k] = sp_ks[k].seconds();
+      inf.n_jk_p[k] = n_jk_p[k];
+      inf.n_kx_launch_p[k] = sp_kx[k].count();
+      inf.t_kx += inf.t_kx_p[k];
+      inf.t_ksyrk += inf.t_ksyrk_p[k];
+      inf.n_kx_launch += inf.n_kx_launch_p[k];
+    }
     inf.t_eig = S.eig_spans ? S.eig_spans->seconds() : 0.0;
     inf.n_jk = sp_j.count();
-    inf.n_kx_launch = sp_kx.count();
     inf.nintegrals = B->info.nintegrals;
     inf.ncols = B->info.ncols;
     if (info) *info = inf;

@@ -54,7 +54,7 @@ def test_not_converged_is_reported_with_outputs(dfx, h4_ref):
     assert np.isfinite(E) and np.abs(C).max() > 0
 
 
-@pytest.mark.parametrize("prec", ["FP32"])
+@pytest.mark.parametrize("prec", ["FP32", "BF16"])
 def test_mixed_schedule_recovers_fp64_energy(dfx, h4_ref, prec):
     xyz, Z, sh, ax, nocc, ref = h4_ref
     E, _, _, info = dfx.scf(xyz, Z, sh, ax, schedule=dfx.SCHED_MIXED, mixed_prec=getattr(dfx, prec),
