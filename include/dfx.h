@@ -186,6 +186,9 @@ int dfx_cholesky(double* dev_A, int n, double* dev_Linv, void* stream);
 #define DFX_GUESS_CORE 0
 #define DFX_GUESS_CINIT 1     /* start from C_init */
 #define DFX_GUESS_DENSITY 2   /* start from D_init (projected to its top nocc natural orbitals) */
+#define DFX_GUESS_LEARNED 3   /* Loewdin-basis density predicted by opts->model (see below) */
+
+typedef struct dfx_guess dfx_guess;  /* trained starting-guess model, see below */
 
 #define DFX_SCHED_FP64 0      /* every iteration in FP64 */
 #define DFX_SCHED_MIXED 1     /* FP32/BF16 K until switch_err, then FP64 */
@@ -202,6 +205,7 @@ typedef struct {
   int32_t mixed_prec;    /* DFX_FP32 or DFX_BF16 for the mixed phase */
   int32_t guess;         /* DFX_GUESS_* */
   int32_t verbose;
+  const dfx_guess* model;  /* DFX_GUESS_LEARNED: the model (not owned), else NULL */
 } dfx_scf_opts;
 
 #define DFX_MAXHIST 256
@@ -236,6 +240,10 @@ typedef struct {
   double E_hist[DFX_MAXHIST];
   double err_hist[DFX_MAXHIST];
   int8_t prec_hist[DFX_MAXHIST];  /* DFX_FP64 / DFX_FP32 / DFX_BF16 of each Fock build */
+  double t_guess;        /* seconds of wall time for the starting guess (inside t_setup) */
+  int32_t guess_fallback; /* DFX_GUESS_LEARNED: 0 used; 1 non-finite prediction, core guess
+                             used instead; 2 no convergence from it in max_iter, restarted
+                             from the core guess (niter and the histories count both passes) */
 } dfx_scf_info;
 
 void dfx_scf_default_opts(dfx_scf_opts* o);
@@ -250,6 +258,109 @@ void dfx_scf_default_opts(dfx_scf_opts* o);
 int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
             const dfx_scf_opts* opts, const double* init, double* E, double* C, double* eps,
             dfx_scf_info* info);
+
+/* ---- learned starting guess ---------------------------------------------------
+ * Replaces the core-Hamiltonian start of the SCF ("Standard algorithms") with a
+ * density predicted block by block: for every atom pair (a, b) closer than the
+ * pair cutoff rc, and for every atom (a, a), an FP32 multilayer perceptron of
+ * that pair's element types maps invariant descriptors of the local geometry
+ * to the block P_ab written in a local frame; the block is rotated to the
+ * laboratory frame with real-solid-harmonic rotation matrices.
+ *
+ * P is the density in the symmetrically orthogonalised (Loewdin) basis,
+ * P = S^1/2 D S^1/2 with D = C_occ C_occ^T (dfx_lowdin): its entries are
+ * bounded by one, and an error in P reaches the orthonormal-basis density of
+ * the SCF unamplified, whereas AO blocks of a nearly linearly dependent basis
+ * are large and cancel each other.  The SCF takes the top nocc eigenvectors of
+ * U^T P U, U the kept eigenvectors of S.
+ *
+ * Local frame of pair (a, b): z along a -> b; x from the nearest further
+ * neighbour of a at least 0.1 rad off the z axis, projected off z (else the
+ * laboratory axis least aligned with z); y = z x x.  Atom frame: z toward the
+ * nearest neighbour, x from the next as above.  Neighbours ranked by distance
+ * rounded to 1e-8 bohr, ties by index.
+ * Descriptors of a pair (a, b), Z_a >= Z_b:  one-hot(Z_a) [3], one-hot(Z_b) [3],
+ *   16 Gaussians of |r_ab| with centres evenly spaced on [0.5, rc] (width =
+ *   spacing), then for a and for b the environment
+ *   sum_k g_n(r) f_c(r) Y_lm(F r_ak / r)  over neighbours k within rc_env other
+ *   than the pair partner, per element channel H, C, O [3 x 8 x 9]: 8 Gaussians
+ *   on [0.5, rc_env], real spherical harmonics l <= 2, f_c(r) = (cos(pi r /
+ *   rc_env) + 1) / 2.  Pairs of equal elements are evaluated in both
+ *   orientations and averaged.
+ * Descriptors of an atom: one-hot(Z_a) [3], its environment [3 x 8 x 9].
+ * Network: widths (d_in, hidden x depth, block size), SiLU between layers,
+ *   inputs and targets standardised per component on the training set,
+ *   mean-squared-error loss, Adam (beta 0.9 / 0.999, eps 1e-8).
+ * All arrays host-side and row-major unless stated.  Not thread-safe per model.
+ */
+typedef struct {
+  int32_t nelem;          /* elements the model covers (H, C, O only) */
+  const int32_t* Z;       /* [nelem] */
+  const int32_t* nshell;  /* [nelem] shells per atom of that element */
+  const int32_t* shell_l; /* concatenated l of those shells, in basis order (l <= 3) */
+  double rc;              /* pair cutoff, bohr (<= 0: 8) */
+  double rc_env;          /* environment cutoff, bohr (<= 0: 6) */
+  int32_t hidden;         /* hidden width (<= 0: 256) */
+  int32_t depth;          /* hidden layers (<= 0: 3) */
+  uint64_t seed;          /* weight initialisation and minibatch order */
+} dfx_guess_spec;
+
+/*
+ * dfx_lowdin -- P = S^1/2 D S^1/2 for the orbital basis `shells` (S from the
+ * same kernels as dfx_int1e, S^1/2 from its eigendecomposition, negative
+ * eigenvalues clamped to zero).  D, P host [nbf][nbf].  Synchronous.
+ */
+int dfx_lowdin(const dfx_geom* geom, const dfx_shell* shells, int nsh, const double* D, double* P, void* stream);
+
+int dfx_guess_create(const dfx_guess_spec* spec, dfx_guess** out);
+int dfx_guess_free(dfx_guess* g);
+/* add the samples of one converged geometry: P host [nbf][nbf], its Loewdin-basis
+ * density (dfx_lowdin), basis ordered atom by atom with the shells of the spec;
+ * adding to a trained type: DFX_EINVAL */
+int dfx_guess_add(dfx_guess* g, const dfx_geom* geom, const double* P);
+/* train every pair type for `epochs` passes of minibatches of `batch` samples
+ * (a ragged last minibatch is skipped); loss_out [epochs] (may be NULL): mean
+ * standardised MSE per epoch over all types.  Synchronous, on the GPU. */
+int dfx_guess_train(dfx_guess* g, int epochs, int batch, double lr, double* loss_out);
+/* predicted Loewdin-basis density P host [nbf][nbf] (symmetric; zero beyond rc);
+ * DFX_EINVAL if a pair type is unknown or untrained */
+int dfx_guess_predict(const dfx_guess* g, const dfx_geom* geom, double* P);
+/* the stored training samples of one type: X [samples][d_in] descriptors,
+ * T [samples][d_out] local-frame blocks (either may be NULL) */
+int dfx_guess_samples(const dfx_guess* g, int type, double* X, double* T);
+/* number of pair types; desc (may be NULL) [ntypes][6] = is_atom, Z_a, Z_b,
+ * d_in, d_out, samples */
+int dfx_guess_info(const dfx_guess* g, int* ntypes, int32_t* desc);
+/* trained parameters of one type: theta (FP32, per layer W[out][in] then b),
+ * input mean/std [d_in], target mean/std [d_out]; any pointer may be NULL */
+int dfx_guess_export(const dfx_guess* g, int type, float* theta, double* fmean, double* fstd, double* tmean,
+                     double* tstd);
+/* set the parameters of one type (created if absent; is_atom: Z_a == Z_b, else
+ * Z_a >= Z_b), with the layout of dfx_guess_export; the type counts as trained */
+int dfx_guess_import(dfx_guess* g, int is_atom, int za, int zb, const float* theta, const double* fmean,
+                     const double* fstd, const double* tmean, const double* tstd);
+/* descriptors [d_in] and frame rows [3][3] of pair (a, b) (a == b: atom a), as used
+ * for training and prediction; nfeat receives d_in.  Any output may be NULL. */
+int dfx_guess_features(const dfx_guess* g, const dfx_geom* geom, int a, int b, double* feat, double* frame,
+                       int* nfeat);
+/* U [(2l+1)][(2l+1)] with Y_m(F^T u) = sum_m' U[m][m'] Y_m'(u), F [3][3] orthogonal */
+int dfx_sh_rotation(int l, const double* F, double* U);
+int dfx_guess_save(const dfx_guess* g, const char* path);
+int dfx_guess_load(const char* path, dfx_guess** out);
+
+/* ---- the network kernels (FP32, device arrays, on `stream`) ------------------
+ * widths [nlayers + 1]; theta as in dfx_guess_export; X [batch][widths[0]];
+ * Y, T [batch][widths[nlayers]].
+ * dfx_mlp_forward: Y = network(X); synchronises the stream.
+ * dfx_mlp_loss_grad: grad [nparams] = d/dtheta of mean((Y - T)^2); *loss the
+ *   mean (accumulated in FP64); synchronises the stream.
+ * dfx_mlp_adam: one Adam step (beta 0.9 / 0.999, eps 1e-8) of theta, with
+ *   moment buffers m, v [n] (zero before step 1). */
+int dfx_mlp_forward(const int32_t* widths, int nlayers, const float* theta, const float* X, int batch, float* Y,
+                    void* stream);
+int dfx_mlp_loss_grad(const int32_t* widths, int nlayers, const float* theta, const float* X, const float* T,
+                      int batch, float* grad, double* loss, void* stream);
+int dfx_mlp_adam(float* theta, const float* grad, float* m, float* v, int64_t n, int step, float lr, void* stream);
 
 const char* dfx_last_error(void);
 

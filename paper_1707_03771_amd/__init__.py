@@ -26,7 +26,7 @@ FP64, FP32, BF16 = 0, 1, 2
 DENSITY, COCC = 0, 1
 KEEP_RAW, KEEP_METRIC = 1, 2
 EXPORT_B, EXPORT_BHI, EXPORT_RAW = 0, 1, 2
-GUESS_CORE, GUESS_CINIT, GUESS_DENSITY = 0, 1, 2
+GUESS_CORE, GUESS_CINIT, GUESS_DENSITY, GUESS_LEARNED = 0, 1, 2, 3
 SCHED_FP64, SCHED_MIXED = 0, 1
 MAXHIST = 256
 
@@ -64,7 +64,8 @@ class ScfOpts(ctypes.Structure):
     _fields_ = [("tau", ctypes.c_double), ("conv_dE", ctypes.c_double), ("conv_err", ctypes.c_double),
                 ("ortho_thresh", ctypes.c_double), ("switch_err", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("diis_size", ctypes.c_int32), ("schedule", ctypes.c_int32),
-                ("mixed_prec", ctypes.c_int32), ("guess", ctypes.c_int32), ("verbose", ctypes.c_int32)]
+                ("mixed_prec", ctypes.c_int32), ("guess", ctypes.c_int32), ("verbose", ctypes.c_int32),
+                ("model", ctypes.c_void_p)]
 
 
 class ScfInfo(ctypes.Structure):
@@ -79,7 +80,15 @@ class ScfInfo(ctypes.Structure):
                 ("n_jk_p", ctypes.c_int32 * 3), ("n_kx_launch_p", ctypes.c_int32 * 3),
                 ("nintegrals", ctypes.c_int64), ("ncols", ctypes.c_int64),
                 ("E_hist", ctypes.c_double * MAXHIST), ("err_hist", ctypes.c_double * MAXHIST),
-                ("prec_hist", ctypes.c_int8 * MAXHIST)]
+                ("prec_hist", ctypes.c_int8 * MAXHIST), ("t_guess", ctypes.c_double),
+                ("guess_fallback", ctypes.c_int32)]
+
+
+class GuessSpec(ctypes.Structure):
+    _fields_ = [("nelem", ctypes.c_int32), ("Z", ctypes.c_void_p), ("nshell", ctypes.c_void_p),
+                ("shell_l", ctypes.c_void_p), ("rc", ctypes.c_double), ("rc_env", ctypes.c_double),
+                ("hidden", ctypes.c_int32),
+                ("depth", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 _vp, _i, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
@@ -96,6 +105,23 @@ _SIGS = {
     "dfx_scf_default_opts": [_vp],
     "dfx_metric": [_vp, _i, _vp, _vp],
     "dfx_cholesky": [_vp, _i, _vp, _vp],
+    "dfx_guess_create": [_vp, _vp],
+    "dfx_guess_free": [_vp],
+    "dfx_guess_add": [_vp, _vp, _vp],
+    "dfx_guess_train": [_vp, _i, _i, _d, _vp],
+    "dfx_guess_predict": [_vp, _vp, _vp],
+    "dfx_guess_info": [_vp, _vp, _vp],
+    "dfx_guess_export": [_vp, _i, _vp, _vp, _vp, _vp, _vp],
+    "dfx_lowdin": [_vp, _vp, _i, _vp, _vp, _vp],
+    "dfx_guess_samples": [_vp, _i, _vp, _vp],
+    "dfx_guess_import": [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp],
+    "dfx_guess_features": [_vp, _vp, _i, _i, _vp, _vp, _vp],
+    "dfx_sh_rotation": [_i, _vp, _vp],
+    "dfx_guess_save": [_vp, ctypes.c_char_p],
+    "dfx_guess_load": [ctypes.c_char_p, _vp],
+    "dfx_mlp_forward": [_vp, _i, _vp, _vp, _i, _vp, _vp],
+    "dfx_mlp_loss_grad": [_vp, _i, _vp, _vp, _vp, _i, _vp, _vp, _vp],
+    "dfx_mlp_adam": [_vp, _vp, _vp, _vp, ctypes.c_int64, _i, ctypes.c_float, _vp],
 }
 for _name, _args in _SIGS.items():
     _f = getattr(_lib, _name, None)
@@ -260,13 +286,17 @@ def scf_default_opts():
     return o
 
 
-def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, **opts):
-    """dfx_scf: DF-RHF.  Returns (E, C, eps, info dict); C and eps are numpy arrays."""
+def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, model=None, **opts):
+    """dfx_scf: DF-RHF.  Returns (E, C, eps, info dict); C and eps are numpy arrays.
+    With a GuessModel, the start is its predicted density (guess = GUESS_LEARNED)."""
     o = scf_default_opts()
     for k, v in opts.items():
-        if not hasattr(o, k):
+        if not hasattr(o, k) or k == "model":
             raise TypeError(f"unknown SCF option {k!r}")
         setattr(o, k, v)
+    if model is not None:
+        o.model = model.h.value
+        o.guess = GUESS_LEARNED
     s, a = _ShellArray(shells), _ShellArray(aux)
     g = _GeomC(xyz, Z, charge)
     n = sum(2 * int(q["l"]) + 1 for q in shells)
@@ -291,3 +321,149 @@ def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, **opts):
     info["prec_hist"] = list(inf.prec_hist)[: inf.niter]
     info["status"] = code
     return E.value, C, eps, info
+
+
+# ---- learned starting guess ------------------------------------------------------
+
+class GuessModel:
+    """Owns a dfx_guess handle: per-pair-type MLPs predicting blocks of the
+    Loewdin-basis density P = S^1/2 D S^1/2 (see lowdin()).
+
+    basis: {Z: [l of each shell of that element, in basis order]}."""
+
+    def __init__(self, basis=None, rc=8.0, rc_env=6.0, hidden=256, depth=3, seed=0, _handle=None):
+        self.h = ctypes.c_void_p()
+        if _handle is not None:
+            self.h = _handle
+            return
+        Zs = sorted(basis)
+        Za = np.array(Zs, np.int32)
+        ns = np.array([len(basis[z]) for z in Zs], np.int32)
+        ls = np.array([l for z in Zs for l in basis[z]], np.int32)
+        spec = GuessSpec(len(Zs), Za.ctypes.data, ns.ctypes.data, ls.ctypes.data, rc, rc_env, hidden, depth, seed)
+        _check(_lib.dfx_guess_create(ctypes.byref(spec), ctypes.byref(self.h)))
+
+    @classmethod
+    def load(cls, path):
+        h = ctypes.c_void_p()
+        _check(_lib.dfx_guess_load(os.fsencode(path), ctypes.byref(h)))
+        return cls(_handle=h)
+
+    def save(self, path):
+        _check(_lib.dfx_guess_save(self.h, os.fsencode(path)))
+
+    def add(self, xyz, Z, P):
+        """Samples of one geometry from its Loewdin-basis density P."""
+        g = _GeomC(xyz, Z)
+        P = np.ascontiguousarray(P, dtype=np.float64)
+        _check(_lib.dfx_guess_add(self.h, ctypes.byref(g.g), P.ctypes.data))
+
+    def samples(self, t):
+        ty = self.types()[t]
+        X = np.zeros((ty["samples"], ty["d_in"]))
+        T = np.zeros((ty["samples"], ty["d_out"]))
+        _check(_lib.dfx_guess_samples(self.h, t, X.ctypes.data, T.ctypes.data))
+        return X, T
+
+    def train(self, epochs, batch=256, lr=1e-3):
+        loss = np.zeros(max(1, epochs))
+        _check(_lib.dfx_guess_train(self.h, epochs, batch, lr, loss.ctypes.data))
+        return loss[:epochs]
+
+    def predict(self, xyz, Z, nbf):
+        g = _GeomC(xyz, Z)
+        D = np.zeros((nbf, nbf))
+        _check(_lib.dfx_guess_predict(self.h, ctypes.byref(g.g), D.ctypes.data))
+        return D
+
+    def types(self):
+        n = ctypes.c_int()
+        _check(_lib.dfx_guess_info(self.h, ctypes.byref(n), None))
+        desc = np.zeros((max(1, n.value), 6), np.int32)
+        _check(_lib.dfx_guess_info(self.h, ctypes.byref(n), desc.ctypes.data))
+        return [dict(atom=bool(d[0]), Za=int(d[1]), Zb=int(d[2]), d_in=int(d[3]), d_out=int(d[4]),
+                     samples=int(d[5])) for d in desc[: n.value]]
+
+    def export(self, t, widths):
+        ty = self.types()[t]
+        npar = sum(widths[i] * widths[i + 1] + widths[i + 1] for i in range(len(widths) - 1))
+        th = np.zeros(npar, np.float32)
+        fm, fs = np.zeros(ty["d_in"]), np.zeros(ty["d_in"])
+        tm, ts = np.zeros(ty["d_out"]), np.zeros(ty["d_out"])
+        _check(_lib.dfx_guess_export(self.h, t, th.ctypes.data, fm.ctypes.data, fs.ctypes.data,
+                                     tm.ctypes.data, ts.ctypes.data))
+        return th, fm, fs, tm, ts
+
+    def import_type(self, is_atom, za, zb, theta, fmean, fstd, tmean, tstd):
+        th = np.ascontiguousarray(theta, dtype=np.float32)
+        arrs = [np.ascontiguousarray(x, dtype=np.float64) for x in (fmean, fstd, tmean, tstd)]
+        _check(_lib.dfx_guess_import(self.h, int(is_atom), int(za), int(zb), th.ctypes.data,
+                                     *[x.ctypes.data for x in arrs]))
+
+    def features(self, xyz, Z, a, b):
+        g = _GeomC(xyz, Z)
+        nf = ctypes.c_int()
+        _check(_lib.dfx_guess_features(self.h, ctypes.byref(g.g), a, b, None, None, ctypes.byref(nf)))
+        f, F = np.zeros(nf.value), np.zeros((3, 3))
+        _check(_lib.dfx_guess_features(self.h, ctypes.byref(g.g), a, b, f.ctypes.data, F.ctypes.data, None))
+        return f, F
+
+    def free(self):
+        if self.h:
+            _check(_lib.dfx_guess_free(self.h))
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def lowdin(xyz, Z, shells, D, stream=None):
+    """dfx_lowdin: P = S^1/2 D S^1/2 (host numpy arrays in and out)."""
+    s = _ShellArray(shells)
+    g = _GeomC(xyz, Z)
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    P = np.zeros_like(D)
+    _check(_lib.dfx_lowdin(ctypes.byref(g.g), s.arr, s.n, D.ctypes.data, P.ctypes.data, _stream(stream)))
+    return P
+
+
+def sh_rotation(l, F):
+    """dfx_sh_rotation: U with Y_m(F^T u) = sum_m' U[m, m'] Y_m'(u)."""
+    F = np.ascontiguousarray(F, dtype=np.float64)
+    U = np.zeros((2 * l + 1, 2 * l + 1))
+    _check(_lib.dfx_sh_rotation(l, F.ctypes.data, U.ctypes.data))
+    return U
+
+
+def _widths(widths):
+    return np.ascontiguousarray(widths, dtype=np.int32)
+
+
+def mlp_forward(widths, theta, X, stream=None):
+    """dfx_mlp_forward on float32 cuda tensors; returns Y (batch, widths[-1])."""
+    import torch
+    w = _widths(widths)
+    Y = torch.empty((X.shape[0], int(w[-1])), dtype=torch.float32, device=X.device)
+    _check(_lib.dfx_mlp_forward(w.ctypes.data, len(w) - 1, _ptr(theta), _ptr(X.contiguous()), X.shape[0],
+                                _ptr(Y), _stream(stream)))
+    return Y
+
+
+def mlp_loss_grad(widths, theta, X, T, stream=None):
+    """dfx_mlp_loss_grad: (mean squared error, gradient in theta as a float32 cuda tensor)."""
+    import torch
+    w = _widths(widths)
+    g = torch.empty_like(theta)
+    loss = ctypes.c_double()
+    _check(_lib.dfx_mlp_loss_grad(w.ctypes.data, len(w) - 1, _ptr(theta), _ptr(X.contiguous()),
+                                  _ptr(T.contiguous()), X.shape[0], _ptr(g), ctypes.byref(loss), _stream(stream)))
+    return loss.value, g
+
+
+def mlp_adam(theta, grad, m, v, step, lr=1e-3, stream=None):
+    """dfx_mlp_adam: one in-place Adam step of theta (m, v updated in place)."""
+    _check(_lib.dfx_mlp_adam(_ptr(theta), _ptr(grad), _ptr(m), _ptr(v), theta.numel(), step, lr,
+                             _stream(stream)))

@@ -55,6 +55,11 @@ struct DevShellSet {
 
 const double* rys_table_device();  // per current device, built on first use
 
+// learned starting guess (guess.cpp): predicted density, host [nbf][nbf]
+void guess_predict_density(const dfx_guess* g, const dfx_geom* geom, double* D, hipStream_t st);
+// throws unless the orbital shells are listed atom by atom with the model's shells per element
+void guess_check_basis(const dfx_guess* g, const dfx_geom* geom, const dfx_shell* shells, int nsh);
+
 // ---- timing ---------------------------------------------------------------------
 struct GpuTimer {
   hipEvent_t a{}, b{};

@@ -91,6 +91,21 @@ __global__ void build_x_kernel(const double* W, const double* s, int n, int ndro
   X[i] = W[(int64_t)(ndrop + k) * n + mu] / sqrt(s[ndrop + k]);
 }
 
+// U[mu][k] = W[ndrop + k][mu]: the kept eigenvectors of S as columns
+__global__ void build_u_kernel(const double* W, int n, int ndrop, int m, double* U) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * m) return;
+  const int mu = (int)(i / m), k = (int)(i % m);
+  U[i] = W[(int64_t)(ndrop + k) * n + mu];
+}
+
+// T[k][mu] = sqrt(max(s_k, 0)) W[k][mu]
+__global__ void scale_rows_sqrt_kernel(const double* W, const double* s, int n, double* T) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * n) return;
+  T[i] = W[i] * sqrt(fmax(s[i / n], 0.0));
+}
+
 __global__ void copy_cols_kernel(const double* A, int lda, int rows, int cols, double* B, int ldb) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)rows * cols) return;
@@ -234,6 +249,10 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     if (o.diis_size < 1 || o.diis_size > 16 || o.max_iter < 1) throw Error(DFX_EINVAL, "dfx_scf: bad options");
     if ((o.guess == DFX_GUESS_CINIT || o.guess == DFX_GUESS_DENSITY) && !init)
       throw Error(DFX_EINVAL, "dfx_scf: guess needs init");
+    if (o.guess == DFX_GUESS_LEARNED) {
+      if (!o.model) throw Error(DFX_EINVAL, "dfx_scf: learned guess needs a model");
+      guess_check_basis(o.model, geom, shells, nsh);
+    }
     int nelec = -geom->charge;
     for (int a = 0; a < geom->natom; ++a) nelec += geom->Z[a];
     if (nelec <= 0 || nelec % 2) throw Error(DFX_EINVAL, "dfx_scf: closed shell needs an even, positive electron count");
@@ -295,6 +314,12 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     DevMem X(8 * (size_t)n * m);
     hipLaunchKernelGGL(build_x_kernel, dim3(nblk((int64_t)n * m)), dim3(256), 0, st, W.as<double>(),
                        sv.as<double>(), n, ndrop, m, X.as<double>());
+    DevMem Uk;
+    if (o.guess == DFX_GUESS_LEARNED) {
+      Uk.alloc(8 * (size_t)n * m);
+      hipLaunchKernelGGL(build_u_kernel, dim3(nblk((int64_t)n * m)), dim3(256), 0, st, W.as<double>(), n, ndrop,
+                         m, Uk.as<double>());
+    }
     W.release();
 
     DevMem F(8 * n2), D(8 * n2), Jm(8 * n2), Km(8 * n2), t1(8 * n2), t2(8 * n2);
@@ -318,7 +343,19 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     };
 
     // ---- guess
-    if (o.guess == DFX_GUESS_CORE) {
+    const auto tg0 = clk::now();
+    int fallback = 0;  // 1: non-finite learned prediction, 2: learned start did not converge
+    std::vector<double> Dl;
+    if (o.guess == DFX_GUESS_LEARNED) {
+      Dl.resize(n2);
+      guess_predict_density(o.model, geom, Dl.data(), st);
+      for (double x : Dl)
+        if (!std::isfinite(x)) {
+          fallback = 1;
+          break;
+        }
+    }
+    if (o.guess == DFX_GUESS_CORE || fallback) {
       diag(h.as<double>());
     } else if (o.guess == DFX_GUESS_CINIT) {
       DevMem Ci(8 * n2);
@@ -326,14 +363,21 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
       hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc)), dim3(256), 0, st, Ci.as<double>(), n, n,
                          nocc, Cocc.as<double>(), nocc);
       S.gemm(n, n, nocc, Cocc.as<double>(), nocc, false, Cocc.as<double>(), nocc, true, D.as<double>(), n);
-    } else if (o.guess == DFX_GUESS_DENSITY) {
-      // orthonormal-basis density X^T S D S X; its top nocc eigenvectors give C_occ
+    } else if (o.guess == DFX_GUESS_DENSITY || o.guess == DFX_GUESS_LEARNED) {
+      // the density in the orthonormal basis of X; its top nocc eigenvectors give C_occ
       DevMem Di(8 * n2);
-      DFX_HIP(hipMemcpyAsync(Di.p, init, 8 * n2, hipMemcpyHostToDevice, st));
-      S.gemm(n, n, n, Sm.as<double>(), n, false, Di.as<double>(), n, false, t1.as<double>(), n);     // S D
-      S.gemm(n, n, n, t1.as<double>(), n, false, Sm.as<double>(), n, false, t2.as<double>(), n);     // S D S
-      S.gemm(m, n, n, X.as<double>(), m, true, t2.as<double>(), n, false, t1.as<double>(), n);       // X^T SDS
-      S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Fp.as<double>(), m);
+      DFX_HIP(hipMemcpyAsync(Di.p, Dl.empty() ? init : Dl.data(), 8 * n2, hipMemcpyHostToDevice, st));
+      if (o.guess == DFX_GUESS_DENSITY) {
+        // AO density: X^T S D S X
+        S.gemm(n, n, n, Sm.as<double>(), n, false, Di.as<double>(), n, false, t1.as<double>(), n);   // S D
+        S.gemm(n, n, n, t1.as<double>(), n, false, Sm.as<double>(), n, false, t2.as<double>(), n);   // S D S
+        S.gemm(m, n, n, X.as<double>(), m, true, t2.as<double>(), n, false, t1.as<double>(), n);     // X^T SDS
+        S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Fp.as<double>(), m);
+      } else {
+        // Loewdin density P = S^1/2 D S^1/2: X^T S D S X = U^T P U with X^T S^1/2 = U^T
+        S.gemm(m, n, n, Uk.as<double>(), m, true, Di.as<double>(), n, false, t1.as<double>(), n);    // U^T P
+        S.gemm(m, m, n, t1.as<double>(), n, false, Uk.as<double>(), m, false, Fp.as<double>(), m);
+      }
       S.syevd(Fp.as<double>(), m, eps.as<double>());
       // eigenvectors of the largest nocc eigenvalues are the last nocc rows
       S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm.as<double>(), m);
@@ -343,8 +387,10 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     } else {
       throw Error(DFX_EINVAL, "dfx_scf: unknown guess");
     }
+    Uk.release();
     DFX_HIP(hipStreamSynchronize(st));
     const auto t1c = clk::now();
+    const double t_guess = std::chrono::duration<double>(t1c - tg0).count();
 
     // ---- iterations
     EventSpans sp_j, sp_kx[3], sp_ks[3];
@@ -360,6 +406,11 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     int n_jk_p[3] = {0, 0, 0};
     JKArgs ja{B->hi.as<float>(), B->lo.as<float>(), B->naux, n, B->ncols_t, PREC_FP64};
     const bool mixed = (o.schedule == DFX_SCHED_MIXED);
+    int nfp64 = 0, it = 0, n_mixed = 0, it_done = 0;
+    double E = 0.0, Eold = 0.0, emax = 0.0;
+    bool converged = false;
+    dfx_scf_info inf{};
+    for (int pass = 0; pass < 2; ++pass) {
     // precision stages: reduced precision first, FP64 last.  A stage ends when the
     // DIIS error falls below its threshold or stops improving.
     std::vector<int> stages;
@@ -377,12 +428,11 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     int stage = 0, stage_it = 0;
     std::vector<double> stage_errs;
     int prec = stages[0];
-    int nfp64 = 0, it = 0, hcount = 0, hpos = 0, n_mixed = 0;
-    double E = 0.0, Eold = 0.0, emax = 0.0;
-    bool converged = false;
+    int hcount = 0, hpos = 0;
+    nfp64 = 0;
     std::vector<double> Bdiis((size_t)dsz * dsz, 0.0);
-    dfx_scf_info inf{};
     for (it = 1; it <= o.max_iter; ++it) {
+      const int ih = it_done + it;  // iteration number over both passes
       ja.prec = prec;
       const size_t need = std::max(sizeof(double) * (2 * (size_t)B->ncols_t + B->naux + 8), k_work_bytes(ja, nocc));
       void* w = B->ensure_work(need);
@@ -404,13 +454,13 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
       double* e_new = Eh[hpos].as<double>();
       S.gemm(m, m, n, t2.as<double>(), n, false, X.as<double>(), m, false, e_new, m);
       emax = S.reduce_max(e_new, (int64_t)m * m);
-      if (it <= DFX_MAXHIST) {
-        inf.E_hist[it - 1] = E;
-        inf.err_hist[it - 1] = emax;
-        inf.prec_hist[it - 1] = (int8_t)prec;
+      if (ih <= DFX_MAXHIST) {
+        inf.E_hist[ih - 1] = E;
+        inf.err_hist[ih - 1] = emax;
+        inf.prec_hist[ih - 1] = (int8_t)prec;
       }
       if (o.verbose)
-        std::fprintf(stderr, "dfx_scf it %3d  %s  E = %.12f  dE = %.3e  err = %.3e\n", it,
+        std::fprintf(stderr, "dfx_scf it %3d  %s  E = %.12f  dE = %.3e  err = %.3e\n", ih,
                      prec == DFX_FP64 ? "fp64" : (prec == DFX_FP32 ? "fp32" : "bf16"), E, E - Eold, emax);
       ++stage_it;
       if (prec == DFX_FP64) {
@@ -483,6 +533,13 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
       hpos = (hpos + 1) % dsz;
       diag(Fuse);
     }
+    it_done += std::min(it, o.max_iter);
+    // a learned start that does not converge is retried once from the core guess
+    if (converged || o.guess != DFX_GUESS_LEARNED || fallback) break;
+    fallback = 2;
+    Eold = 0.0;
+    diag(h.as<double>());
+    }
     DFX_HIP(hipStreamSynchronize(st));
     const auto t2c = clk::now();
 
@@ -500,7 +557,8 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
       DFX_HIP(hipMemcpy(e.data(), eps.p, 8 * (size_t)m, hipMemcpyDeviceToHost));
       for (int i = 0; i < n; ++i) eps_out[i] = i < m ? e[i] : 0.0;
     }
-    inf.niter = std::min(it, o.max_iter);
+    inf.niter = it_done;
+    inf.guess_fallback = fallback;
     inf.converged = converged ? 1 : 0;
     inf.n_mixed = n_mixed;
     inf.ndropped = ndrop;
@@ -510,6 +568,7 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     inf.E_nuc = Enuc;
     inf.err_max = emax;
     inf.t_setup = std::chrono::duration<double>(t1c - t0).count();
+    inf.t_guess = t_guess;
     inf.t_scf = std::chrono::duration<double>(t2c - t1c).count();
     inf.t_total = std::chrono::duration<double>(clk::now() - t0).count();
     inf.t_eri = B->info.eri_seconds;
@@ -538,6 +597,38 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     }
   });
   return rc != DFX_OK ? rc : status;
+}
+
+int dfx_lowdin(const dfx_geom* geom, const dfx_shell* shells, int nsh, const double* D, double* P, void* stream) {
+  return guard([&] {
+    if (!geom || !shells || !D || !P) throw Error(DFX_EINVAL, "dfx_lowdin: NULL argument");
+    HostShells hb = make_shells(shells, nsh, 3, "orbital basis");
+    const int n = hb.nbf;
+    const int64_t n2 = (int64_t)n * n;
+    Scf S;
+    S.st = (hipStream_t)stream;
+    struct Cleanup {
+      Scf& s;
+      ~Cleanup() {
+        if (s.rb) rocblas_destroy_handle(s.rb);
+      }
+    } cleanup{S};
+    if (rocblas_create_handle(&S.rb) != rocblas_status_success) throw Error(DFX_EHIP, "rocblas_create_handle failed");
+    rocblas_set_stream(S.rb, S.st);
+    S.eig_info.alloc(sizeof(int));
+    hipStream_t st = S.st;
+    DevMem W(8 * n2), Tm(8 * n2), Vm(8 * n2), sv(8 * (size_t)n);
+    int1e_build(hb, geom, W.as<double>(), Tm.as<double>(), Vm.as<double>(), st);
+    S.syevd(W.as<double>(), n, sv.as<double>());                         // rows of W: eigenvectors
+    hipLaunchKernelGGL(scale_rows_sqrt_kernel, dim3(nblk(n2)), dim3(256), 0, st, W.as<double>(), sv.as<double>(), n,
+                       Tm.as<double>());
+    S.gemm(n, n, n, W.as<double>(), n, true, Tm.as<double>(), n, false, Vm.as<double>(), n);  // S^1/2
+    DFX_HIP(hipMemcpyAsync(W.p, D, 8 * n2, hipMemcpyHostToDevice, st));
+    S.gemm(n, n, n, Vm.as<double>(), n, false, W.as<double>(), n, false, Tm.as<double>(), n);  // S^1/2 D
+    S.gemm(n, n, n, Tm.as<double>(), n, false, Vm.as<double>(), n, false, W.as<double>(), n);  // ... S^1/2
+    DFX_HIP(hipMemcpyAsync(P, W.p, 8 * n2, hipMemcpyDeviceToHost, st));
+    DFX_HIP(hipStreamSynchronize(st));
+  });
 }
 
 }  // extern "C"
