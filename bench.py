@@ -3,11 +3,17 @@
 
 One step = one complete DF-RHF (dfx_scf through the C-ABI): Schwarz screening,
 Rys three-index integrals, metric, Cholesky, B = L^-1 (mu nu|P), one-electron
-integrals, guess and every SCF iteration, on the (H2O)64 workload (seeded
-water cluster, even-tempered O [3s2p1d] / H [2s1p], auxiliary O [8s6p4d2f] /
+integrals, the learned starting guess (descriptors, MLP inference, rotation,
+projection) and every SCF iteration, on the (H2O)64 workload (seeded water
+cluster, even-tempered O [3s2p1d] / H [2s1p], auxiliary O [8s6p4d2f] /
 H [4s3p2d]; 1536 basis / 6784 auxiliary functions).  Prints ONE JSON line.
 
+Before the timed steps (untimed, reported): the guess model is trained on the
+GPU from converged densities of seeded 3x3x3 and 2x2x2 water clusters; a
+core-guess run and a plain FP64 run of the same workload are timed for context.
+
     python bench.py [--steps K] [--warmup W] [--workload water4] [--schedule fp64|mixed]
+                    [--guess learned|core] [--trajectory]
 """
 from __future__ import annotations
 
@@ -128,6 +134,35 @@ def cpu_baseline(elems, xyz, sh, ax, niter, budget_pairs=250, q_rows=16, seed=0)
             "phases_s": {k: round(v, 3) for k, v in t_all.items()}}
 
 
+def train_guess(dfx, n27=8, n8=16, epochs=80, batch=128, seed=5):
+    """Guess model for water from converged GPU densities of seeded clusters:
+    3x3x3 clusters hold every coordination a water has in the 4x4x4 cluster
+    (corner to fully surrounded), 2x2x2 clusters add surface environments."""
+    basis = {8: [0, 0, 0, 1, 1, 2], 1: [0, 0, 1]}
+    m = dfx.GuessModel(basis, rc=8.0, rc_env=6.0, hidden=256, depth=3, seed=seed)
+    t0 = time.perf_counter()
+    ngeom = 0
+    for side, seeds in ((3, range(1, 1 + n27)), (2, range(1, 1 + n8))):
+        for sd in seeds:
+            elems, xyz = W.water_cluster(side=side, seed=1000 + sd)
+            sh, ax = W.basis_for("water", elems, xyz)
+            Z = W.charges(elems)
+            E, C, _, info = dfx.scf(xyz, Z, sh, ax, schedule=dfx.SCHED_MIXED, conv_dE=1e-8, conv_err=1e-6)
+            nocc = info["nocc"]
+            m.add(xyz, Z, dfx.lowdin(xyz, Z, sh, C[:, :nocc] @ C[:, :nocc].T))
+            ngeom += 1
+        log(f"guess training data: {ngeom} geometries, {time.perf_counter() - t0:.1f} s")
+    t_data = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    loss = m.train(epochs=epochs, batch=batch, lr=1e-3)
+    t_train = time.perf_counter() - t1
+    log(f"guess training: {epochs} epochs in {t_train:.1f} s, loss {loss[0]:.3f} -> {loss[-1]:.4f}")
+    return m, {"geometries": f"{n27} x (H2O)27 + {n8} x (H2O)8, seeds 1001..", "data_s": round(t_data, 2),
+               "train_s": round(t_train, 2), "epochs": epochs, "batch": batch,
+               "samples": sum(t["samples"] for t in m.types()), "loss_first": round(float(loss[0]), 4),
+               "loss_last": round(float(loss[-1]), 4)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,7 +171,11 @@ def main():
     ap.add_argument("--workload", default="water4")
     ap.add_argument("--schedule", default="mixed", choices=["fp64", "mixed"])
     ap.add_argument("--mixed-prec", default="fp32", choices=["fp32", "bf16"])
+    ap.add_argument("--guess", default="learned", choices=["learned", "core"])
+    ap.add_argument("--trajectory", action="store_true",
+                    help="step k runs frame k of a seeded trajectory (per-atom sigma 0.02 bohr)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 reference run")
+    ap.add_argument("--no-context", action="store_true", help="skip the core-guess context run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -158,33 +197,48 @@ def main():
     opts = dict(conv_dE=1e-8, conv_err=1e-6, schedule=sched, mixed_prec=mp, max_iter=100)
     log(f"workload {a.workload}: {len(elems)} atoms, nbf {nbf}, naux {naux}, nocc {nocc}")
 
-    def step(tag):
+    model, learned = (None, None)
+    if a.guess == "learned":
+        model, learned = train_guess(dfx)
+    frames = W.trajectory(xyz, a.steps + a.warmup, seed=1) if a.trajectory else None
+
+    def step(tag, k=None, **kw):
+        x = xyz if frames is None or k is None else frames[k]
+        shx, axx = (sh, ax) if x is xyz else (W.shells_at(sh, xyz, x), W.shells_at(ax, xyz, x))
+        o = dict(opts, **kw)
         t0 = time.perf_counter()
-        E, _, _, info = dfx.scf(xyz, Z, sh, ax, want_c=False, **opts)
+        E, _, _, info = dfx.scf(x, Z, shx, axx, want_c=False, **o)
         dt = time.perf_counter() - t0
         log(f"{tag}: E = {E:.10f}  iters {info['niter']} (mixed {info['n_mixed']})  "
-            f"wall {dt:.2f} s  eri {info['t_eri']:.3f} trsm {info['t_trsm']:.3f} "
+            f"wall {dt:.2f} s  guess {info['t_guess']:.3f} eri {info['t_eri']:.3f} trsm {info['t_trsm']:.3f} "
             f"j {info['t_j']:.3f} kx {info['t_kx']:.3f} ksyrk {info['t_ksyrk']:.3f} eig {info['t_eig']:.3f}")
         pn = {0: "d", 1: "s", 2: "b"}
         log("   history: " + " ".join(f"{pn.get(p, '?')}{e:.1e}" for p, e in zip(info["prec_hist"], info["err_hist"])))
+        if info["guess_fallback"]:
+            log(f"   learned guess fell back to the core guess (code {info['guess_fallback']})")
         return E, info, dt
 
+    gk = {"model": model} if model is not None else {}
     for w in range(a.warmup):
-        step(f"warmup {w}")
+        step(f"warmup {w}", a.steps + w, **gk)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = [step(f"step {k}") for k in range(a.steps)]
+    res = [step(f"step {k}", k, **gk) for k in range(a.steps)]
     torch.cuda.synchronize()
     T = (time.perf_counter() - t0) / max(1, a.steps)
     E, info, _ = res[-1]
+    k_last = a.steps - 1
 
+    context = None
+    if model is not None and not a.no_context:
+        Ec, ic, tc = step("context: same schedule, core guess", k_last)
+        context = {"guess": "core", "wall_s": round(tc, 3), "niter": ic["niter"], "n_mixed": ic["n_mixed"],
+                   "dE_vs_learned": Ec - E}
     plain = None
     if sched != dfx.SCHED_FP64 and not a.no_plain:
-        opts_p = dict(opts, schedule=dfx.SCHED_FP64)
-        t1 = time.perf_counter()
-        Ep, _, _, ip = dfx.scf(xyz, Z, sh, ax, want_c=False, **opts_p)
-        plain = {"wall_s": time.perf_counter() - t1, "E": Ep, "niter": ip["niter"], "dE_vs_plain": E - Ep}
-        log(f"plain fp64: E = {Ep:.10f} wall {plain['wall_s']:.2f} s")
+        Ep, ip, tp = step("plain fp64, core guess", k_last, schedule=dfx.SCHED_FP64)
+        plain = {"wall_s": round(tp, 3), "E": Ep, "niter": ip["niter"], "dE_vs_plain": E - Ep,
+                 "speedup": round(tp / T, 3)}
 
     out = {
         "metric": METRIC,
@@ -201,9 +255,14 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{a.workload}: (H2O)_{len(elems) // 3} DF-RHF, O[3s2p1d] H[2s1p] / "
                                f"O[8s6p4d2f] H[4s3p2d] even-tempered", "nbf": nbf, "naux": naux,
-                   "nocc": nocc, "schedule": a.schedule, "guess": "core", "tau": 1e-12},
+                   "nocc": nocc, "schedule": a.schedule, "guess": a.guess, "tau": 1e-12,
+                   "trajectory": bool(a.trajectory)},
         "E": E,
         "niter": info["niter"],
+        "n_mixed": info["n_mixed"],
+        "t_guess_s": round(info["t_guess"], 4),
+        "learned_guess": learned,
+        "context_core_guess": context,
         "eri_per_s": info["nintegrals"] / info["t_eri"] if info["t_eri"] > 0 else None,
         "phases_s": {k: round(info[k], 4) for k in ("t_setup", "t_scf", "t_eri", "t_metric", "t_trsm",
                                                      "t_j", "t_kx", "t_ksyrk", "t_eig")},
