@@ -131,162 +131,17 @@ void j_build(const JKArgs& a, const double* D, double* J, double* work, hipStrea
 }
 
 // ---------------------------------------------------------------------------
-// K, FP64: X_Q[mu][i] = sum_nu B_Q[mu][nu] C[nu][i] on v_mfma_f64_16x16x4, with
-// B_Q read from the packed tiles (each tile serves (mu, nu) and, transposed,
-// (nu, mu)).  X is stored as Xm[mu][(Q - q0) nocc + i].
-constexpr int KM = 128, KN = 64, KK = 16, KT = 256;
-
-__device__ __forceinline__ double b_elem(const float* hi, const float* lo, int64_t rowoff, int mu,
-                                         int nu) {
-  int r = mu, c = nu;
-  if (r < c) {
-    r = nu;
-    c = mu;
-  }
-  const int64_t o = rowoff + tile_base(r >> 5, c >> 5) + ((r & 31) << 5) + (c & 31);
-  return (double)hi[o] + (double)lo[o];
-}
-
-__global__ void __launch_bounds__(KT) kx_f64_kernel(const float* __restrict__ hi,
-                                                    const float* __restrict__ lo, int64_t ncols,
-                                                    int nbf, int q0, const double* __restrict__ C,
-                                                    int nocc, double* __restrict__ X, int64_t ldx) {
-  __shared__ double As[KK][KM + 2];
-  __shared__ double Bs[KK][KN + 2];
-  const int Q = q0 + blockIdx.z;
-  const int m0 = blockIdx.x * KM, n0 = blockIdx.y * KN;
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = w * 32;  // each wave: 32 rows x 64 columns = 2 x 4 MFMA blocks
-  const int li = lane & 15, lk = lane >> 4;
-  const int64_t rowoff = (int64_t)Q * ncols;
-  v4d acc[2][4];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = v4d{0, 0, 0, 0};
-  for (int k0 = 0; k0 < nbf; k0 += KK) {
-    double ra[8], rb[4];
-    {
-      const int i = tid >> 1, kb = (tid & 1) * 8, mu = m0 + i;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int nu = k0 + kb + j;
-        ra[j] = (mu < nbf && nu < nbf) ? b_elem(hi, lo, rowoff, mu, nu) : 0.0;
-      }
-    }
-    {
-      const int k = tid >> 4, nb = (tid & 15) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int nu = k0 + k, i = n0 + nb + j;
-        rb[j] = (nu < nbf && i < nocc) ? C[(int64_t)nu * nocc + i] : 0.0;
-      }
-    }
-    __syncthreads();
-    {
-      const int i = tid >> 1, kb = (tid & 1) * 8;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) As[kb + j][i] = ra[j];
-      const int k = tid >> 4, nb = (tid & 15) * 4;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) Bs[k][nb + j] = rb[j];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < KK; kk += 4) {
-      double fa[2], fb[4];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) fa[i] = As[kk + lk][wm + i * 16 + li];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) fb[j] = Bs[kk + lk][j * 16 + li];
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j)
-          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[i], fb[j], acc[i][j], 0, 0, 0);
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int mu = m0 + wm + i * 16 + r * 4 + lk;  // f64 MFMA output layout
-        const int col = n0 + j * 16 + li;
-        if (mu < nbf && col < nocc) X[(int64_t)mu * ldx + (int64_t)blockIdx.z * nocc + col] = acc[i][j][r];
-      }
-}
-
-// K_lower = sum_s P_s  (partial SYRKs of the Q slices), then mirrored
-__global__ void k_reduce_kernel(const double* __restrict__ P, int ns, int nbf, double* __restrict__ K,
-                                int accumulate) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t n2 = (int64_t)nbf * nbf;
-  if (idx >= n2) return;
-  const int r = (int)(idx / nbf), c = (int)(idx % nbf);
-  if (c > r) return;
-  double s = accumulate ? K[idx] : 0.0;
-  for (int k = 0; k < ns; ++k) s += P[k * n2 + idx];
-  K[idx] = s;
-}
-
-struct KPlan {
-  int qc;      // Q per chunk
-  int ns;      // slices per chunk
-  int qs;      // Q per slice
-  size_t x_elems, p_elems;
-};
-static KPlan k_plan(const JKArgs& a, int nocc) {
-  KPlan p{};
-  const size_t per_q = (size_t)a.nbf * (size_t)nocc;
-  size_t cap = ((size_t)2 << 30) / (per_q * sizeof(double));  // ~2 GiB of X per chunk
-  if (cap < 1) cap = 1;
-  p.qc = (int)std::min<size_t>(cap, (size_t)a.naux);
-  p.ns = std::min(8, p.qc);
-  p.qs = (p.qc + p.ns - 1) / p.ns;
-  p.x_elems = (size_t)a.nbf * (size_t)p.ns * p.qs * nocc;
-  p.p_elems = (size_t)p.ns * a.nbf * a.nbf;
-  return p;
-}
-
+// K: FP64 in jk_f64.hip, FP32 / BF16 in jk_mixed.hip
 size_t k_work_bytes(const JKArgs& a, int nocc) {
-  if (a.prec != PREC_FP64) return k_work_bytes_mixed(a, nocc);
-  const KPlan p = k_plan(a, nocc);
-  return (p.x_elems + p.p_elems) * sizeof(double) + 256;
+  return a.prec == PREC_FP64 ? k_work_bytes_f64(a, nocc) : k_work_bytes_mixed(a, nocc);
 }
 
 void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st,
              KTimer* timer) {
-  if (a.prec != PREC_FP64) {
+  if (a.prec == PREC_FP64)
+    k_build_f64(a, C, nocc, K, work, st, timer);
+  else
     k_build_mixed(a, C, nocc, K, work, st, timer);
-    return;
-  }
-  const KPlan p = k_plan(a, nocc);
-  double* X = reinterpret_cast<double*>(work);
-  double* P = X + p.x_elems;
-  const int64_t ldx = (int64_t)p.ns * p.qs * nocc;
-  const int64_t n2 = (int64_t)a.nbf * a.nbf;
-  for (int q0 = 0; q0 < a.naux; q0 += p.qc) {
-    const int nq = std::min(p.qc, a.naux - q0);
-    if (nq < p.ns * p.qs) fill_f64(X, p.x_elems, 0.0, st);
-    const dim3 g1((a.nbf + KM - 1) / KM, (nocc + KN - 1) / KN, nq);
-    if (timer) timer->begin_x();
-    hipLaunchKernelGGL(kx_f64_kernel, g1, dim3(KT), 0, st, a.hi, a.lo, a.ncols, a.nbf, q0, C, nocc, X, ldx);
-    if (timer) timer->end_x();
-    if (timer) timer->begin_syrk();
-    GemmF64 g{};
-    g.M = a.nbf; g.N = a.nbf; g.K = p.qs * nocc;
-    g.A = X; g.lda = ldx; g.sA = (int64_t)p.qs * nocc;
-    g.B = X; g.ldb = ldx; g.sB = (int64_t)p.qs * nocc; g.tb = true;
-    g.C = P; g.ldc = a.nbf; g.sC = n2;
-    g.alpha = 1.0; g.beta = 0.0; g.batch = p.ns; g.lowerC = true;
-    dgemm(g, st);
-    hipLaunchKernelGGL(k_reduce_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, P, p.ns,
-                       a.nbf, K, q0 > 0 ? 1 : 0);
-    if (timer) timer->end_syrk();
-  }
-  sym_from_lower(K, a.nbf, st);
 }
 
 // ---------------------------------------------------------------------------

@@ -81,6 +81,10 @@ struct KTimer {
 };
 void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st,
              KTimer* timer = nullptr);
+// FP64 K (jk_f64.hip), dispatched by k_build for PREC_FP64
+size_t k_work_bytes_f64(const JKArgs& a, int nocc);
+void k_build_f64(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st,
+                 KTimer* timer);
 // reduced-precision K (jk_mixed.hip), dispatched by k_build for PREC_FP32 / PREC_BF16
 size_t k_work_bytes_mixed(const JKArgs& a, int nocc);
 void k_build_mixed(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st,

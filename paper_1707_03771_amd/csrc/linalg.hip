@@ -9,7 +9,9 @@ namespace dfx {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int GM = 128, GN = 128, GK = 16, GT = 256;
-constexpr int LDS_PAD = 2;
+// k-major LDS rows of GM + 16 doubles: the four k rows a fragment read touches
+// fall on alternate halves of the 64 banks (2 passes per read, the minimum)
+constexpr int LDS_PAD = 16;
 enum { EPI_F64 = 0, EPI_SPLIT = 1 };
 
 // Workgroup -> tile map.  Workgroups are dealt round-robin to the 8 XCDs; give
@@ -21,8 +23,21 @@ __device__ __forceinline__ int xcd_tile(int bid, int tiles) {
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + slot;
 }
 
+// 8 consecutive doubles from p (16-byte aligned) as four 16-byte loads
+__device__ __forceinline__ void ld8d(const double* __restrict__ p, double* v) {
+  const double2* q = reinterpret_cast<const double2*>(p);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const double2 x = q[e];
+    v[2 * e] = x.x;
+    v[2 * e + 1] = x.y;
+  }
+}
+
+// C = alpha op(A) op(B) + beta C (EPI_F64) or hi/lo = split(op(A) op(B)) (EPI_SPLIT).
+// Each k-stage is loaded into registers while the MFMAs of the previous stage run.
 template <bool TA, bool TB, int EPI>
-__global__ void __launch_bounds__(GT) dgemm_kernel(GemmF64 g, float* __restrict__ hi,
+__global__ void __launch_bounds__(GT, 2) dgemm_kernel(GemmF64 g, float* __restrict__ hi,
                                                    float* __restrict__ lo) {
   __shared__ double As[GK][GM + LDS_PAD];
   __shared__ double Bs[GK][GN + LDS_PAD];
@@ -37,6 +52,9 @@ __global__ void __launch_bounds__(GT) dgemm_kernel(GemmF64 g, float* __restrict_
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
   const int li = lane & 15, lk = lane >> 4;
+  // vector loads need even leading dimensions and 16-byte aligned bases
+  const bool va = (g.lda % 2 == 0) && ((reinterpret_cast<uintptr_t>(A) & 15) == 0);
+  const bool vb = (g.ldb % 2 == 0) && ((reinterpret_cast<uintptr_t>(B) & 15) == 0);
 
   v4d acc[4][4];
 #pragma unroll
@@ -47,42 +65,44 @@ __global__ void __launch_bounds__(GT) dgemm_kernel(GemmF64 g, float* __restrict_
   int kmax = g.K;
   if (g.lowerA && m0 + GM < kmax) kmax = m0 + GM;
 
-  for (int k0 = 0; k0 < kmax; k0 += GK) {
-    double ra[8], rb[8];
-    // ---- global -> registers
-    if (!TA) {
-      const int i = tid >> 1, kb = (tid & 1) * 8;
-      const int m = m0 + i;
+  double ra[8], rb[8];
+  auto load = [&](int k0) {
+    if (!TA) {  // row m, 8 consecutive k
+      const int m = m0 + (tid >> 1), k = k0 + (tid & 1) * 8;
+      if (va && m < g.M && k + 8 <= kmax) {
+        ld8d(A + (int64_t)m * g.lda + k, ra);
+      } else {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + kb + j;
-        ra[j] = (m < g.M && k < kmax) ? A[(int64_t)m * g.lda + k] : 0.0;
+        for (int j = 0; j < 8; ++j) ra[j] = (m < g.M && k + j < kmax) ? A[(int64_t)m * g.lda + k + j] : 0.0;
       }
-    } else {
-      const int k = k0 + (tid >> 4), mb = (tid & 15) * 8;
+    } else {    // row k, 8 consecutive m
+      const int k = k0 + (tid >> 4), m = m0 + (tid & 15) * 8;
+      if (va && k < kmax && m + 8 <= g.M) {
+        ld8d(A + (int64_t)k * g.lda + m, ra);
+      } else {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int m = m0 + mb + j;
-        ra[j] = (m < g.M && k < kmax) ? A[(int64_t)k * g.lda + m] : 0.0;
-      }
-    }
-    if (!TB) {
-      const int k = k0 + (tid >> 4), nb = (tid & 15) * 8;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int n = n0 + nb + j;
-        rb[j] = (n < g.N && k < kmax) ? B[(int64_t)k * g.ldb + n] : 0.0;
-      }
-    } else {
-      const int n = n0 + (tid >> 1), kb = (tid & 1) * 8;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int k = k0 + kb + j;
-        rb[j] = (n < g.N && k < kmax) ? B[(int64_t)n * g.ldb + k] : 0.0;
+        for (int j = 0; j < 8; ++j) ra[j] = (m + j < g.M && k < kmax) ? A[(int64_t)k * g.lda + m + j] : 0.0;
       }
     }
-    __syncthreads();
-    // ---- registers -> LDS (k-major)
+    if (!TB) {  // row k, 8 consecutive n
+      const int k = k0 + (tid >> 4), n = n0 + (tid & 15) * 8;
+      if (vb && k < kmax && n + 8 <= g.N) {
+        ld8d(B + (int64_t)k * g.ldb + n, rb);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) rb[j] = (n + j < g.N && k < kmax) ? B[(int64_t)k * g.ldb + n + j] : 0.0;
+      }
+    } else {    // row n, 8 consecutive k
+      const int n = n0 + (tid >> 1), k = k0 + (tid & 1) * 8;
+      if (vb && n < g.N && k + 8 <= kmax) {
+        ld8d(B + (int64_t)n * g.ldb + k, rb);
+      } else {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) rb[j] = (n < g.N && k + j < kmax) ? B[(int64_t)n * g.ldb + k + j] : 0.0;
+      }
+    }
+  };
+  auto store = [&]() {  // registers -> LDS, k-major
     if (!TA) {
       const int i = tid >> 1, kb = (tid & 1) * 8;
 #pragma unroll
@@ -101,8 +121,14 @@ __global__ void __launch_bounds__(GT) dgemm_kernel(GemmF64 g, float* __restrict_
 #pragma unroll
       for (int j = 0; j < 8; ++j) Bs[kb + j][n] = rb[j];
     }
+  };
+
+  if (kmax > 0) load(0);
+  for (int k0 = 0; k0 < kmax; k0 += GK) {
+    __syncthreads();  // the previous stage's fragments have been read
+    store();
     __syncthreads();
-    // ---- MFMA
+    if (k0 + GK < kmax) load(k0 + GK);
 #pragma unroll
     for (int kk = 0; kk < GK; kk += 4) {
       double fa[4], fb[4];
