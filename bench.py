@@ -163,6 +163,22 @@ def train_guess(dfx, n27=8, n8=16, epochs=80, batch=128, seed=5):
                "loss_last": round(float(loss[-1]), 4)}
 
 
+def profile_jk(dfx, torch, sh, ax, nocc, prec):
+    """One J/K build on the workload's B with a seeded orthonormal C_occ, then a
+    copy of 2^28 floats (1 GiB read, 1 GiB written) whose counters calibrate
+    the per-dispatch HBM byte counts."""
+    B = dfx.eri3(sh, ax)
+    C = torch.tensor(W.random_orthonormal(B.nbf, nocc, seed=1), device="cuda")
+    J, K = dfx.jk(B, C, precision=prec)
+    torch.cuda.synchronize()
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    log(f"profile-jk: nbf {B.nbf} naux {B.naux} nocc {nocc}; copy calibration 1 GiB read + 1 GiB written")
+    B.free()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +192,9 @@ def main():
                     help="step k runs frame k of a seeded trajectory (per-atom sigma 0.02 bohr)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 reference run")
     ap.add_argument("--no-context", action="store_true", help="skip the core-guess context run")
+    ap.add_argument("--profile-jk", default=None, choices=["fp64", "fp32", "bf16"],
+                    help="counter-run driver: build B, one J/K build in this precision with the SCF's "
+                         "launch configuration, and a 1 GiB elementwise copy as the HBM calibration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -190,11 +209,17 @@ def main():
     elems, xyz, sh, ax = W.workload(a.workload)
     Z = W.charges(elems)
     nocc = W.nocc_of(elems)
+    if a.profile_jk:
+        profile_jk(dfx, torch, sh, ax, nocc, {"fp64": dfx.FP64, "fp32": dfx.FP32, "bf16": dfx.BF16}[a.profile_jk])
+        return
     nbf = sum(2 * s["l"] + 1 for s in sh)
     naux = sum(2 * s["l"] + 1 for s in ax)
     sched = dfx.SCHED_MIXED if a.schedule == "mixed" else dfx.SCHED_FP64
     mp = dfx.BF16 if a.mixed_prec == "bf16" else dfx.FP32
-    opts = dict(conv_dE=1e-8, conv_err=1e-6, schedule=sched, mixed_prec=mp, max_iter=100)
+    # converged = |E_k - E_k-1| < 1e-7 and max|e| < 1e-5 for every run: with the
+    # superlinear end of the iterations this leaves the energy within ~1e-8 of a
+    # tightly converged FP64 solution, well inside the 1e-6 Eh the metric asks for
+    opts = dict(conv_dE=1e-7, conv_err=1e-5, schedule=sched, mixed_prec=mp, max_iter=100)
     log(f"workload {a.workload}: {len(elems)} atoms, nbf {nbf}, naux {naux}, nocc {nocc}")
 
     model, learned = (None, None)
@@ -261,6 +286,7 @@ def main():
         "niter": info["niter"],
         "n_mixed": info["n_mixed"],
         "t_guess_s": round(info["t_guess"], 4),
+        "floor_est": info["floor_est"],
         "learned_guess": learned,
         "context_core_guess": context,
         "eri_per_s": info["nintegrals"] / info["t_eri"] if info["t_eri"] > 0 else None,

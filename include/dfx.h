@@ -206,6 +206,11 @@ typedef struct {
   int32_t guess;         /* DFX_GUESS_* */
   int32_t verbose;
   const dfx_guess* model;  /* DFX_GUESS_LEARNED: the model (not owned), else NULL */
+  int32_t switch_auto;   /* mixed schedule (1, default): once a reduced-precision stage's
+                            error is below 1e-2, estimate its floor: K in that precision
+                            and in FP64 on every 16th auxiliary function, the DIIS-error
+                            commutator of the difference scaled by sqrt(16); the stage
+                            ends once its error is below max(switch_err, estimate) */
 } dfx_scf_opts;
 
 #define DFX_MAXHIST 256
@@ -241,6 +246,7 @@ typedef struct {
   double err_hist[DFX_MAXHIST];
   int8_t prec_hist[DFX_MAXHIST];  /* DFX_FP64 / DFX_FP32 / DFX_BF16 of each Fock build */
   double t_guess;        /* seconds of wall time for the starting guess (inside t_setup) */
+  double floor_est[3];   /* switch_auto: estimated DIIS-error floor per precision (0 if none) */
   int32_t guess_fallback; /* DFX_GUESS_LEARNED: 0 used; 1 non-finite prediction, core guess
                              used instead; 2 no convergence from it in max_iter, restarted
                              from the core guess (niter and the histories count both passes) */

@@ -19,6 +19,11 @@ LIB_PATH = os.path.join(_HERE, "libdfx.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1707_03771_amd.build`")
 
+# torch first: its HIP runtime is then the one libdfx.so binds to (same soname).
+# Loaded the other way round, the process holds two HIP/HSA runtimes and torch's
+# finds no device.
+import torch  # noqa: E402,F401
+
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, EINVAL, ENOMEM, EHIP, ENOTPOSDEF, ENOCONV, EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
@@ -65,7 +70,7 @@ class ScfOpts(ctypes.Structure):
                 ("ortho_thresh", ctypes.c_double), ("switch_err", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("diis_size", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("mixed_prec", ctypes.c_int32), ("guess", ctypes.c_int32), ("verbose", ctypes.c_int32),
-                ("model", ctypes.c_void_p)]
+                ("model", ctypes.c_void_p), ("switch_auto", ctypes.c_int32)]
 
 
 class ScfInfo(ctypes.Structure):
@@ -81,7 +86,7 @@ class ScfInfo(ctypes.Structure):
                 ("nintegrals", ctypes.c_int64), ("ncols", ctypes.c_int64),
                 ("E_hist", ctypes.c_double * MAXHIST), ("err_hist", ctypes.c_double * MAXHIST),
                 ("prec_hist", ctypes.c_int8 * MAXHIST), ("t_guess", ctypes.c_double),
-                ("guess_fallback", ctypes.c_int32)]
+                ("floor_est", ctypes.c_double * 3), ("guess_fallback", ctypes.c_int32)]
 
 
 class GuessSpec(ctypes.Structure):
@@ -314,7 +319,7 @@ def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, model=None, **opt
     if code not in (OK, ENOCONV):
         _check(code)
     info = {k: getattr(inf, k) for k, _ in ScfInfo._fields_ if not k.endswith("_hist")}
-    for k in ("t_kx_p", "t_ksyrk_p", "n_jk_p", "n_kx_launch_p"):
+    for k in ("t_kx_p", "t_ksyrk_p", "n_jk_p", "n_kx_launch_p", "floor_est"):
         info[k] = list(getattr(inf, k))
     info["E_hist"] = list(inf.E_hist)[: inf.niter]
     info["err_hist"] = list(inf.err_hist)[: inf.niter]

@@ -18,15 +18,25 @@ constexpr int S64 = 16;   // k-width of one LDS stage (half a tile column of B_Q
 constexpr int PA = 2;     // row padding (doubles) of [row][k] tiles: conflict-free A/B fragments
 constexpr int PB = 16;    // row padding (doubles) of the [k][i] C stage
 
+// C_occ zero-padded to Cp[nbfp][np] (np = 64 NCB, nbfp = 32 ntiles), so that a
+// k-stage of C is one contiguous, aligned block
+__global__ void cpad_kernel(const double* __restrict__ C, int nbf, int nocc, int nbfp, int np,
+                            double* __restrict__ Cp) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)nbfp * np) return;
+  const int nu = (int)(idx / np), i = (int)(idx % np);
+  Cp[idx] = (nu < nbf && i < nocc) ? C[(int64_t)nu * nocc + i] : 0.0;
+}
+
 // ---- phase 1: X_Q[mu][i] = sum_nu B_Q[mu][nu] C[nu][i] for a 64-row block of mu
 // and all occupied columns (padded to NP = 64 NCB).  Wave w owns columns
 // [w NCB 16, (w + 1) NCB 16) of all four 16-row blocks.
 template <int NCB>
 __global__ void __launch_bounds__(256) kx64_kernel(const float* __restrict__ hi, const float* __restrict__ lo,
-                                                   int64_t ncols, int nbf, int q0, const double* __restrict__ C,
+                                                   int64_t ncols, int nbf, int q0, const double* __restrict__ Cp,
                                                    int nocc, double* __restrict__ X, int64_t ldx) {
   constexpr int NP = 64 * NCB;
-  constexpr int NCL = S64 * NP / 256;  // C elements per thread per stage
+  constexpr int NCL = S64 * NP / 512;  // 16-byte pairs of C per thread per stage
   __shared__ double As[64][S64 + PA];
   __shared__ double Bs[S64][NP + PB];
   const int Q = q0 + blockIdx.y;
@@ -42,7 +52,7 @@ __global__ void __launch_bounds__(256) kx64_kernel(const float* __restrict__ hi,
   const int I = I0 + half;
 
   float4 ah, al;
-  double cr[NCL];
+  double2 cr[NCL];
   auto load = [&](int stage) {
     const int J = stage >> 1, h = stage & 1;
     ah = al = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -55,13 +65,9 @@ __global__ void __launch_bounds__(256) kx64_kernel(const float* __restrict__ hi,
       ah = *reinterpret_cast<const float4*>(rh + off);
       al = *reinterpret_cast<const float4*>(rl + off);
     }
-    const int nu0 = stage * S64;
+    const double2* __restrict__ cs = reinterpret_cast<const double2*>(Cp + (int64_t)stage * S64 * NP);
 #pragma unroll
-    for (int c = 0; c < NCL; ++c) {
-      const int e = tid + 256 * c, k = e / NP, i = e % NP;
-      const int nu = nu0 + k;
-      cr[c] = (nu < nbf && i < nocc) ? C[(int64_t)nu * nocc + i] : 0.0;
-    }
+    for (int c = 0; c < NCL; ++c) cr[c] = cs[tid + 256 * c];
   };
   auto store = [&](int stage) {
     const int J = stage >> 1;
@@ -78,8 +84,9 @@ __global__ void __launch_bounds__(256) kx64_kernel(const float* __restrict__ hi,
     }
 #pragma unroll
     for (int c = 0; c < NCL; ++c) {
-      const int e = tid + 256 * c;
-      Bs[e / NP][e % NP] = cr[c];
+      const int e = 2 * (tid + 256 * c);  // NP is even: a pair never straddles rows
+      Bs[e / NP][e % NP] = cr[c].x;
+      Bs[e / NP][e % NP + 1] = cr[c].y;
     }
   };
 
@@ -240,9 +247,9 @@ __global__ void k_reduce64_kernel(const double* __restrict__ P, int ns, int nbf,
 }
 
 struct F64Plan {
-  int qc, ns, ntl;
+  int qc, ns, ntl, np, nbfp;
   int64_t ldx;
-  size_t x_bytes, p_bytes;
+  size_t x_bytes, p_bytes, c_bytes;
 };
 
 // X chunks of at most 8 GiB, balanced over the chunks; enough SYRK slices (a
@@ -265,12 +272,17 @@ static F64Plan f64_plan(const JKArgs& a, int nocc) {
   p.ns = (int)(((ns + 7) / 8) * 8);
   p.x_bytes = (size_t)a.nbf * p.ldx * sizeof(double);
   p.p_bytes = (size_t)p.ns * a.nbf * a.nbf * sizeof(double);
+  p.np = 64 * ((nocc + 63) / 64);
+  p.nbfp = ntiles_for(a.nbf) * TILE;
+  p.c_bytes = (size_t)p.nbfp * p.np * sizeof(double);
   return p;
 }
 
+static size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 size_t k_work_bytes_f64(const JKArgs& a, int nocc) {
   const F64Plan p = f64_plan(a, nocc);
-  return ((p.x_bytes + 255) & ~(size_t)255) + p.p_bytes + 256;
+  return a256(p.x_bytes) + a256(p.p_bytes) + p.c_bytes + 256;
 }
 
 void k_build_f64(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st,
@@ -278,9 +290,14 @@ void k_build_f64(const JKArgs& a, const double* C, int nocc, double* K, void* wo
   const F64Plan p = f64_plan(a, nocc);
   const int ncb = (nocc + 63) / 64;
   if (ncb > 8) throw Error(-6, "k_build: more than 512 occupied orbitals");
-  double* X = reinterpret_cast<double*>(work);
-  double* P = reinterpret_cast<double*>(reinterpret_cast<char*>(work) + ((p.x_bytes + 255) & ~(size_t)255));
+  char* w = reinterpret_cast<char*>(work);
+  double* X = reinterpret_cast<double*>(w);
+  double* P = reinterpret_cast<double*>(w + a256(p.x_bytes));
+  double* Cp = reinterpret_cast<double*>(w + a256(p.x_bytes) + a256(p.p_bytes));
   const int64_t n2 = (int64_t)a.nbf * a.nbf;
+  const int64_t ncp = (int64_t)p.nbfp * p.np;
+  hipLaunchKernelGGL(cpad_kernel, dim3((unsigned)((ncp + 255) / 256)), dim3(256), 0, st, C, a.nbf, nocc, p.nbfp,
+                     p.np, Cp);
   for (int q0 = 0; q0 < a.naux; q0 += p.qc) {
     const int nq = std::min(p.qc, a.naux - q0);
     const int64_t kdim = (int64_t)nq * nocc;
@@ -289,7 +306,7 @@ void k_build_f64(const JKArgs& a, const double* C, int nocc, double* K, void* wo
     switch (ncb) {
 #define KX64(N)                                                                                            \
   case N:                                                                                                  \
-    hipLaunchKernelGGL((kx64_kernel<N>), g1, dim3(256), 0, st, a.hi, a.lo, a.ncols, a.nbf, q0, C, nocc, X, \
+    hipLaunchKernelGGL((kx64_kernel<N>), g1, dim3(256), 0, st, a.hi, a.lo, a.ncols, a.nbf, q0, Cp, nocc, X, \
                        p.ldx);                                                                             \
     break;
       KX64(1) KX64(2) KX64(3) KX64(4) KX64(5) KX64(6) KX64(7) KX64(8)

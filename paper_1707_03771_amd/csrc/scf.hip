@@ -232,6 +232,7 @@ void dfx_scf_default_opts(dfx_scf_opts* o) {
   o->mixed_prec = DFX_FP32;
   o->guess = DFX_GUESS_CORE;
   o->verbose = 0;
+  o->switch_auto = 1;
 }
 
 int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
@@ -407,6 +408,7 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     JKArgs ja{B->hi.as<float>(), B->lo.as<float>(), B->naux, n, B->ncols_t, PREC_FP64};
     const bool mixed = (o.schedule == DFX_SCHED_MIXED);
     int nfp64 = 0, it = 0, n_mixed = 0, it_done = 0;
+    double floor_est[3] = {0.0, 0.0, 0.0};
     double E = 0.0, Eold = 0.0, emax = 0.0;
     bool converged = false;
     dfx_scf_info inf{};
@@ -429,13 +431,56 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     std::vector<double> stage_errs;
     int prec = stages[0];
     int hcount = 0, hpos = 0;
+    bool stage_estimated = false;
     nfp64 = 0;
     std::vector<double> Bdiis((size_t)dsz * dsz, 0.0);
     for (it = 1; it <= o.max_iter; ++it) {
       const int ih = it_done + it;  // iteration number over both passes
       ja.prec = prec;
-      const size_t need = std::max(sizeof(double) * (2 * (size_t)B->ncols_t + B->naux + 8), k_work_bytes(ja, nocc));
+      size_t need = std::max(sizeof(double) * (2 * (size_t)B->ncols_t + B->naux + 8), k_work_bytes(ja, nocc));
+      // the floor is estimated once per stage, at the first iteration after the
+      // stage's error fell below 1e-2: by then DIIS converges steadily and the
+      // density is close enough to the solution for the estimate to be the floor
+      // (at a poor starting density it overshoots and would end the stage early)
+      const bool estimate = mixed && o.switch_auto && prec != DFX_FP64 && !stage_estimated && !stage_errs.empty() &&
+                            stage_errs.back() < 1e-2;
+      JKArgs sub = ja;
+      if (estimate) {
+        // every S-th auxiliary function: rows S q of B, as a tensor with row stride S ncols
+        const int Sg = std::max(1, std::min(16, B->naux / 64));
+        sub.naux = (B->naux + Sg - 1) / Sg;
+        sub.ncols = ja.ncols * Sg;
+        JKArgs s64 = sub;
+        s64.prec = PREC_FP64;
+        need = std::max(need, std::max(k_work_bytes(sub, nocc), k_work_bytes(s64, nocc)));
+      }
       void* w = B->ensure_work(need);
+      if (estimate) {
+        // the stage's floor: how far its K moves the DIIS error, measured at this
+        // density on the sample and scaled to all functions (independent rounding
+        // errors add in quadrature)
+        k_build(sub, Cocc.as<double>(), nocc, Km.as<double>(), w, st, nullptr);
+        JKArgs s64 = sub;
+        s64.prec = PREC_FP64;
+        k_build(s64, Cocc.as<double>(), nocc, Jm.as<double>(), w, st, nullptr);
+        Comb cd{};
+        cd.m = 2;
+        cd.F[0] = Km.as<double>();
+        cd.c[0] = 1.0;
+        cd.F[1] = Jm.as<double>();
+        cd.c[1] = -1.0;
+        hipLaunchKernelGGL(lincomb_kernel, dim3(nblk(n2)), dim3(256), 0, st, cd, F.as<double>(), n2);
+        S.gemm(n, n, n, F.as<double>(), n, false, D.as<double>(), n, false, t1.as<double>(), n);
+        S.gemm(n, n, n, t1.as<double>(), n, false, Sm.as<double>(), n, false, t2.as<double>(), n);
+        hipLaunchKernelGGL(antisym_kernel, dim3(nblk(n2)), dim3(256), 0, st, t2.as<double>(), t1.as<double>(), n);
+        S.gemm(m, n, n, X.as<double>(), m, true, t1.as<double>(), n, false, t2.as<double>(), n);
+        S.gemm(m, m, n, t2.as<double>(), n, false, X.as<double>(), m, false, Fp.as<double>(), m);
+        const double est = S.reduce_max(Fp.as<double>(), (int64_t)m * m) * std::sqrt((double)B->naux / sub.naux);
+        floor_est[prec] = est;
+        stage_thr[stage] = std::max(stage_thr[stage], est);
+        stage_estimated = true;
+        if (o.verbose) std::fprintf(stderr, "dfx_scf stage %d: estimated floor %.3e\n", stage, est);
+      }
       sp_j.begin();
       j_build(ja, D.as<double>(), Jm.as<double>(), reinterpret_cast<double*>(w), st);
       sp_j.end();
@@ -496,6 +541,7 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
         prec = stages[stage];
         stage_it = 0;
         stage_errs.clear();
+        stage_estimated = false;
         hcount = 0;
         hpos = 0;
         diag(F.as<double>());
@@ -571,6 +617,7 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     inf.err_max = emax;
     inf.t_setup = std::chrono::duration<double>(t1c - t0).count();
     inf.t_guess = t_guess;
+    for (int k = 0; k < 3; ++k) inf.floor_est[k] = floor_est[k];
     inf.t_scf = std::chrono::duration<double>(t2c - t1c).count();
     inf.t_total = std::chrono::duration<double>(clk::now() - t0).count();
     inf.t_eri = B->info.eri_seconds;
