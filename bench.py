@@ -43,6 +43,29 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def measured_traffic(kernel_label):
+    """HBM bytes per launch from the committed counter summary of the FP64 half
+    transform, or None if the kernel's source has changed since the counters
+    were taken (or the summary is for another kernel)."""
+    import hashlib
+    if not kernel_label.startswith("K half-transform X_Q = B_Q C, FP64"):
+        return None
+    path = os.path.join(ROOT, "profiles", "kx64_water64_pmc.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = os.path.join(ROOT, kv.get("source", ""))
+    if not os.path.exists(src):
+        return None
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != kv.get("source_sha256_16"):
+        return None
+    return float(kv["traffic_bytes_per_launch"])
+
+
 def roofline(info, nbf, naux, nocc):
     """Roofline of the kernel with the largest GPU time, from the live HIP-event
     timings the library reports per kernel and precision: algorithmic FLOPs per
@@ -67,7 +90,7 @@ def roofline(info, nbf, naux, nocc):
     launches = max(1, launches)
     achieved = (flops / launches) / (t / launches)
     return {"kernel": name, "bound": "mfma", "achieved": achieved / 1e12, "peak": peak / 1e12,
-            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+            "unit": "TFLOP/s", "frac": achieved / peak, "traffic": measured_traffic(name),
             "flops_per_launch": flops / launches, "avg_launch_ms": 1e3 * t / launches,
             "all": {k: {"s": round(v[0], 4), "TFLOP/s": round(v[1] / v[0] / 1e12, 2) if v[0] > 0 else None,
                         "frac": round(v[1] / v[0] / v[3], 4) if v[0] > 0 else None} for k, v in cands.items()}}
