@@ -121,6 +121,29 @@ int dfx_eri3(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
 int dfx_B_info_get(const dfx_B* b, dfx_B_info* info);
 
 /*
+ * dfx_eri3_plan -- sizes of dfx_eri3's device memory, host only (no GPU
+ * work): function counts and the bytes of B (hi + lo over the packed 32x32
+ * tile layout, independent of screening), of the raw integrals held during
+ * setup, and of the metric, its factor and inverse.  Errors as dfx_eri3.
+ */
+typedef struct {
+  int32_t nbf, naux;
+  int64_t ncols_tiled;      /* storage columns of B */
+  int64_t bytes_B;          /* kept until dfx_B_free */
+  int64_t bytes_raw;        /* setup only */
+  int64_t bytes_metric;     /* setup only: J_PQ, L, L^-1 */
+  int64_t bytes_setup_peak; /* B + raw + metric */
+} dfx_eri3_sizes;
+int dfx_eri3_plan(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh, dfx_eri3_sizes* out);
+
+/*
+ * dfx_B_unpack -- rows q0..q1-1 of B as dense symmetric matrices,
+ * dev_out[(q - q0) nbf nbf + mu nbf + nu] = B_q,mu nu (FP64 = hi + lo), device
+ * memory of (q1 - q0) nbf^2 doubles owned by the caller.  Enqueued on stream.
+ */
+int dfx_B_unpack(const dfx_B* b, int q0, int q1, double* dev_out, void* stream);
+
+/*
  * Integer lists of the screening (host buffers, the bit-exact contract):
  *   pairs   [2 * npairs]  (a, b) of each kept pair, canonical order a = 0..,
  *                         b = 0..a, a-major
@@ -152,7 +175,10 @@ int dfx_B_free(dfx_B* b);
  * utilities"): J = sum_Q B_Q gamma_Q with gamma_Q = sum B_Q D (Eqs. 3a, 3b);
  * K = sum_Q X_Q X_Q^T with X_Q = B_Q C_occ (Eqs. 1a, 2a).
  *   dev_in     kind = DFX_COCC: C_occ [nbf][nocc]; DFX_DENSITY: D [nbf][nbf]
- *              (K for a density input needs DFX_COCC in this version)
+ *              (symmetric).  For a density, K = sum_Q B_Q D B_Q through the
+ *              signed factorisation D = C+ C+^T - C- C-^T from D's
+ *              eigenvectors (eigenvalues below 1e-14 of the largest dropped);
+ *              that call synchronises the stream.
  *   precision  DFX_FP64 | DFX_FP32 | DFX_BF16
  *   dev_J, dev_K  nbf x nbf outputs, either may be NULL
  * Errors: DFX_EINVAL, DFX_ENOMEM, DFX_EHIP, DFX_EUNSUPPORTED.

@@ -89,6 +89,12 @@ class ScfInfo(ctypes.Structure):
                 ("floor_est", ctypes.c_double * 3), ("guess_fallback", ctypes.c_int32)]
 
 
+class Eri3Sizes(ctypes.Structure):
+    _fields_ = [("nbf", ctypes.c_int32), ("naux", ctypes.c_int32), ("ncols_tiled", ctypes.c_int64),
+                ("bytes_B", ctypes.c_int64), ("bytes_raw", ctypes.c_int64), ("bytes_metric", ctypes.c_int64),
+                ("bytes_setup_peak", ctypes.c_int64)]
+
+
 class GuessSpec(ctypes.Structure):
     _fields_ = [("nelem", ctypes.c_int32), ("Z", ctypes.c_void_p), ("nshell", ctypes.c_void_p),
                 ("shell_l", ctypes.c_void_p), ("rc", ctypes.c_double), ("rc_env", ctypes.c_double),
@@ -117,6 +123,8 @@ _SIGS = {
     "dfx_guess_predict": [_vp, _vp, _vp],
     "dfx_guess_info": [_vp, _vp, _vp],
     "dfx_guess_export": [_vp, _i, _vp, _vp, _vp, _vp, _vp],
+    "dfx_eri3_plan": [_vp, _i, _vp, _i, _vp],
+    "dfx_B_unpack": [_vp, _i, _i, _vp, _vp],
     "dfx_lowdin": [_vp, _vp, _i, _vp, _vp, _vp],
     "dfx_guess_samples": [_vp, _i, _vp, _vp],
     "dfx_guess_import": [_vp, _i, _i, _i, _vp, _vp, _vp, _vp, _vp],
@@ -218,6 +226,14 @@ class DFTensor:
         _check(_lib.dfx_B_metric(self.h, what, _ptr(out), _stream(stream)))
         return out
 
+    def unpack(self, q0=0, q1=None, stream=None):
+        """Rows q0..q1-1 of B as dense (q1 - q0, nbf, nbf) float64 cuda tensors."""
+        import torch
+        q1 = self.naux if q1 is None else q1
+        out = torch.empty((q1 - q0, self.nbf, self.nbf), dtype=torch.float64, device="cuda")
+        _check(_lib.dfx_B_unpack(self.h, q0, q1, _ptr(out), _stream(stream)))
+        return out
+
     def free(self):
         if self.h:
             _check(_lib.dfx_B_free(self.h))
@@ -228,6 +244,14 @@ class DFTensor:
             self.free()
         except Exception:
             pass
+
+
+def eri3_plan(shells, aux):
+    """dfx_eri3_plan: device-memory sizes of dfx_eri3 (host only)."""
+    s, a = _ShellArray(shells), _ShellArray(aux)
+    z = Eri3Sizes()
+    _check(_lib.dfx_eri3_plan(s.arr, s.n, a.arr, a.n, ctypes.byref(z)))
+    return {k: getattr(z, k) for k, _ in Eri3Sizes._fields_}
 
 
 def eri3(shells, aux, tau=1e-12, flags=0, stream=None):

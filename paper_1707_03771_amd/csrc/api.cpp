@@ -429,6 +429,33 @@ int dfx_cholesky(double* dev_A, int n, double* dev_Linv, void* stream) {
   });
 }
 
+int dfx_eri3_plan(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh, dfx_eri3_sizes* out) {
+  return guard([&] {
+    if (!out) throw Error(DFX_EINVAL, "dfx_eri3_plan: out is NULL");
+    if (nsh <= 0 || nauxsh <= 0) throw Error(DFX_EINVAL, "dfx_eri3_plan: empty basis");
+    const HostShells b = make_shells(shells, nsh, 3, "orbital basis");
+    const HostShells a = make_shells(aux, nauxsh, 4, "auxiliary basis");
+    dfx_eri3_sizes z{};
+    z.nbf = b.nbf;
+    z.naux = a.nbf;
+    z.ncols_tiled = tiled_cols(b.nbf);
+    z.bytes_B = (int64_t)a.nbf * z.ncols_tiled * 8;
+    z.bytes_raw = (int64_t)a.nbf * z.ncols_tiled * 8;
+    z.bytes_metric = (int64_t)a.nbf * a.nbf * 8 * 3;
+    z.bytes_setup_peak = z.bytes_B + z.bytes_raw + z.bytes_metric;
+    *out = z;
+  });
+}
+
+int dfx_B_unpack(const dfx_B* b, int q0, int q1, double* dev_out, void* stream) {
+  return guard([&] {
+    if (!b || !dev_out) throw Error(DFX_EINVAL, "dfx_B_unpack: NULL argument");
+    if (q0 < 0 || q1 > b->naux || q1 < q0) throw Error(DFX_EINVAL, "dfx_B_unpack: bad row range");
+    unpack_rows(b->hi.as<float>(), b->lo.as<float>(), b->ncols_t, b->nbf, q0, q1, dev_out, (hipStream_t)stream);
+    DFX_HIP(hipGetLastError());
+  });
+}
+
 int dfx_B_info_get(const dfx_B* b, dfx_B_info* info) {
   return guard([&] {
     if (!b || !info) throw Error(DFX_EINVAL, "dfx_B_info_get: NULL argument");
@@ -509,7 +536,6 @@ int dfx_jk(const dfx_B* bc, const double* dev_in, int kind, int nocc, int precis
     if (kind != DFX_DENSITY && kind != DFX_COCC) throw Error(DFX_EINVAL, "dfx_jk: bad kind");
     if (precision < DFX_FP64 || precision > DFX_BF16) throw Error(DFX_EINVAL, "dfx_jk: bad precision");
     if (kind == DFX_COCC && (nocc <= 0 || nocc > b->nbf)) throw Error(DFX_EINVAL, "dfx_jk: bad nocc");
-    if (kind == DFX_DENSITY && dev_K) throw Error(DFX_EUNSUPPORTED, "dfx_jk: K from a density needs DFX_COCC");
     hipStream_t st = (hipStream_t)stream;
     JKArgs a{b->hi.as<float>(), b->lo.as<float>(), b->naux, b->nbf, b->ncols_t, precision};
     const int nbf = b->nbf;
@@ -517,7 +543,7 @@ int dfx_jk(const dfx_B* bc, const double* dev_in, int kind, int nocc, int precis
     const size_t jw = sizeof(double) * (2 * (size_t)b->ncols_t + b->naux + 8);
     const size_t dbytes = (kind == DFX_COCC) ? sizeof(double) * (size_t)nbf * nbf : 0;
     if (dev_J) need = std::max(need, jw + dbytes);
-    if (dev_K) need = std::max(need, k_work_bytes(a, nocc));
+    if (dev_K && kind == DFX_COCC) need = std::max(need, k_work_bytes(a, nocc));
     char* w = static_cast<char*>(b->ensure_work(need));
     if (dev_J) {
       const double* D = dev_in;
@@ -534,7 +560,8 @@ int dfx_jk(const dfx_B* bc, const double* dev_in, int kind, int nocc, int precis
       }
       j_build(a, D, dev_J, reinterpret_cast<double*>(w), st);
     }
-    if (dev_K) k_build(a, dev_in, nocc, dev_K, w, st);
+    if (dev_K && kind == DFX_COCC) k_build(a, dev_in, nocc, dev_K, w, st);
+    if (dev_K && kind == DFX_DENSITY) k_from_density(a, dev_in, dev_K, st);
     DFX_HIP(hipGetLastError());
   });
 }

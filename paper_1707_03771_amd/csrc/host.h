@@ -55,6 +55,9 @@ struct DevShellSet {
 
 const double* rys_table_device();  // per current device, built on first use
 
+// K from a symmetric density by signed eigen-factorisation (scf.hip); synchronous
+void k_from_density(const JKArgs& a, const double* D, double* K, hipStream_t st);
+
 // learned starting guess (guess.cpp): predicted density, host [nbf][nbf]
 void guess_predict_density(const dfx_guess* g, const dfx_geom* geom, double* D, hipStream_t st);
 // throws unless the orbital shells are listed atom by atom with the model's shells per element

@@ -157,6 +157,26 @@ __global__ void export_kernel(const float* __restrict__ hi, const float* __restr
   out[(int64_t)blockIdx.y * ncols_p + c] = raw ? raw[o] : (double)hi[o] + (lo ? (double)lo[o] : 0.0);
 }
 
+// out[q - q0][mu][nu] = B_q (mu, nu) = hi + lo at the packed tile position
+__global__ void unpack_rows_kernel(const float* __restrict__ hi, const float* __restrict__ lo, int64_t ncols_t,
+                                   int nbf, int q0, double* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n2 = (int64_t)nbf * nbf;
+  if (i >= n2) return;
+  const int mu = (int)(i / nbf), nu = (int)(i % nbf);
+  const int r = mu > nu ? mu : nu, c = mu > nu ? nu : mu;
+  const int64_t o = (int64_t)(q0 + blockIdx.y) * ncols_t + tile_base(r >> 5, c >> 5) + ((r & 31) << 5) + (c & 31);
+  out[(int64_t)blockIdx.y * n2 + i] = (double)hi[o] + (double)lo[o];
+}
+
+void unpack_rows(const float* hi, const float* lo, int64_t ncols_t, int nbf, int q0, int q1, double* out,
+                 hipStream_t st) {
+  if (q1 <= q0) return;
+  const int64_t n2 = (int64_t)nbf * nbf;
+  const dim3 g((unsigned)((n2 + 255) / 256), q1 - q0);
+  hipLaunchKernelGGL(unpack_rows_kernel, g, dim3(256), 0, st, hi, lo, ncols_t, nbf, q0, out);
+}
+
 void export_rows(const float* hi, const float* lo, const double* raw, int64_t ncols_t, int q0, int q1,
                  const int64_t* toff, int64_t ncols_p, double* out, hipStream_t st) {
   if (q1 <= q0 || ncols_p <= 0) return;

@@ -91,6 +91,9 @@ void k_build_mixed(const JKArgs& a, const double* C, int nocc, double* K, void* 
                    KTimer* timer);
 // canonical packed rows [q1 - q0][ncols_p] (FP64) from the tiled storage;
 // toff[c] is the tile offset of packed column c
+// dense rows out[q1 - q0][nbf][nbf] (FP64 = hi + lo) from the tiled storage
+void unpack_rows(const float* hi, const float* lo, int64_t ncols_t, int nbf, int q0, int q1, double* out,
+                 hipStream_t st);
 void export_rows(const float* hi, const float* lo, const double* raw, int64_t ncols_t, int q0, int q1,
                  const int64_t* toff, int64_t ncols_p, double* out, hipStream_t st);
 

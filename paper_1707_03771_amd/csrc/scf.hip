@@ -169,6 +169,15 @@ struct Scf {
   }
 };
 
+// C_sel[mu][j] = W[idx[j]][mu] * scale[j]  (rows of W are eigenvectors)
+__global__ void gather_evec_kernel(const double* __restrict__ W, int n, const int* __restrict__ idx,
+                                   const double* __restrict__ scale, int r, double* __restrict__ Csel) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)n * r) return;
+  const int mu = (int)(i / r), j = (int)(i % r);
+  Csel[i] = W[(int64_t)idx[j] * n + mu] * scale[j];
+}
+
 // Solve the bordered DIIS system  [B -1; -1 0] [c; l] = [0; -1]  (Gaussian elimination
 // with partial pivoting).  Returns false if it is singular to working precision.
 static bool diis_solve(const std::vector<double>& Bm, int m, std::vector<double>& c) {
@@ -210,6 +219,64 @@ static bool diis_solve(const std::vector<double>& Bm, int m, std::vector<double>
   }
   c.assign(x.begin(), x.begin() + m);
   return true;
+}
+
+// K(D) = K(C+) - K(C-) with D = V diag(lambda) V^T, C+- = V_+- sqrt(|lambda_+-|);
+// eigenvalues below 1e-14 max|lambda| are dropped.  Columns go to k_build in
+// chunks of at most 512.  Synchronous.
+void k_from_density(const JKArgs& a, const double* D, double* K, hipStream_t st) {
+  const int n = a.nbf;
+  const int64_t n2 = (int64_t)n * n;
+  Scf S;
+  S.st = st;
+  struct Cleanup {
+    Scf& s;
+    ~Cleanup() {
+      if (s.rb) rocblas_destroy_handle(s.rb);
+    }
+  } cleanup{S};
+  if (rocblas_create_handle(&S.rb) != rocblas_status_success) throw Error(DFX_EHIP, "rocblas_create_handle failed");
+  rocblas_set_stream(S.rb, st);
+  S.eig_info.alloc(sizeof(int));
+  DevMem W(8 * n2), lam(8 * (size_t)n);
+  DFX_HIP(hipMemcpyAsync(W.p, D, 8 * n2, hipMemcpyDeviceToDevice, st));
+  S.syevd(W.as<double>(), n, lam.as<double>());
+  std::vector<double> l(n);
+  DFX_HIP(hipMemcpyAsync(l.data(), lam.p, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+  DFX_HIP(hipStreamSynchronize(st));
+  double lmax = 0.0;
+  for (double x : l) lmax = std::max(lmax, std::fabs(x));
+  std::vector<int> pos, neg;
+  for (int k = 0; k < n; ++k) {
+    if (l[k] > 1e-14 * lmax) pos.push_back(k);
+    else if (l[k] < -1e-14 * lmax) neg.push_back(k);
+  }
+  constexpr int CH = 512;
+  DevMem Cs(8 * (size_t)n * CH), Kt(8 * n2), idx_d(sizeof(int) * CH), sc_d(8 * CH);
+  DevMem work(k_work_bytes(a, std::min(CH, std::max(1, (int)std::max(pos.size(), neg.size())))));
+  fill_f64(K, (size_t)n2, 0.0, st);
+  for (int sign = 1; sign >= -1; sign -= 2) {
+    const std::vector<int>& sel = sign > 0 ? pos : neg;
+    for (size_t c0 = 0; c0 < sel.size(); c0 += CH) {
+      const int r = (int)std::min<size_t>(CH, sel.size() - c0);
+      std::vector<int> id(sel.begin() + c0, sel.begin() + c0 + r);
+      std::vector<double> sc(r);
+      for (int j = 0; j < r; ++j) sc[j] = std::sqrt(std::fabs(l[id[j]]));
+      DFX_HIP(hipMemcpyAsync(idx_d.p, id.data(), sizeof(int) * r, hipMemcpyHostToDevice, st));
+      DFX_HIP(hipMemcpyAsync(sc_d.p, sc.data(), 8 * (size_t)r, hipMemcpyHostToDevice, st));
+      hipLaunchKernelGGL(gather_evec_kernel, dim3(nblk((int64_t)n * r)), dim3(256), 0, st, W.as<double>(), n,
+                         idx_d.as<int>(), sc_d.as<double>(), r, Cs.as<double>());
+      k_build(a, Cs.as<double>(), r, Kt.as<double>(), work.p, st);
+      Comb cb{};
+      cb.m = 2;
+      cb.F[0] = K;
+      cb.c[0] = 1.0;
+      cb.F[1] = Kt.as<double>();
+      cb.c[1] = (double)sign;
+      hipLaunchKernelGGL(lincomb_kernel, dim3(nblk(n2)), dim3(256), 0, st, cb, K, n2);
+      DFX_HIP(hipStreamSynchronize(st));  // host vectors of this chunk go out of scope
+    }
+  }
 }
 
 }  // namespace dfx

@@ -61,3 +61,26 @@ def test_argument_errors_are_status_codes():
     # jk / B calls on a NULL handle
     assert lib.dfx_jk(None, None, 1, 1, 0, None, None, None) == dfx.EINVAL
     assert lib.dfx_B_info_get(None, None) == dfx.EINVAL
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdfx.so not built")
+def test_eri3_plan_sizes_host_only():
+    """dfx_eri3_plan touches no GPU: counts and byte sizes from the shells."""
+    import paper_1707_03771_amd as dfx
+    import workloads as W
+    _, _, sh, ax = W.workload("h4")
+    z = dfx.eri3_plan(sh, ax)
+    assert (z["nbf"], z["naux"], z["ncols_tiled"]) == (24, 100, 1024)
+    assert z["bytes_B"] == 100 * 1024 * 8 and z["bytes_raw"] == z["bytes_B"]
+    assert z["bytes_setup_peak"] == z["bytes_B"] + z["bytes_raw"] + 3 * 100 * 100 * 8
+    _, _, sh, ax = W.workload("water4")
+    z = dfx.eri3_plan(sh, ax)
+    nt = 1536 // 32
+    assert (z["nbf"], z["naux"], z["ncols_tiled"]) == (1536, 6784, nt * (nt + 1) // 2 * 1024)
+    with pytest.raises(dfx.DfxError) as e:
+        dfx.eri3_plan([], ax)
+    assert e.value.code == dfx.EINVAL
+    bad = [dict(sh[0], l=4)]
+    with pytest.raises(dfx.DfxError) as e:
+        dfx.eri3_plan(bad, ax)
+    assert e.value.code == dfx.EUNSUPPORTED

@@ -1,0 +1,270 @@
+"""Parity at the benchmark configurations' full sizes, through the C-ABI, in the
+launch configurations the benchmark times, on outputs the oracle can compute
+one by one, plus properties that hold at any size.
+
+* 40 C atoms (1200 / 3600 functions): screening lists bit-exact; sampled raw
+  (mu nu|P) blocks; the leading rows of B (they depend only on the leading
+  block of the metric); K on the blocks of sampled shells, in FP64, FP32 and
+  BF16, from the oracle's exact B columns of every pair holding those shells;
+  J rows for a density supported on two shells; K from a density against K
+  from C_occ; K symmetric positive semidefinite.
+* (H2O)64 (1536 / 6784 functions, 320 occupied): lists, leading rows of B, K
+  blocks with nocc = 320 (the FP64 half transform's four 1696-row launches);
+  DF-RHF in the mixed schedule from the learned guess and from the core
+  guess against plain FP64, and the converged density's idempotency.
+
+Tolerances: integrals 1e-13 of the block scale; FP64 B, J, K 1e-9 absolute
+(K also relative to its largest element when that exceeds one), except where
+the metric's condition number puts the problem's own FP64 noise floor above
+it: the floor is measured with the oracle (K from a metric perturbed at the
+rounding level) and the bound is four times the floor; FP32 K 1e-5 and BF16
+K 2e-2 of max|K| (unit roundoffs 6e-8 and 3.9e-3 amplified by accumulation
+over up to nbf terms); energies 1e-6 Eh between schedules.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dfx():
+    import paper_1707_03771_amd as m
+    return m
+
+
+def sub_screen(scr, sel, aux_shells=None):
+    """Screen restricted to pairs sel (and optionally to the leading aux shells)."""
+    keep = scr.keep[sel] if aux_shells is None else scr.keep[sel][:, :aux_shells]
+    col = np.concatenate([[0], np.cumsum(np.diff(scr.col_off)[sel])]).astype(np.int64)
+    return O.Screen(scr.pairs[sel], col, keep, scr.tau)
+
+
+class Columns:
+    """Exact oracle B columns of every kept pair that holds one of `shells`."""
+
+    def __init__(self, bas, aux, scr, L, shells):
+        self.bas = bas
+        hold = np.isin(scr.pairs[:, 0], shells) | np.isin(scr.pairs[:, 1], shells)
+        self.sel = np.where(hold)[0]
+        self.sub = sub_screen(scr, self.sel)
+        raw = O.eri3_packed(bas, aux, self.sub)
+        self.B = sla.solve_triangular(L, raw, lower=True)      # [naux][cols]
+        self.mu, self.nu = O.pair_index(bas, self.sub)
+
+    def rows(self, funcs):
+        """B_Q[mu][lambda] for mu in funcs, all lambda: [naux][len(funcs)][nbf]."""
+        n = self.bas.nbf
+        idx = {f: k for k, f in enumerate(funcs)}
+        out = np.zeros((self.B.shape[0], len(funcs), n))
+        for c, (m, v) in enumerate(zip(self.mu, self.nu)):
+            if m in idx:
+                out[:, idx[m], v] = self.B[:, c]
+            if v in idx and v != m:
+                out[:, idx[v], m] = self.B[:, c]
+        return out
+
+
+def funcs_of(bas, shells):
+    return [f for s in shells for f in range(bas.foff[s], bas.foff[s] + bas.size[s])]
+
+
+def leading_rows(bas, aux_shells, scr, J2, nshell_aux):
+    """Rows Q < k of B, k = functions of the first nshell_aux aux shells:
+    L[:k, :k]^-1 raw[:k] (a leading block of the Cholesky factor depends only
+    on the leading block of the metric)."""
+    aux_sub = O.Basis(aux_shells[:nshell_aux])
+    raw = O.eri3_packed(bas, aux_sub, sub_screen(scr, np.arange(len(scr.pairs)), nshell_aux))
+    k = aux_sub.nbf
+    Lk = sla.cholesky(J2[:k, :k], lower=True)
+    return sla.solve_triangular(Lk, raw, lower=True)
+
+
+def k_blocks(cols, funcs, C):
+    """K[funcs][funcs] = sum_Q (B_Q C)[funcs] (B_Q C)[funcs]^T."""
+    R = cols.rows(funcs)                                   # [q][m][n]
+    nq, m, n = R.shape
+    X = (R.reshape(nq * m, n) @ C).reshape(nq, m, -1)      # [q][m][i]
+    Xt = X.transpose(1, 0, 2).reshape(m, -1)
+    return Xt @ Xt.T
+
+
+def fp64_floor(bas, aux, scr, J2, shells, funcs, C, K):
+    """The problem's own FP64 noise floor for these K blocks: the change when the
+    metric is perturbed at the rounding level (relative 2.2e-16, symmetric).
+    K depends on J_PQ^-1, so this grows with the metric's condition number."""
+    E = np.random.default_rng(0).uniform(-1.0, 1.0, size=J2.shape)
+    Lp = sla.cholesky(J2 * (1.0 + 1.1e-16 * (E + E.T)), lower=True)
+    return np.abs(k_blocks(Columns(bas, aux, scr, Lp, shells), funcs, C) - K).max()
+
+
+# ---- 40 carbons -------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c40(dfx):
+    elems, xyz, sh, ax = W.workload("c40")
+    bas, aux = O.Basis(sh), O.Basis(ax)
+    Qab, QC = O.schwarz(bas, aux)
+    scr = O.screen(bas, aux, Qab, QC, 1e-12)
+    J2 = O.eri2(aux)
+    L = sla.cholesky(J2, lower=True)
+    B = dfx.eri3(sh, ax, tau=1e-12, flags=dfx.KEEP_RAW)
+    torch.cuda.synchronize()
+    C = W.random_orthonormal(bas.nbf, 120, seed=1)
+    yield dict(sh=sh, ax=ax, bas=bas, aux=aux, scr=scr, J2=J2, L=L, B=B, C=C)
+    B.free()
+
+
+def test_c40_lists_bit_exact(c40):
+    pairs, off, keep, gQab, gQC = c40["B"].lists(keep=True)
+    scr = c40["scr"]
+    assert c40["B"].info["npairs"] == len(scr.pairs)
+    if scr.margin > 1e-12:
+        assert np.array_equal(pairs, scr.pairs)
+        assert np.array_equal(off, scr.col_off)
+        assert np.array_equal(keep.astype(bool), scr.keep)
+
+
+def test_c40_sampled_raw_blocks(c40, dfx):
+    bas, aux, scr, B = c40["bas"], c40["aux"], c40["scr"], c40["B"]
+    rng = np.random.default_rng(7)
+    kept = np.argwhere(scr.keep)
+    for k, c in kept[rng.choice(len(kept), size=40, replace=False)]:
+        k, c = int(k), int(c)
+        a, b = int(scr.pairs[k][0]), int(scr.pairs[k][1])
+        q0 = aux.foff[c]
+        rows = B.export(what=dfx.EXPORT_RAW, q0=q0, q1=q0 + aux.size[c]).cpu().numpy()
+        g = rows[:, scr.col_off[k]:scr.col_off[k + 1]]
+        r = O.eri3_block(bas, a, b, aux, c).reshape(-1, aux.size[c]).T
+        assert np.abs(g - r).max() <= 1e-13 * max(np.abs(r).max(), 1e-300) + 1e-15, (a, b, c)
+
+
+def test_c40_leading_rows_of_B(c40, dfx):
+    ref = leading_rows(c40["bas"], c40["ax"], c40["scr"], c40["J2"], 6)
+    g = c40["B"].export(what=0, q0=0, q1=ref.shape[0]).cpu().numpy()
+    assert np.abs(g - ref).max() <= 1e-9
+
+
+@pytest.mark.parametrize("prec,tol", [("FP64", None), ("FP32", 1e-5), ("BF16", 2e-2)])
+def test_c40_k_blocks(c40, dfx, prec, tol):
+    bas = c40["bas"]
+    shells = [3, 104, 257, 399]          # s, p, d, f of different atoms (4s3p2d1f per C)
+    assert sorted(set(int(bas.l[s]) for s in shells)) == [0, 1, 2, 3]
+    cols = Columns(bas, c40["aux"], c40["scr"], c40["L"], shells)
+    funcs = funcs_of(bas, shells)
+    Kr = k_blocks(cols, funcs, c40["C"])
+    _, K = dfx.jk(c40["B"], torch.tensor(c40["C"], device="cuda"), precision=getattr(dfx, prec), want_j=False)
+    Kg = K.cpu().numpy()[np.ix_(funcs, funcs)]
+    err = np.abs(Kg - Kr).max()
+    if tol is None:
+        assert err <= 1e-9 * max(1.0, np.abs(Kr).max()), err
+    else:
+        full = K.abs().max().item()
+        assert err <= tol * full, (prec, err, full)
+
+
+def test_c40_j_rows_for_local_density(c40, dfx):
+    bas = c40["bas"]
+    a, b = 120, 121                      # two shells of one atom
+    cols = Columns(bas, c40["aux"], c40["scr"], c40["L"], [a, b])
+    fa, fb = funcs_of(bas, [a]), funcs_of(bas, [b])
+    n = bas.nbf
+    rng = np.random.default_rng(3)
+    D = np.zeros((n, n))
+    idx = fa + fb
+    A = rng.normal(size=(len(idx), len(idx)))
+    D[np.ix_(idx, idx)] = A + A.T
+    rows = cols.rows(idx)                             # B_Q[mu in a u b][all]
+    gamma = np.einsum("qmn,mn->q", rows[:, :, idx], D[np.ix_(idx, idx)])
+    Jr = np.einsum("q,qmn->mn", gamma, rows)          # J rows mu in a u b
+    J, _ = dfx.jk(c40["B"], torch.tensor(D, device="cuda"), kind=dfx.DENSITY, want_k=False)
+    assert np.abs(J.cpu().numpy()[idx] - Jr).max() <= 1e-9 * max(1.0, np.abs(Jr).max())
+
+
+def test_c40_k_properties(c40, dfx):
+    Cg = torch.tensor(c40["C"], device="cuda")
+    J1, K = dfx.jk(c40["B"], Cg)
+    _, Kd = dfx.jk(c40["B"], Cg @ Cg.T, kind=dfx.DENSITY, want_j=False)
+    assert (Kd - K).abs().max().item() <= 1e-12 * K.abs().max().item()
+    Kn = K.cpu().numpy()
+    assert np.array_equal(Kn, Kn.T)
+    w = np.linalg.eigvalsh(Kn)
+    assert w.min() >= -1e-10 * w.max()
+    # J is linear in D
+    C2 = torch.tensor(W.random_orthonormal(c40["bas"].nbf, 30, seed=9), device="cuda")
+    J2, _ = dfx.jk(c40["B"], C2, want_k=False)
+    J12, _ = dfx.jk(c40["B"], Cg @ Cg.T + C2 @ C2.T, kind=dfx.DENSITY, want_k=False)
+    assert (J12 - J1 - J2).abs().max().item() <= 1e-12 * J12.abs().max().item()
+
+
+# ---- (H2O)64 ------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def water(dfx):
+    elems, xyz, sh, ax = W.workload("water4")
+    bas, aux = O.Basis(sh), O.Basis(ax)
+    Qab, QC = O.schwarz(bas, aux)
+    scr = O.screen(bas, aux, Qab, QC, 1e-12)
+    J2 = O.eri2(aux)
+    L = sla.cholesky(J2, lower=True)
+    yield dict(elems=elems, xyz=xyz, sh=sh, ax=ax, bas=bas, aux=aux, scr=scr, J2=J2, L=L)
+
+
+def test_water_lists_B_rows_and_k_blocks(water, dfx):
+    B = dfx.eri3(water["sh"], water["ax"])
+    try:
+        scr = water["scr"]
+        pairs, off, _, _, _ = B.lists()
+        if scr.margin > 1e-12:
+            assert np.array_equal(pairs, scr.pairs) and np.array_equal(off, scr.col_off)
+        ref = leading_rows(water["bas"], water["ax"], scr, water["J2"], 5)
+        g = B.export(what=0, q0=0, q1=ref.shape[0]).cpu().numpy()
+        assert np.abs(g - ref).max() <= 1e-9
+        C = W.random_orthonormal(water["bas"].nbf, 320, seed=2)
+        shells = [0, 5, 400, 767]
+        cols = Columns(water["bas"], water["aux"], scr, water["L"], shells)
+        funcs = funcs_of(water["bas"], shells)
+        Kr = k_blocks(cols, funcs, C)
+        _, K = dfx.jk(B, torch.tensor(C, device="cuda"), want_j=False)
+        err = np.abs(K.cpu().numpy()[np.ix_(funcs, funcs)] - Kr).max()
+        # kappa(J_PQ) >= 8.6e9 here: the 1e-9 bound gives way to the FP64 floor
+        floor = fp64_floor(water["bas"], water["aux"], scr, water["J2"], shells, funcs, C, Kr)
+        print(f"(H2O)64 K blocks: |dK| = {err:.2e}, FP64 floor {floor:.2e}, kappa_lb {B.info['kappa_lb']:.2e}")
+        assert err <= max(1e-9 * max(1.0, np.abs(Kr).max()), 4.0 * floor), (err, floor)
+    finally:
+        B.free()
+
+
+def test_water_scf_schedules_agree(water, dfx):
+    """Plain FP64, mixed from the core guess and mixed from a learned guess
+    reach the same energy; the converged density is idempotent in S."""
+    xyz, sh, ax = water["xyz"], water["sh"], water["ax"]
+    Z = W.charges(water["elems"])
+    conv = dict(conv_dE=1e-7, conv_err=1e-5)
+    Ep, Cp, _, ip = dfx.scf(xyz, Z, sh, ax, **conv)
+    assert ip["converged"]
+    nocc = ip["nocc"]
+    D = Cp[:, :nocc] @ Cp[:, :nocc].T
+    S = dfx.int1e(sh, xyz, Z)[0].cpu().numpy()
+    assert np.abs(D @ S @ D - D).max() <= 1e-6 * np.abs(D).max()
+    assert abs(np.trace(D @ S) - nocc) <= 1e-8 * nocc
+    Em, _, _, im = dfx.scf(xyz, Z, sh, ax, want_c=False, schedule=dfx.SCHED_MIXED, **conv)
+    assert im["converged"] and abs(Em - Ep) <= 1e-6
+    # a small learned model (trained here on seeded 2x2x2 clusters)
+    m = dfx.GuessModel({8: [0, 0, 0, 1, 1, 2], 1: [0, 0, 1]}, hidden=64, depth=2, seed=3)
+    for sd in range(1, 7):
+        e2, x2 = W.water_cluster(side=2, seed=2000 + sd)
+        s2, a2 = W.basis_for("water", e2, x2)
+        Z2 = W.charges(e2)
+        _, C2, _, i2 = dfx.scf(x2, Z2, s2, a2, **conv)
+        m.add(x2, Z2, dfx.lowdin(x2, Z2, s2, C2[:, :i2["nocc"]] @ C2[:, :i2["nocc"]].T))
+    m.train(epochs=40, batch=64)
+    El, _, _, il = dfx.scf(xyz, Z, sh, ax, want_c=False, schedule=dfx.SCHED_MIXED, model=m, **conv)
+    assert il["converged"] and il["guess_fallback"] == 0
+    assert abs(El - Ep) <= 1e-6
+    print(f"(H2O)64: plain {ip['niter']} iterations, mixed core {im['niter']}, mixed learned {il['niter']}")

@@ -107,6 +107,38 @@ def test_jk_fp64(case, dfx):
     assert np.abs(_np(J2g) - Jr).max() <= 1e-9
 
 
+def test_k_from_density(case, dfx):
+    """K for a density input (signed eigen-factorisation of D): equal to the
+    C_occ route for D = C C^T to 1e-12 of max|K|, and to the oracle's
+    sum_Q B_Q D B_Q for an indefinite symmetric D to 1e-9."""
+    name, sh, ax, ref, B = case
+    bas, aux, Qab, QC, scr, raw, J2, L, Bref = ref
+    df = O.DF(bas, aux, scr, Bref, L)
+    rng = np.random.default_rng(4)
+    nocc = max(2, min(12, bas.nbf // 5))
+    C = torch.tensor(np.linalg.qr(rng.normal(size=(bas.nbf, nocc)))[0], device="cuda")
+    _, Kc = dfx.jk(B, C, kind=dfx.COCC, want_j=False)
+    _, Kd = dfx.jk(B, C @ C.T, kind=dfx.DENSITY, want_j=False)
+    assert (Kd - Kc).abs().max().item() <= 1e-12 * Kc.abs().max().item()
+    A = rng.normal(size=(bas.nbf, bas.nbf)) / bas.nbf
+    D = A + A.T
+    Jr, Kr = O.jk(df, D=D)
+    Jg, Kg = dfx.jk(B, torch.tensor(D, device="cuda"), kind=dfx.DENSITY)
+    assert np.abs(_np(Kg) - Kr).max() <= 1e-9
+    assert np.abs(_np(Jg) - Jr).max() <= 1e-9
+
+
+def test_unpack_rows(case, dfx):
+    """dfx_B_unpack: dense symmetric rows of B equal the oracle's B scattered
+    to (mu, nu) and (nu, mu), including a ragged last row block."""
+    name, sh, ax, ref, B = case
+    bas, scr, Bref = ref[0], ref[4], ref[8]
+    q0, q1 = max(0, B.naux - 7), B.naux
+    dense = O.unpack(Bref, bas, scr, rows=np.arange(q0, q1))
+    assert np.abs(_np(B.unpack(q0, q1)) - dense).max() <= 1e-9
+    assert np.abs(_np(B.unpack(0, 1))[0] - O.unpack(Bref, bas, scr, rows=[0])[0]).max() <= 1e-9
+
+
 def test_one_electron(case, dfx):
     name, sh, ax, ref, B = case
     rng = np.random.default_rng(2)
