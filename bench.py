@@ -157,10 +157,12 @@ def cpu_baseline(elems, xyz, sh, ax, niter, budget_pairs=250, q_rows=16, seed=0)
             "phases_s": {k: round(v, 3) for k, v in t_all.items()}}
 
 
-def train_guess(dfx, n27=8, n8=16, epochs=80, batch=128, seed=5):
+def train_guess(dfx, n27=8, n8=16, epochs=80, batch=128, seed=5, sigma=0.04):
     """Guess model for water from converged GPU densities of seeded clusters:
     3x3x3 clusters hold every coordination a water has in the 4x4x4 cluster
-    (corner to fully surrounded), 2x2x2 clusters add surface environments."""
+    (corner to fully surrounded), 2x2x2 clusters add surface environments.
+    Every atom is displaced by N(0, sigma^2) per coordinate, so that bond
+    lengths and angles vary as they do along a trajectory."""
     basis = {8: [0, 0, 0, 1, 1, 2], 1: [0, 0, 1]}
     m = dfx.GuessModel(basis, rc=8.0, rc_env=6.0, hidden=256, depth=3, seed=seed)
     t0 = time.perf_counter()
@@ -168,6 +170,7 @@ def train_guess(dfx, n27=8, n8=16, epochs=80, batch=128, seed=5):
     for side, seeds in ((3, range(1, 1 + n27)), (2, range(1, 1 + n8))):
         for sd in seeds:
             elems, xyz = W.water_cluster(side=side, seed=1000 + sd)
+            xyz = xyz + np.random.default_rng(5000 + sd).normal(0.0, sigma, size=xyz.shape)
             sh, ax = W.basis_for("water", elems, xyz)
             Z = W.charges(elems)
             E, C, _, info = dfx.scf(xyz, Z, sh, ax, schedule=dfx.SCHED_MIXED, conv_dE=1e-8, conv_err=1e-6)
@@ -180,7 +183,8 @@ def train_guess(dfx, n27=8, n8=16, epochs=80, batch=128, seed=5):
     loss = m.train(epochs=epochs, batch=batch, lr=1e-3)
     t_train = time.perf_counter() - t1
     log(f"guess training: {epochs} epochs in {t_train:.1f} s, loss {loss[0]:.3f} -> {loss[-1]:.4f}")
-    return m, {"geometries": f"{n27} x (H2O)27 + {n8} x (H2O)8, seeds 1001..", "data_s": round(t_data, 2),
+    return m, {"geometries": f"{n27} x (H2O)27 + {n8} x (H2O)8, seeds 1001.., per-atom sigma {sigma} bohr",
+               "data_s": round(t_data, 2),
                "train_s": round(t_train, 2), "epochs": epochs, "batch": batch,
                "samples": sum(t["samples"] for t in m.types()), "loss_first": round(float(loss[0]), 4),
                "loss_last": round(float(loss[-1]), 4)}
@@ -202,6 +206,125 @@ def profile_jk(dfx, torch, sh, ax, nocc, prec):
     B.free()
 
 
+def _shape_ls(kind, elem):
+    return [l for l, n in enumerate(W.ORB_SHAPE[kind][elem]) for _ in range(n)]
+
+
+def _stats(v):
+    v = np.asarray(v, float)
+    return {"mean": round(float(v.mean()), 4), "median": round(float(np.median(v)), 4),
+            "min": round(float(v.min()), 4), "max": round(float(v.max()), 4)}
+
+
+def eval_ring_guess(dfx, ntrain, ntest, epochs, batch):
+    """Seeded C8H16 crowns: train the guess on ntrain converged densities (seeds
+    0..), then on ntest unseen crowns (seeds 1600..) compare plain FP64 DF-RHF
+    from the learned guess with the core guess at |dE| < 1e-8."""
+    m = dfx.GuessModel({6: _shape_ls("ring", "C"), 1: _shape_ls("ring", "H")}, rc=8.0, rc_env=6.0,
+                       hidden=256, depth=3, seed=4)
+    conv = dict(conv_dE=1e-8, conv_err=1e-7)
+    elems, xyz, sh, ax = W.workload("ring", seed=0)
+    dfx.scf(xyz, W.charges(elems), sh, ax, want_c=False, **conv)          # warm-up
+    t0 = time.perf_counter()
+    for sd in range(ntrain):
+        elems, xyz, sh, ax = W.workload("ring", seed=sd)
+        Z = W.charges(elems)
+        _, C, _, info = dfx.scf(xyz, Z, sh, ax, **conv)
+        nocc = info["nocc"]
+        m.add(xyz, Z, dfx.lowdin(xyz, Z, sh, C[:, :nocc] @ C[:, :nocc].T))
+        if sd % 100 == 99:
+            log(f"ring training data: {sd + 1} geometries, {time.perf_counter() - t0:.1f} s")
+    t_data = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    loss = m.train(epochs=epochs, batch=batch, lr=1e-3)
+    t_train = time.perf_counter() - t1
+    log(f"ring guess training: {epochs} epochs in {t_train:.1f} s, loss {loss[0]:.3f} -> {loss[-1]:.4f}")
+    it_c, it_l, w_c, w_l, dE, nfb = [], [], [], [], [], 0
+    for sd in range(1600, 1600 + ntest):
+        elems, xyz, sh, ax = W.workload("ring", seed=sd)
+        Z = W.charges(elems)
+        ta = time.perf_counter()
+        Ec, _, _, ic = dfx.scf(xyz, Z, sh, ax, want_c=False, **conv)
+        tb = time.perf_counter()
+        El, _, _, il = dfx.scf(xyz, Z, sh, ax, want_c=False, model=m, **conv)
+        tc = time.perf_counter()
+        it_c.append(ic["niter"])
+        it_l.append(il["niter"])
+        w_c.append(tb - ta)
+        w_l.append(tc - tb)
+        dE.append(abs(El - Ec))
+        nfb += il["guess_fallback"] != 0
+    out = {"metric": "learned-guess gain, C8H16 crowns (plain FP64 DF-RHF, |dE| < 1e-8)",
+           "workload": "ring: crown C8H16, C [4s3p2d1f] / [8s6p5d3f2g], H [2s1p] / [4s3p2d], sigma 0.1 bohr",
+           "train": {"geometries": ntrain, "seeds": f"0..{ntrain - 1}", "data_s": round(t_data, 2),
+                     "train_s": round(t_train, 2), "epochs": epochs, "batch": batch,
+                     "samples": sum(t["samples"] for t in m.types()), "loss_first": round(float(loss[0]), 4),
+                     "loss_last": round(float(loss[-1]), 4)},
+           "test": {"geometries": ntest, "seeds": f"1600..{1600 + ntest - 1}",
+                    "iterations_core": _stats(it_c), "iterations_learned": _stats(it_l),
+                    "wall_core_s": _stats(w_c), "wall_learned_s": _stats(w_l),
+                    "max_abs_dE_learned_vs_core": float(max(dE)), "fallbacks": nfb}}
+    print(json.dumps(out))
+
+
+def eval_alkane(dfx):
+    """C30H62: plain FP64 against the mixed schedules (FP32 -> FP64 and
+    BF16 -> FP32 -> FP64), each |dE| against the oracle's stored energy."""
+    elems, xyz, sh, ax = W.workload("alkane", seed=0)
+    Z = W.charges(elems)
+    gold = os.path.join(ROOT, "tests", "golden", "alkane_df_rhf.json")
+    E_or = json.load(open(gold))["E"] if os.path.exists(gold) else None
+    conv = dict(conv_dE=1e-9, conv_err=1e-7)
+    dfx.scf(xyz, Z, sh, ax, want_c=False, **conv)                                     # warm-up
+    runs = {}
+    for tag, kw in (("plain_fp64", {}), ("mixed_fp32", dict(schedule=dfx.SCHED_MIXED, mixed_prec=dfx.FP32)),
+                    ("mixed_bf16", dict(schedule=dfx.SCHED_MIXED, mixed_prec=dfx.BF16))):
+        t0 = time.perf_counter()
+        E, _, _, i = dfx.scf(xyz, Z, sh, ax, want_c=False, **conv, **kw)
+        runs[tag] = {"wall_s": round(time.perf_counter() - t0, 3), "E": E, "niter": i["niter"],
+                     "n_mixed": i["n_mixed"], "dE_vs_oracle": (E - E_or) if E_or is not None else None}
+        log(f"alkane {tag}: E = {E:.10f} iters {i['niter']} wall {runs[tag]['wall_s']:.2f} s")
+    print(json.dumps({"metric": "C30H62 DF-RHF: plain FP64 vs mixed, |dE| vs the oracle",
+                      "workload": "alkane: zigzag C30H62 seed 0, C [3s2p1d] / [7s5p4d2f], H [2s1p] / [4s3p2d]",
+                      "oracle_E": E_or, "runs": runs}))
+
+
+def eval_trajectory(dfx, nframes):
+    """(H2O)64 over a seeded trajectory: per frame, mixed + learned (timed) and
+    plain FP64 from the core guess; as context, mixed from the previous frame's
+    orbitals."""
+    model, learned = train_guess(dfx)
+    elems, xyz, sh, ax = W.workload("water4")
+    Z = W.charges(elems)
+    frames = W.trajectory(xyz, nframes, seed=1)
+    conv = dict(conv_dE=1e-7, conv_err=1e-5)
+    rows, C_prev = [], None
+    for k, x in enumerate(frames):
+        shx, axx = W.shells_at(sh, xyz, x), W.shells_at(ax, xyz, x)
+        t0 = time.perf_counter()
+        El, _, _, il = dfx.scf(x, Z, shx, axx, want_c=False, schedule=dfx.SCHED_MIXED, model=model, **conv)
+        t1 = time.perf_counter()
+        Ep, Cp, _, ip = dfx.scf(x, Z, shx, axx, **conv)
+        t2 = time.perf_counter()
+        row = {"frame": k, "learned_mixed_s": round(t1 - t0, 3), "learned_mixed_iters": il["niter"],
+               "plain_fp64_s": round(t2 - t1, 3), "plain_fp64_iters": ip["niter"], "dE": El - Ep}
+        if C_prev is not None:
+            t3 = time.perf_counter()
+            Eq, _, _, iq = dfx.scf(x, Z, shx, axx, want_c=False, schedule=dfx.SCHED_MIXED, init=C_prev,
+                                   guess=dfx.GUESS_CINIT, **conv)
+            row.update(prev_frame_mixed_s=round(time.perf_counter() - t3, 3), prev_frame_mixed_iters=iq["niter"],
+                       dE_prev=Eq - Ep)
+        C_prev = Cp
+        rows.append(row)
+        log(json.dumps(row))
+    tl = sum(r["learned_mixed_s"] for r in rows)
+    tp = sum(r["plain_fp64_s"] for r in rows)
+    print(json.dumps({"metric": "(H2O)64 trajectory: mixed + learned vs plain FP64, per frame",
+                      "frames": nframes, "learned_guess": learned, "total_learned_mixed_s": round(tl, 3),
+                      "total_plain_fp64_s": round(tp, 3), "speedup": round(tp / tl, 3),
+                      "max_abs_dE": max(abs(r["dE"]) for r in rows), "per_frame": rows}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +338,12 @@ def main():
                     help="step k runs frame k of a seeded trajectory (per-atom sigma 0.02 bohr)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 reference run")
     ap.add_argument("--no-context", action="store_true", help="skip the core-guess context run")
+    ap.add_argument("--eval", default=None, choices=["ring-guess", "alkane", "trajectory"],
+                    help="evaluation runs beside the benchmark line (each prints its own JSON line)")
+    ap.add_argument("--ntrain", type=int, default=1600)
+    ap.add_argument("--ntest", type=int, default=400)
+    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--frames", type=int, default=10)
     ap.add_argument("--profile-jk", default=None, choices=["fp64", "fp32", "bf16"],
                     help="counter-run driver: build B, one J/K build in this precision with the SCF's "
                          "launch configuration, and a 1 GiB elementwise copy as the HBM calibration")
@@ -232,6 +361,15 @@ def main():
     elems, xyz, sh, ax = W.workload(a.workload)
     Z = W.charges(elems)
     nocc = W.nocc_of(elems)
+    if a.eval == "ring-guess":
+        eval_ring_guess(dfx, a.ntrain, a.ntest, a.epochs, 256)
+        return
+    if a.eval == "alkane":
+        eval_alkane(dfx)
+        return
+    if a.eval == "trajectory":
+        eval_trajectory(dfx, a.frames)
+        return
     if a.profile_jk:
         profile_jk(dfx, torch, sh, ax, nocc, {"fp64": dfx.FP64, "fp32": dfx.FP32, "bf16": dfx.BF16}[a.profile_jk])
         return

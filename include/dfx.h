@@ -321,7 +321,8 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
  *   orientations and averaged.
  * Descriptors of an atom: one-hot(Z_a) [3], its environment [3 x 8 x 9].
  * Network: widths (d_in, hidden x depth, block size), SiLU between layers,
- *   inputs and targets standardised per component on the training set,
+ *   inputs and targets standardised per component on the training set (input
+ *   scales floored at 0.1, target scales at 1e-6),
  *   mean-squared-error loss, Adam (beta 0.9 / 0.999, eps 1e-8).
  * All arrays host-side and row-major unless stated.  Not thread-safe per model.
  */

@@ -619,7 +619,10 @@ int dfx_guess_train(dfx_guess* g, int epochs, int batch, double lr, double* loss
             T.tstd[i] += d * d / T.nsamp;
           }
         }
-        for (auto& x : T.fstd) x = std::max(std::sqrt(x), 1e-6);
+        // Descriptors are O(0.1 - 5).  One that barely varies over the training set
+        // (a rigid bond length, a one-hot) keeps a scale of at least 0.1, so that a
+        // small departure at prediction time is not blown up into a huge input.
+        for (auto& x : T.fstd) x = std::max(std::sqrt(x), 0.1);
         for (auto& x : T.tstd) x = std::max(std::sqrt(x), 1e-6);
         init_theta(T, g->seed * 1000003ull + ti);
         T.normalised = true;
@@ -639,22 +642,28 @@ int dfx_guess_train(dfx_guess* g, int epochs, int batch, double lr, double* loss
       std::vector<int> perm(T.nsamp);
       std::iota(perm.begin(), perm.end(), 0);
       std::mt19937_64 rng(g->seed * 7919ull + ti);
+      // minibatch losses accumulate on the device; the host reads them once per epoch
+      DevMem lacc(sizeof(double) * (size_t)std::max(epochs, 1));
+      DFX_HIP(hipMemsetAsync(lacc.p, 0, lacc.n, st));
+      std::vector<int> nbatch(epochs, 0);
       for (int ep = 0; ep < epochs; ++ep) {
         std::shuffle(perm.begin(), perm.end(), rng);
-        DFX_HIP(hipMemcpy(idx.p, perm.data(), sizeof(int) * perm.size(), hipMemcpyHostToDevice));
-        double lsum = 0.0;
-        int nbatch = 0;
+        DFX_HIP(hipMemcpyAsync(idx.p, perm.data(), sizeof(int) * perm.size(), hipMemcpyHostToDevice, st));
         for (int s0 = 0; s0 + bs <= T.nsamp; s0 += bs) {
           gather_rows(Xd.as<float>(), idx.as<int>() + s0, bs, T.nin, xb.as<float>(), st);
           gather_rows(Td.as<float>(), idx.as<int>() + s0, bs, T.nout, tb.as<float>(), st);
-          lsum += mlp_loss_grad(T.widths, T.theta.as<float>(), xb.as<float>(), tb.as<float>(), bs, grad.as<float>(),
-                                work.as<float>(), st);
+          mlp_loss_grad_acc(T.widths, T.theta.as<float>(), xb.as<float>(), tb.as<float>(), bs, grad.as<float>(),
+                            work.as<float>(), lacc.as<double>() + ep, st);
           mlp_adam(T.theta.as<float>(), grad.as<float>(), T.m.as<float>(), T.v.as<float>(),
                    (int64_t)T.theta_h.size(), ++T.adam_step, (float)lr, st);
-          ++nbatch;
+          ++nbatch[ep];
         }
-        eloss[ep] += (nbatch ? lsum / nbatch : 0.0) * T.nsamp;
+        // the permutation buffer is rewritten next epoch: wait for this epoch's gathers
+        DFX_HIP(hipStreamSynchronize(st));
       }
+      std::vector<double> lh(std::max(epochs, 1), 0.0);
+      DFX_HIP(hipMemcpy(lh.data(), lacc.p, sizeof(double) * lh.size(), hipMemcpyDeviceToHost));
+      for (int ep = 0; ep < epochs; ++ep) eloss[ep] += (nbatch[ep] ? lh[ep] / nbatch[ep] : 0.0) * T.nsamp;
       DFX_HIP(hipMemcpy(T.theta_h.data(), T.theta.p, sizeof(float) * T.theta_h.size(), hipMemcpyDeviceToHost));
       total += T.nsamp;
     }

@@ -13,6 +13,9 @@ void mlp_forward(const std::vector<int>& widths, const float* theta, const float
 // mean squared error over all outputs and its gradient in theta (synchronises st)
 double mlp_loss_grad(const std::vector<int>& widths, const float* theta, const float* X, const float* T, int batch,
                      float* grad, float* work, hipStream_t st);
+// the same without synchronising: the batch's mean squared error is added to *loss_acc (device)
+void mlp_loss_grad_acc(const std::vector<int>& widths, const float* theta, const float* X, const float* T, int batch,
+                       float* grad, float* work, double* loss_acc, hipStream_t st);
 void mlp_adam(float* theta, const float* grad, float* m, float* v, int64_t n, int step, float lr, hipStream_t st);
 void gather_rows(const float* src, const int* idx, int rows, int cols, float* out, hipStream_t st);
 

@@ -177,8 +177,40 @@ void mlp_forward(const std::vector<int>& w, const float* theta, const float* X, 
   DFX_HIP(hipMemcpyAsync(Y, out, sizeof(float) * (size_t)batch * w.back(), hipMemcpyDeviceToDevice, st));
 }
 
+// acc[0] += sum of the 64 partial sums / n  (one thread, fixed order)
+__global__ void loss_accumulate_kernel(const double* __restrict__ part, int64_t n, double* acc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < 64; ++i) s += part[i];
+  acc[0] += s / (double)n;
+}
+
+static void loss_grad_impl(const std::vector<int>& w, const float* theta, const float* X, const float* T, int batch,
+                           float* grad, float* work, double*& part_out, int64_t& nout_out, hipStream_t st);
+
 double mlp_loss_grad(const std::vector<int>& w, const float* theta, const float* X, const float* T, int batch,
                      float* grad, float* work, hipStream_t st) {
+  double* part = nullptr;
+  int64_t nout = 0;
+  loss_grad_impl(w, theta, X, T, batch, grad, work, part, nout, st);
+  std::vector<double> hp(64);
+  DFX_HIP(hipMemcpyAsync(hp.data(), part, sizeof(double) * 64, hipMemcpyDeviceToHost, st));
+  DFX_HIP(hipStreamSynchronize(st));
+  double s = 0.0;
+  for (double v : hp) s += v;
+  return s / (double)nout;
+}
+
+void mlp_loss_grad_acc(const std::vector<int>& w, const float* theta, const float* X, const float* T, int batch,
+                       float* grad, float* work, double* loss_acc, hipStream_t st) {
+  double* part = nullptr;
+  int64_t nout = 0;
+  loss_grad_impl(w, theta, X, T, batch, grad, work, part, nout, st);
+  hipLaunchKernelGGL(loss_accumulate_kernel, dim3(1), dim3(64), 0, st, part, nout, loss_acc);
+}
+
+static void loss_grad_impl(const std::vector<int>& w, const float* theta, const float* X, const float* T, int batch,
+                           float* grad, float* work, double*& part_out, int64_t& nout_out, hipStream_t st) {
   const int nl = (int)w.size() - 1;
   const float* Y = forward_impl(w, theta, X, batch, work, st);
   size_t act = 0;
@@ -218,12 +250,8 @@ double mlp_loss_grad(const std::vector<int>& w, const float* theta, const float*
       std::swap(G, G2);
     }
   }
-  std::vector<double> hp(64);
-  DFX_HIP(hipMemcpyAsync(hp.data(), part, sizeof(double) * 64, hipMemcpyDeviceToHost, st));
-  DFX_HIP(hipStreamSynchronize(st));
-  double s = 0.0;
-  for (double v : hp) s += v;
-  return s / (double)nout;
+  part_out = part;
+  nout_out = nout;
 }
 
 void mlp_adam(float* theta, const float* grad, float* m, float* v, int64_t n, int step, float lr, hipStream_t st) {
