@@ -300,10 +300,54 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     const double t_metric0 = tm.seconds();
     GpuTimer te(st);
     te.start();
+    // The (class, l_C) launches write disjoint blocks of raw: they run on NSTR
+    // streams forked from and joined back to st, most expensive first, each on
+    // the least loaded stream, so that short launches fill the others' tails.
+    constexpr int NSTR = 4;
+    struct Fork {
+      hipStream_t s[NSTR] = {};
+      hipEvent_t ev[NSTR + 1] = {};
+      hipStream_t main;
+      explicit Fork(hipStream_t m) : main(m) {
+        for (int i = 0; i < NSTR; ++i) DFX_HIP(hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking));
+        for (int i = 0; i <= NSTR; ++i) DFX_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
+        DFX_HIP(hipEventRecord(ev[NSTR], main));
+        for (int i = 0; i < NSTR; ++i) DFX_HIP(hipStreamWaitEvent(s[i], ev[NSTR], 0));
+      }
+      void join() {
+        for (int i = 0; i < NSTR; ++i) {
+          DFX_HIP(hipEventRecord(ev[i], s[i]));
+          DFX_HIP(hipStreamWaitEvent(main, ev[i], 0));
+        }
+      }
+      ~Fork() {
+        (void)hipStreamSynchronize(main);
+        for (int i = 0; i < NSTR; ++i) (void)hipStreamDestroy(s[i]);
+        for (int i = 0; i <= NSTR; ++i) (void)hipEventDestroy(ev[i]);
+      }
+    } fork(st);
+    struct Launch {
+      double cost;
+      int cls, lc;
+    };
+    std::vector<Launch> launches;
     for (int cls = 0; cls < 16; ++cls) {
       if (cf[cls].empty()) continue;
+      const int la = cls / 4, lb = cls % 4;
       for (int lc = 0; lc <= 4; ++lc) {
         if (auxby[lc].empty()) continue;
+        const double roots = (la + lb + lc) / 2 + 1;
+        launches.push_back({(double)cf[cls].size() * auxby[lc].size() * ncart(la) * ncart(lb) * ncart(lc) * roots,
+                            cls, lc});
+      }
+    }
+    std::sort(launches.begin(), launches.end(), [](const Launch& x, const Launch& y) { return x.cost > y.cost; });
+    double load[NSTR] = {0.0, 0.0, 0.0, 0.0};
+    for (const Launch& L : launches) {
+      const int cls = L.cls, lc = L.lc;
+      const int k = (int)(std::min_element(load, load + NSTR) - load);
+      load[k] += L.cost;
+      {
         Eri3Args a{};
         a.F = B->dbas.view();
         a.S = B->dbas.view();
@@ -320,10 +364,11 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
         a.out = B->raw.as<double>();
         a.ld = B->ncols_t;
         a.rys = rys;
-        eri3_dispatch(cls / 4, cls % 4, lc, false, STORE_TILED, a, st);
+        eri3_dispatch(cls / 4, cls % 4, lc, false, STORE_TILED, a, fork.s[k]);
       }
     }
     DFX_HIP(hipGetLastError());
+    fork.join();
     te.stop();
     B->info.eri_seconds = te.seconds();
 
