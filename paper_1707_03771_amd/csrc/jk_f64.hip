@@ -1,7 +1,7 @@
 // Exchange build K = sum_Q (B_Q C)(B_Q C)^T (Eqs. 1a, 2a) in FP64 on gfx950
 // v_mfma_f64_16x16x4f64, with B_Q = hi + lo (two FP32 words per element).
 // Phase 1 (half transform) streams each packed 32x32 tile of B_Q once per
-// 64-row block as 16-byte vector loads, transposing tiles of the upper
+// block of 64 or 128 rows as vector loads, transposing tiles of the upper
 // triangle in LDS, and multiplies it by all occupied columns of C at once.
 // Phase 2 is a split-K SYRK over the (Q, i) index into FP64 partial sums with
 // an XCD-aware tile map, reduced in a fixed order.  Both phases issue the
@@ -28,71 +28,86 @@ __global__ void cpad_kernel(const double* __restrict__ C, int nbf, int nocc, int
   Cp[idx] = (nu < nbf && i < nocc) ? C[(int64_t)nu * nocc + i] : 0.0;
 }
 
-// ---- phase 1: X_Q[mu][i] = sum_nu B_Q[mu][nu] C[nu][i] for a 64-row block of mu
-// and all occupied columns (padded to NP = 64 NCB).  Wave w owns columns
-// [w NCB 16, (w + 1) NCB 16) of all four 16-row blocks.
-template <int NCB>
-__global__ void __launch_bounds__(256) kx64_kernel(const float* __restrict__ hi, const float* __restrict__ lo,
-                                                   int64_t ncols, int nbf, int q0, const double* __restrict__ Cp,
-                                                   int nocc, double* __restrict__ X, int64_t ldx) {
+// ---- phase 1: X_Q[mu][i] = sum_nu B_Q[mu][nu] C[nu][i] for a block of MR = 64 RB
+// rows of mu and all occupied columns (padded to NP = 64 NCB).  Eight waves in
+// a 2 x 4 grid: wave w owns rows [(w & 1) MR / 2, +MR / 2) and columns
+// [(w >> 1) NCB 16, +NCB 16), i.e. 2 RB x NCB accumulator blocks.
+constexpr int KX_T = 512;
+// Rows per block in units of 64.  128 rows halve the L2 reads of C per flop,
+// which pays from 256 occupied columns on (measured); beyond 320 columns the
+// 128-row accumulators no longer fit in 256 registers.
+constexpr int kx_rb(int ncb) { return (ncb >= 4 && ncb <= 5) ? 2 : 1; }
+template <int NCB, int RB>
+__global__ void __launch_bounds__(KX_T) kx64_kernel(const float* __restrict__ hi, const float* __restrict__ lo,
+                                                    int64_t ncols, int nbf, int q0, const double* __restrict__ Cp,
+                                                    int nocc, double* __restrict__ X, int64_t ldx) {
   constexpr int NP = 64 * NCB;
-  constexpr int NCL = S64 * NP / 512;  // 16-byte pairs of C per thread per stage
-  __shared__ double As[64][S64 + PA];
+  constexpr int MR = 64 * RB;
+  constexpr int WA = 2 * RB;                  // 16-row fragments per wave
+  constexpr int EP = 2 * RB;                  // consecutive A elements per thread per stage
+  constexpr int TPR = KX_T / (MR / 32);       // threads per 32-row tile row
+  constexpr int NCL = S64 * NP / (2 * KX_T);  // 16-byte pairs of C per thread per stage
+  static_assert(NCL * 2 * KX_T == S64 * NP, "C stage must split evenly");
+  static_assert(TPR * EP == 32 * S64, "A stage must split evenly");
+  typedef float vfa __attribute__((ext_vector_type(EP)));
+  __shared__ double As[MR][S64 + PA];
   __shared__ double Bs[S64][NP + PB];
   const int Q = q0 + blockIdx.y;
-  const int m0 = blockIdx.x * 64;
+  const int m0 = blockIdx.x * MR;
   const int I0 = m0 >> 5;
   const int nt = ntiles_for(nbf);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
+  const int wr = (w & 1) * (MR / 2), wc = (w >> 1) * NCB * 16;
   const float* __restrict__ rh = hi + (int64_t)Q * ncols;
   const float* __restrict__ rl = lo + (int64_t)Q * ncols;
-  // A loader: threads 0..127 serve tile row I0, 128..255 tile row I0 + 1
-  const int half = tid >> 7, t = tid & 127;
+  // A loader: thread group `half` serves tile row I0 + half, EP consecutive
+  // elements per thread (along nu in a direct tile, along mu in a mirrored one)
+  const int half = tid / TPR, t = tid % TPR;
   const int I = I0 + half;
+  constexpr int DK = S64 / EP;  // threads per row of a direct stage
+  constexpr int TM = 32 / EP;   // threads per row of a mirrored stage
 
-  float4 ah, al;
+  vfa ah, al;
   double2 cr[NCL];
   auto load = [&](int stage) {
     const int J = stage >> 1, h = stage & 1;
-    ah = al = make_float4(0.f, 0.f, 0.f, 0.f);
+    ah = al = vfa(0.f);
     if (I < nt) {
       int64_t off;
-      if (I >= J)  // direct tile (I, J): row mu = t / 4, nu = 16 h + 4 (t % 4) ..
-        off = tile_base(I, J) + (t >> 2) * 32 + 16 * h + (t & 3) * 4;
-      else         // tile (J, I): row nu = 16 h + t / 8, mu = 4 (t % 8) ..
-        off = tile_base(J, I) + (16 * h + (t >> 3)) * 32 + (t & 7) * 4;
-      ah = *reinterpret_cast<const float4*>(rh + off);
-      al = *reinterpret_cast<const float4*>(rl + off);
+      if (I >= J)  // direct tile (I, J): row mu = t / DK, nu = 16 h + EP (t % DK) ..
+        off = tile_base(I, J) + (t / DK) * 32 + 16 * h + (t % DK) * EP;
+      else         // tile (J, I): row nu = 16 h + t / TM, mu = EP (t % TM) ..
+        off = tile_base(J, I) + (16 * h + t / TM) * 32 + (t % TM) * EP;
+      ah = *reinterpret_cast<const vfa*>(rh + off);
+      al = *reinterpret_cast<const vfa*>(rl + off);
     }
     const double2* __restrict__ cs = reinterpret_cast<const double2*>(Cp + (int64_t)stage * S64 * NP);
 #pragma unroll
-    for (int c = 0; c < NCL; ++c) cr[c] = cs[tid + 256 * c];
+    for (int c = 0; c < NCL; ++c) cr[c] = cs[tid + KX_T * c];
   };
   auto store = [&](int stage) {
     const int J = stage >> 1;
-    const double v[4] = {(double)ah.x + (double)al.x, (double)ah.y + (double)al.y, (double)ah.z + (double)al.z,
-                         (double)ah.w + (double)al.w};
     if (I >= J) {
-      const int r = half * 32 + (t >> 2), k0 = (t & 3) * 4;
+      const int r = half * 32 + t / DK, k0 = (t % DK) * EP;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) As[r][k0 + e] = v[e];
+      for (int e = 0; e < EP; ++e) As[r][k0 + e] = (double)ah[e] + (double)al[e];
     } else {
-      const int k = t >> 3, r0 = half * 32 + (t & 7) * 4;
+      const int k = t / TM, r0 = half * 32 + (t % TM) * EP;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) As[r0 + e][k] = v[e];
+      for (int e = 0; e < EP; ++e) As[r0 + e][k] = (double)ah[e] + (double)al[e];
     }
 #pragma unroll
     for (int c = 0; c < NCL; ++c) {
-      const int e = 2 * (tid + 256 * c);  // NP is even: a pair never straddles rows
+      const int e = 2 * (tid + KX_T * c);  // NP is even: a pair never straddles rows
       Bs[e / NP][e % NP] = cr[c].x;
       Bs[e / NP][e % NP + 1] = cr[c].y;
     }
   };
 
-  v4d acc[4][NCB];
+  v4d acc[WA][NCB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < WA; ++a)
 #pragma unroll
     for (int b = 0; b < NCB; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
 
@@ -105,36 +120,40 @@ __global__ void __launch_bounds__(256) kx64_kernel(const float* __restrict__ hi,
     if (s + 1 < nstage) load(s + 1);  // in flight during the MFMAs below
 #pragma unroll
     for (int kk = 0; kk < S64; kk += 4) {
-      double fa[4];
+      double fa[WA];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) fa[a] = As[a * 16 + li][kk + lk];
+      for (int a = 0; a < WA; ++a) fa[a] = As[wr + a * 16 + li][kk + lk];
 #pragma unroll
       for (int b = 0; b < NCB; ++b) {
-        const double fb = Bs[kk + lk][w * NCB * 16 + b * 16 + li];
+        const double fb = Bs[kk + lk][wc + b * 16 + li];
 #pragma unroll
-        for (int a = 0; a < 4; ++a) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb, acc[a][b], 0, 0, 0);
+        for (int a = 0; a < WA; ++a) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb, acc[a][b], 0, 0, 0);
       }
     }
   }
   // f64 MFMA output: element r of lane (li, lk) is row 4 r + lk, column li
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < WA; ++a)
 #pragma unroll
     for (int b = 0; b < NCB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int mu = m0 + a * 16 + 4 * r + lk;
-        const int i = w * NCB * 16 + b * 16 + li;
+        const int mu = m0 + wr + a * 16 + 4 * r + lk;
+        const int i = wc + b * 16 + li;
         if (mu < nbf && i < nocc) X[(int64_t)mu * ldx + (int64_t)blockIdx.y * nocc + i] = acc[a][b][r];
       }
 }
 
 // ---- phase 2: P_s = X_s X_s^T (lower 128x128 tiles) for k-slices s of X.
 // Workgroups are dealt round-robin to the 8 XCDs; every tile of a slice goes to
-// one XCD so that the slice of X is fetched from HBM once per XCD L2.
-__global__ void __launch_bounds__(256) syrk64_kernel(const double* __restrict__ X, int64_t ldx, int nbf,
-                                                     int64_t kslice, int64_t kdim, int nslices, int ntl,
-                                                     double* __restrict__ P) {
+// one XCD so that the slice of X is fetched from HBM once per XCD L2.  Eight
+// waves in a 2 x 4 grid of 64 x 32 sub-tiles; on a diagonal tile the two waves
+// whose sub-tiles lie wholly above the diagonal load and synchronise but skip
+// their MFMAs.
+constexpr int SY_T = 512;
+__global__ void __launch_bounds__(SY_T) syrk64_kernel(const double* __restrict__ X, int64_t ldx, int nbf,
+                                                      int64_t kslice, int64_t kdim, int nslices, int ntl,
+                                                      double* __restrict__ P) {
   __shared__ double As[128][S64 + PA];
   __shared__ double Bs[128][S64 + PA];
   const int bid = blockIdx.x;
@@ -150,39 +169,32 @@ __global__ void __launch_bounds__(256) syrk64_kernel(const double* __restrict__ 
   const int64_t k0s = (int64_t)s * kslice;
   const int64_t k1s = k0s + kslice < kdim ? k0s + kslice : kdim;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+  const int wm = (w & 1) * 64, wn = (w >> 1) * 32;
+  const bool active = !(ti == tj && wn >= wm + 64);
   const int li = lane & 15, lk = lane >> 4;
-  // loader: row r = tid / 2 of both operands, 8 consecutive k from kh
-  const int r = tid >> 1, kh = (tid & 1) * 8;
+  // loader: row r = tid / 4 of both operands, 4 consecutive k from kq
+  const int r = tid >> 2, kq = (tid & 3) * 4;
   const int ma = m0 + r, nb = n0 + r;
 
-  double va[8], vb[8];
+  double va[4], vb[4];
   auto load = [&](int64_t k0) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) va[e] = vb[e] = 0.0;
+    for (int e = 0; e < 4; ++e) va[e] = vb[e] = 0.0;
     if (k0 + S64 <= k1s) {
       if (ma < nbf) {
-        const double2* p = reinterpret_cast<const double2*>(X + (int64_t)ma * ldx + k0 + kh);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const double2 v = p[e];
-          va[2 * e] = v.x;
-          va[2 * e + 1] = v.y;
-        }
+        const double2* p = reinterpret_cast<const double2*>(X + (int64_t)ma * ldx + k0 + kq);
+        const double2 v0 = p[0], v1 = p[1];
+        va[0] = v0.x, va[1] = v0.y, va[2] = v1.x, va[3] = v1.y;
       }
       if (nb < nbf) {
-        const double2* p = reinterpret_cast<const double2*>(X + (int64_t)nb * ldx + k0 + kh);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const double2 v = p[e];
-          vb[2 * e] = v.x;
-          vb[2 * e + 1] = v.y;
-        }
+        const double2* p = reinterpret_cast<const double2*>(X + (int64_t)nb * ldx + k0 + kq);
+        const double2 v0 = p[0], v1 = p[1];
+        vb[0] = v0.x, vb[1] = v0.y, vb[2] = v1.x, vb[3] = v1.y;
       }
     } else {  // ragged end of the slice
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t k = k0 + kh + e;
+      for (int e = 0; e < 4; ++e) {
+        const int64_t k = k0 + kq + e;
         if (k < k1s) {
           if (ma < nbf) va[e] = X[(int64_t)ma * ldx + k];
           if (nb < nbf) vb[e] = X[(int64_t)nb * ldx + k];
@@ -191,40 +203,44 @@ __global__ void __launch_bounds__(256) syrk64_kernel(const double* __restrict__ 
     }
   };
 
-  v4d acc[4][4];
+  v4d acc[4][2];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
 
   if (k0s < k1s) load(k0s);
   for (int64_t k0 = k0s; k0 < k1s; k0 += S64) {
     __syncthreads();
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      As[r][kh + e] = va[e];
-      Bs[r][kh + e] = vb[e];
+    for (int e = 0; e < 4; ++e) {
+      As[r][kq + e] = va[e];
+      Bs[r][kq + e] = vb[e];
     }
     __syncthreads();
     if (k0 + S64 < k1s) load(k0 + S64);
+    if (active) {
 #pragma unroll
-    for (int kk = 0; kk < S64; kk += 4) {
-      double fa[4], fb[4];
+      for (int kk = 0; kk < S64; kk += 4) {
+        double fa[4], fb[2];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) fa[a] = As[wm + a * 16 + li][kk + lk];
+        for (int a = 0; a < 4; ++a) fa[a] = As[wm + a * 16 + li][kk + lk];
 #pragma unroll
-      for (int b = 0; b < 4; ++b) fb[b] = Bs[wn + b * 16 + li][kk + lk];
+        for (int b = 0; b < 2; ++b) fb[b] = Bs[wn + b * 16 + li][kk + lk];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+      }
     }
   }
+  if (!active) return;
   double* __restrict__ Ps = P + (int64_t)s * nbf * nbf;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int m = m0 + wm + a * 16 + 4 * q + lk;
@@ -301,13 +317,14 @@ void k_build_f64(const JKArgs& a, const double* C, int nocc, double* K, void* wo
   for (int q0 = 0; q0 < a.naux; q0 += p.qc) {
     const int nq = std::min(p.qc, a.naux - q0);
     const int64_t kdim = (int64_t)nq * nocc;
-    const dim3 g1((a.nbf + 63) / 64, nq);
+    const int mr = 64 * kx_rb(ncb);
+    const dim3 g1((a.nbf + mr - 1) / mr, nq);
     if (timer) timer->begin_x();
     switch (ncb) {
-#define KX64(N)                                                                                            \
-  case N:                                                                                                  \
-    hipLaunchKernelGGL((kx64_kernel<N>), g1, dim3(256), 0, st, a.hi, a.lo, a.ncols, a.nbf, q0, Cp, nocc, X, \
-                       p.ldx);                                                                             \
+#define KX64(N)                                                                                                   \
+  case N:                                                                                                         \
+    hipLaunchKernelGGL((kx64_kernel<N, kx_rb(N)>), g1, dim3(KX_T), 0, st, a.hi, a.lo, a.ncols, a.nbf, q0, Cp, nocc, \
+                       X, p.ldx);                                                                                 \
     break;
       KX64(1) KX64(2) KX64(3) KX64(4) KX64(5) KX64(6) KX64(7) KX64(8)
 #undef KX64
@@ -315,7 +332,7 @@ void k_build_f64(const JKArgs& a, const double* C, int nocc, double* K, void* wo
     if (timer) timer->end_x();
     if (timer) timer->begin_syrk();
     const int64_t kslice = ((kdim + p.ns - 1) / p.ns + S64 - 1) / S64 * S64;
-    hipLaunchKernelGGL(syrk64_kernel, dim3((unsigned)(p.ns * p.ntl)), dim3(256), 0, st, X, p.ldx, a.nbf, kslice,
+    hipLaunchKernelGGL(syrk64_kernel, dim3((unsigned)(p.ns * p.ntl)), dim3(SY_T), 0, st, X, p.ldx, a.nbf, kslice,
                        kdim, p.ns, p.ntl, P);
     hipLaunchKernelGGL(k_reduce64_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, P, p.ns, a.nbf, K,
                        q0 > 0 ? 1 : 0);

@@ -268,3 +268,22 @@ def test_water_scf_schedules_agree(water, dfx):
     assert il["converged"] and il["guess_fallback"] == 0
     assert abs(El - Ep) <= 1e-6
     print(f"(H2O)64: plain {ip['niter']} iterations, mixed core {im['niter']}, mixed learned {il['niter']}")
+
+
+# ---- C30H62 against the oracle's stored energy ---------------------------------
+
+def test_alkane_energy_against_oracle(dfx):
+    """Plain FP64 and the mixed FP32 -> FP64 schedule reproduce the oracle's
+    converged DF-RHF energy of the zigzag C30H62 workload (written by
+    tests/golden/make_alkane_energy.py from the oracle alone) within 1e-6 Eh."""
+    import json
+    import os
+    gold = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "alkane_df_rhf.json")))
+    elems, xyz, sh, ax = W.workload("alkane", seed=0)
+    Z = W.charges(elems)
+    conv = dict(conv_dE=1e-9, conv_err=1e-7)
+    for kw in ({}, dict(schedule=dfx.SCHED_MIXED, mixed_prec=dfx.FP32)):
+        E, _, _, i = dfx.scf(xyz, Z, sh, ax, want_c=False, **conv, **kw)
+        assert i["converged"] and i["nbf"] == gold["nbf"] and i["nocc"] == gold["nocc"]
+        print(f"C30H62 {kw.get('schedule', 'plain')}: E = {E:.10f}, oracle {gold['E']:.10f}, dE {E - gold['E']:.2e}")
+        assert abs(E - gold["E"]) <= 1e-6
