@@ -237,6 +237,12 @@ typedef struct {
                             and in FP64 on every 16th auxiliary function, the DIIS-error
                             commutator of the difference scaled by sqrt(16); the stage
                             ends once its error is below max(switch_err, estimate) */
+  int32_t purify;        /* 1 (default): after the first iteration, the occupied orbitals of
+                            X^T F X come from trace-correcting purification (Niklasson,
+                            Phys. Rev. B 66, 155115 (2002)) and a Cholesky QR of the
+                            projector times the previous ones; dsyevd where it does not
+                            settle.  0: dsyevd every iteration.  C and eps are the
+                            eigenvectors and eigenvalues of the last X^T F X either way */
 } dfx_scf_opts;
 
 #define DFX_MAXHIST 256
@@ -258,7 +264,8 @@ typedef struct {
   double t_j;            /* all J builds */
   double t_kx;           /* all K half-transforms X_Q = B_Q C_occ */
   double t_ksyrk;        /* all K contractions sum_Q X_Q X_Q^T (incl. reduction) */
-  double t_eig;          /* all eigensolves */
+  double t_eig;          /* all occupied-space updates (X^T F X, purification or dsyevd,
+                            C_occ and D) and the overlap eigensolve */
   int32_t n_jk;          /* J/K builds performed */
   int32_t n_kx_launch;   /* half-transform kernel launches */
   /* the same K figures split by precision, index DFX_FP64 / DFX_FP32 / DFX_BF16 */
@@ -276,6 +283,9 @@ typedef struct {
   int32_t guess_fallback; /* DFX_GUESS_LEARNED: 0 used; 1 non-finite prediction, core guess
                              used instead; 2 no convergence from it in max_iter, restarted
                              from the core guess (niter and the histories count both passes) */
+  int32_t n_purified;    /* occupied-space updates by purification */
+  int32_t n_eigh;        /* occupied-space updates by dsyevd (the final C/eps solve excluded) */
+  int32_t purify_steps;  /* purification steps (matrix squarings) over all updates */
 } dfx_scf_info;
 
 void dfx_scf_default_opts(dfx_scf_opts* o);

@@ -70,7 +70,7 @@ class ScfOpts(ctypes.Structure):
                 ("ortho_thresh", ctypes.c_double), ("switch_err", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("diis_size", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("mixed_prec", ctypes.c_int32), ("guess", ctypes.c_int32), ("verbose", ctypes.c_int32),
-                ("model", ctypes.c_void_p), ("switch_auto", ctypes.c_int32)]
+                ("model", ctypes.c_void_p), ("switch_auto", ctypes.c_int32), ("purify", ctypes.c_int32)]
 
 
 class ScfInfo(ctypes.Structure):
@@ -86,7 +86,8 @@ class ScfInfo(ctypes.Structure):
                 ("nintegrals", ctypes.c_int64), ("ncols", ctypes.c_int64),
                 ("E_hist", ctypes.c_double * MAXHIST), ("err_hist", ctypes.c_double * MAXHIST),
                 ("prec_hist", ctypes.c_int8 * MAXHIST), ("t_guess", ctypes.c_double),
-                ("floor_est", ctypes.c_double * 3), ("guess_fallback", ctypes.c_int32)]
+                ("floor_est", ctypes.c_double * 3), ("guess_fallback", ctypes.c_int32),
+                ("n_purified", ctypes.c_int32), ("n_eigh", ctypes.c_int32), ("purify_steps", ctypes.c_int32)]
 
 
 class Eri3Sizes(ctypes.Structure):
@@ -316,8 +317,8 @@ def scf_default_opts():
 
 
 def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, model=None, **opts):
-    """dfx_scf: DF-RHF.  Returns (E, C, eps, info dict); C and eps are numpy arrays.
-    With a GuessModel, the start is its predicted density (guess = GUESS_LEARNED)."""
+    """dfx_scf: DF-RHF.  Returns (E, C, eps, info dict); C and eps are numpy arrays
+    (None with want_c=False).  With a GuessModel, the start is its predicted density (guess = GUESS_LEARNED)."""
     o = scf_default_opts()
     for k, v in opts.items():
         if not hasattr(o, k) or k == "model":
@@ -331,7 +332,7 @@ def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, model=None, **opt
     n = sum(2 * int(q["l"]) + 1 for q in shells)
     E = ctypes.c_double()
     C = np.zeros((n, n)) if want_c else None
-    eps = np.zeros(n)
+    eps = np.zeros(n) if want_c else None
     inf = ScfInfo()
     ini = None
     if init is not None:
@@ -339,7 +340,7 @@ def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, model=None, **opt
         assert ini.shape == (n, n)
     code = _lib.dfx_scf(ctypes.byref(g.g), s.arr, s.n, a.arr, a.n, ctypes.byref(o),
                         ini.ctypes.data if ini is not None else None, ctypes.byref(E),
-                        C.ctypes.data if want_c else None, eps.ctypes.data, ctypes.byref(inf))
+                        C.ctypes.data if want_c else None, eps.ctypes.data if want_c else None, ctypes.byref(inf))
     if code not in (OK, ENOCONV):
         _check(code)
     info = {k: getattr(inf, k) for k, _ in ScfInfo._fields_ if not k.endswith("_hist")}

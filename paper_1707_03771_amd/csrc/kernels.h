@@ -47,6 +47,10 @@ struct GemmF64 {
   bool lowerC;     // only the lower triangle of C is needed (skip blocks above)
 };
 void dgemm(const GemmF64& g, hipStream_t st);
+// dgemm, with the k-range split over up to 8 partial products (work: ns M N
+// doubles, work_elems available) when C alone has too few 128 x 128 tiles to
+// fill the chip; the partials are summed in a fixed order
+void dgemm_sk(const GemmF64& g, double* work, int64_t work_elems, hipStream_t st);
 
 // B-transform: out = L^-1 * raw with lower-triangular Linv [n x n], raw [n x ncols],
 // written as hi = fl32(out), lo = fl32(out - hi).

@@ -2,6 +2,8 @@
 // the blocked Cholesky factorisation of the fitting metric J_PQ = L L^T, the
 // inverse L^-1, and the transform B = L^-1 (mu nu|P) of Eq. (1c) with
 // M' = L^-1, whose epilogue splits B into two FP32 words.
+#include <algorithm>
+
 #include "kernels.h"
 
 namespace dfx {
@@ -187,6 +189,66 @@ void dgemm(const GemmF64& g, hipStream_t st) {
   else if (g.ta && !g.tb) L(true, false);
   else L(true, true);
 #undef L
+}
+
+// C = alpha sum_s W_s + beta C, partials W_s [M][N] contiguous, summed in order
+__global__ void sk_reduce_kernel(const double* __restrict__ W, int ns, int M, int N, double alpha, double beta,
+                                 double* __restrict__ C, int64_t ldc) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t mn = (int64_t)M * N;
+  if (i >= mn) return;
+  double s = 0.0;
+  for (int z = 0; z < ns; ++z) s += W[z * mn + i];
+  double* c = C + (i / N) * ldc + (i % N);
+  *c = beta != 0.0 ? alpha * s + beta * *c : alpha * s;
+}
+
+void dgemm_sk(const GemmF64& g, double* work, int64_t work_elems, hipStream_t st) {
+  const int tiles = gemm_tiles(g.M, g.N);
+  const int64_t mn = (int64_t)g.M * g.N;
+  int ns = 1;
+  while (ns < 8 && tiles * ns < 512 && g.K / (2 * ns) >= 128 && 2 * ns * mn <= work_elems) ns *= 2;
+  if (ns == 1 || g.batch > 1 || g.lowerA || g.lowerC || !work) {
+    dgemm(g, st);
+    return;
+  }
+  const int klen = ((g.K + ns - 1) / ns + GK - 1) / GK * GK;
+  GemmF64 a = g;
+  a.ldc = g.N;
+  a.alpha = 1.0;
+  a.beta = 0.0;
+  a.batch = 1;
+  auto launch = [&](const GemmF64& x, int nz) {
+    const dim3 grid(tiles, 1, nz);
+#define L(TA_, TB_) \
+  hipLaunchKernelGGL((dgemm_kernel<TA_, TB_, EPI_F64>), grid, dim3(GT), 0, st, x, nullptr, nullptr)
+    if (!x.ta && !x.tb) L(false, false);
+    else if (!x.ta && x.tb) L(false, true);
+    else if (x.ta && !x.tb) L(true, false);
+    else L(true, true);
+#undef L
+  };
+  if ((int64_t)klen * ns == g.K) {  // equal k-ranges: one batched launch
+    a.K = klen;
+    a.sA = g.ta ? (int64_t)klen * g.lda : klen;
+    a.sB = g.tb ? klen : (int64_t)klen * g.ldb;
+    a.sC = mn;
+    a.C = work;
+    launch(a, ns);
+  } else {
+    int z = 0;
+    for (int k0 = 0; k0 < g.K; k0 += klen, ++z) {
+      a.K = std::min(klen, g.K - k0);
+      a.A = g.ta ? g.A + (int64_t)k0 * g.lda : g.A + k0;
+      a.B = g.tb ? g.B + k0 : g.B + (int64_t)k0 * g.ldb;
+      a.C = work + z * mn;
+      a.sA = a.sB = a.sC = 0;
+      launch(a, 1);
+    }
+    ns = z;
+  }
+  hipLaunchKernelGGL(sk_reduce_kernel, dim3((unsigned)((mn + 255) / 256)), dim3(256), 0, st, work, ns, g.M, g.N,
+                     g.alpha, g.beta, g.C, g.ldc);
 }
 
 void trsm_split(const double* Linv, int n, const double* raw, int64_t ncols, float* hi, float* lo,

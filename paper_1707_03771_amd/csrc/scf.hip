@@ -7,7 +7,13 @@
 //
 // Everything lives on the GPU; per iteration only E, max|e| and the DIIS
 // overlaps (a few doubles) travel to the host, where the (m+1)x(m+1) DIIS
-// system is solved.  The eigensolver is rocSOLVER's dsyevd.
+// system is solved.
+//
+// The occupied space of X^T F X comes from trace-correcting purification
+// (Niklasson, Phys. Rev. B 66, 155115 (2002)) -- FP64 matrix products only --
+// followed by a Cholesky QR (applied twice) of the projector times the previous
+// occupied orbitals; rocSOLVER's dsyevd serves the starting guess, the final
+// orbitals and energies, and any purification that does not converge.
 #include <rocblas/rocblas.h>
 #include <rocsolver/rocsolver.h>
 
@@ -113,6 +119,125 @@ __global__ void copy_cols_kernel(const double* A, int lda, int rows, int cols, d
   B[(int64_t)r * ldb + c] = A[(int64_t)r * lda + c];
 }
 
+// ---- purification kernels (X^T F X is m x m, row-major) -------------------------
+// Gershgorin discs of row r: centre A_rr, radius sum_{j != r} |A_rj|
+__global__ void gersh_kernel(const double* __restrict__ A, int m, double* __restrict__ lo, double* __restrict__ hi) {
+  __shared__ double red[256];
+  const int r = blockIdx.x;
+  const double* row = A + (int64_t)r * m;
+  double s = 0.0;
+  for (int j = threadIdx.x; j < m; j += blockDim.x)
+    if (j != r) s += fabs(row[j]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    lo[r] = row[r] - red[0];
+    hi[r] = row[r] + red[0];
+  }
+}
+
+// out[0] = min lo, out[1] = max hi (one block)
+__global__ void minmax_kernel(const double* __restrict__ lo, const double* __restrict__ hi, int m,
+                              double* __restrict__ out) {
+  __shared__ double a[256], b[256];
+  double x = 1e300, y = -1e300;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    x = fmin(x, lo[i]);
+    y = fmax(y, hi[i]);
+  }
+  a[threadIdx.x] = x;
+  b[threadIdx.x] = y;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      a[threadIdx.x] = fmin(a[threadIdx.x], a[threadIdx.x + o]);
+      b[threadIdx.x] = fmax(b[threadIdx.x], b[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = a[0];
+    out[1] = b[0];
+  }
+}
+
+// P0 = (emax I - F) / (emax - emin): spectrum mapped into [0, 1], occupied levels high
+__global__ void tc2_init_kernel(const double* __restrict__ F, int m, double emax, double inv_w,
+                                double* __restrict__ P) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)m * m) return;
+  const int r = (int)(i / m), c = (int)(i % m);
+  P[i] = ((r == c ? emax : 0.0) - F[i]) * inv_w;
+}
+
+// out[0] = tr P, out[1] = tr P2 (one block, fixed order)
+__global__ void trace2_kernel(const double* __restrict__ P, const double* __restrict__ P2, int m,
+                              double* __restrict__ out) {
+  __shared__ double a[256], b[256];
+  double x = 0.0, y = 0.0;
+  for (int i = threadIdx.x; i < m; i += blockDim.x) {
+    x += P[(int64_t)i * m + i];
+    y += P2[(int64_t)i * m + i];
+  }
+  a[threadIdx.x] = x;
+  b[threadIdx.x] = y;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      a[threadIdx.x] += a[threadIdx.x + o];
+      b[threadIdx.x] += b[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = a[0];
+    out[1] = b[0];
+  }
+}
+
+// P <- 2 P - P2
+__global__ void tc2_raise_kernel(double* __restrict__ P, const double* __restrict__ P2, int64_t n2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n2) P[i] = 2.0 * P[i] - P2[i];
+}
+
+// Y[k][j] = V[row0 + j][k]: eigenvectors (rows of V) row0 .. row0 + nocc - 1 as columns
+__global__ void rows_to_cols_kernel(const double* __restrict__ V, int m, int row0, int nocc, double* __restrict__ Y) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)m * nocc) return;
+  const int k = (int)(i / nocc), j = (int)(i % nocc);
+  Y[i] = V[(int64_t)(row0 + j) * m + k];
+}
+
+// out[0] = min_i |G_ii|, out[1] = max_i |G_ii| (one block)
+__global__ void diag_minmax_kernel(const double* __restrict__ G, int k, double* __restrict__ out) {
+  __shared__ double a[256], b[256];
+  double x = 1e300, y = 0.0;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    const double v = fabs(G[(int64_t)i * k + i]);
+    x = fmin(x, v);
+    y = fmax(y, v);
+  }
+  a[threadIdx.x] = x;
+  b[threadIdx.x] = y;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      a[threadIdx.x] = fmin(a[threadIdx.x], a[threadIdx.x + o]);
+      b[threadIdx.x] = fmax(b[threadIdx.x], b[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    out[0] = a[0];
+    out[1] = b[0];
+  }
+}
+
 static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // ---- driver ---------------------------------------------------------------------------
@@ -120,9 +245,10 @@ struct Scf {
   hipStream_t st{};
   rocblas_handle rb{};
   int n = 0, m = 0, nocc = 0;
-  DevMem part, eig_e, eig_info;
+  DevMem part, eig_e, eig_info, gw;  // gw: split-K partial products
   std::vector<double> hpart;
   EventSpans* eig_spans = nullptr;
+  int verbose = 0;
 
   double reduce_sum(const double* a, const double* b, const double* c, int64_t cnt) {
     const int nb = 512;
@@ -152,7 +278,72 @@ struct Scf {
     g.B = B; g.ldb = ldb; g.tb = tb;
     g.C = C; g.ldc = ldc;
     g.alpha = alpha; g.beta = beta; g.batch = 1;
-    dgemm(g, st);
+    dgemm_sk(g, gw.p ? gw.as<double>() : nullptr, (int64_t)(gw.n / sizeof(double)), st);
+  }
+  // Occupied space of the symmetric m x m matrix F (the nocc lowest levels) by
+  // trace-correcting purification: P0 = (e_max I - F) / (e_max - e_min) with
+  // Gershgorin bounds, then P <- P^2 or 2P - P^2, whichever moves tr P toward
+  // nocc, until sum lambda (1 - lambda) = tr P - tr P^2 < 1e-9 nocc, plus three
+  // more steps.  The projector times the previous occupied orbitals Y, put
+  // through a Cholesky QR twice, is the new Y (m x nocc, orthonormal columns).
+  // P and P2 are m x m work, Z m x nocc, G nocc x nocc, lohi 2m.  Returns false,
+  // Y unchanged, if the iteration does not settle in 100 steps, the trace
+  // misses nocc, or Z = P Y is too ill-conditioned (a Cholesky pivot below
+  // 1e-4 of the largest).
+  bool purify_occ(const double* F, double* P, double* P2, double* Y, double* Z, double* G, double* lohi,
+                  int& steps, const char*& why) {
+    double b[2];
+    hipLaunchKernelGGL(gersh_kernel, dim3(m), dim3(256), 0, st, F, m, lohi, lohi + m);
+    hipLaunchKernelGGL(minmax_kernel, dim3(1), dim3(256), 0, st, lohi, lohi + m, m, part.as<double>());
+    DFX_HIP(hipMemcpyAsync(b, part.p, sizeof b, hipMemcpyDeviceToHost, st));
+    DFX_HIP(hipStreamSynchronize(st));
+    const double w = b[1] - b[0];
+    why = "spectral bounds";
+    if (!(w > 0.0) || !std::isfinite(w)) return false;
+    if (verbose) std::fprintf(stderr, "dfx_scf purification: Gershgorin [%.3f, %.3f]\n", b[0], b[1]);
+    const int64_t mm = (int64_t)m * m;
+    hipLaunchKernelGGL(tc2_init_kernel, dim3(nblk(mm)), dim3(256), 0, st, F, m, b[1], 1.0 / w, P);
+    int settled = 0;
+    bool ok = false;
+    for (steps = 0; steps < 100; ++steps) {
+      gemm(m, m, m, P, m, false, P, m, false, P2, m);
+      hipLaunchKernelGGL(trace2_kernel, dim3(1), dim3(256), 0, st, P, P2, m, part.as<double>());
+      DFX_HIP(hipMemcpyAsync(b, part.p, sizeof b, hipMemcpyDeviceToHost, st));
+      DFX_HIP(hipStreamSynchronize(st));
+      if (!std::isfinite(b[0]) || !std::isfinite(b[1])) return false;
+      if (b[0] - b[1] < 1e-9 * nocc && ++settled > 3) {
+        ok = std::fabs(b[0] - nocc) < 1e-6;
+        why = "trace";
+        break;
+      }
+      why = "not settled";
+      if (std::fabs(b[1] - nocc) < std::fabs(2.0 * b[0] - b[1] - nocc))
+        std::swap(P, P2);
+      else
+        hipLaunchKernelGGL(tc2_raise_kernel, dim3(nblk(mm)), dim3(256), 0, st, P, P2, mm);
+    }
+    if (!ok) return false;
+    gemm(m, nocc, m, P, m, false, Y, nocc, false, Z, nocc);  // Z = P Y
+    for (int pass = 0; pass < 2; ++pass) {
+      gemm(nocc, nocc, m, Z, nocc, true, Z, nocc, false, G, nocc);  // G = Z^T Z = U^T U
+      if (rocsolver_dpotrf(rb, rocblas_fill_upper, nocc, G, nocc, eig_info.as<rocblas_int>()) !=
+          rocblas_status_success)
+        return false;
+      hipLaunchKernelGGL(diag_minmax_kernel, dim3(1), dim3(256), 0, st, G, nocc, part.as<double>());
+      int info = 0;
+      DFX_HIP(hipMemcpyAsync(&info, eig_info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+      DFX_HIP(hipMemcpyAsync(b, part.p, sizeof b, hipMemcpyDeviceToHost, st));
+      DFX_HIP(hipStreamSynchronize(st));
+      why = "Cholesky QR";
+      if (info != 0 || !(b[0] > 1e-4 * b[1])) return false;
+      // Z <- Z U^-1: in column-major terms Z^T <- U^-T Z^T
+      const double one = 1.0;
+      if (rocblas_dtrsm(rb, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
+                        rocblas_diagonal_non_unit, nocc, m, &one, G, nocc, Z, nocc) != rocblas_status_success)
+        return false;
+    }
+    DFX_HIP(hipMemcpyAsync(Y, Z, sizeof(double) * (size_t)m * nocc, hipMemcpyDeviceToDevice, st));
+    return true;
   }
   // symmetric eigen-decomposition in place: A (k x k) -> rows are eigenvectors, w ascending
   void syevd(double* A, int k, double* w) {
@@ -300,6 +491,7 @@ void dfx_scf_default_opts(dfx_scf_opts* o) {
   o->guess = DFX_GUESS_CORE;
   o->verbose = 0;
   o->switch_auto = 1;
+  o->purify = 1;
 }
 
 int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
@@ -345,6 +537,8 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     S.n = n;
     S.nocc = nocc;
     S.part.alloc(sizeof(double) * 512);
+    S.gw.alloc(sizeof(double) * 4 * (size_t)n * n);
+    S.verbose = o.verbose;
     EventSpans sp_eig_all;
     sp_eig_all.st = S.st;
     S.eig_spans = &sp_eig_all;
@@ -399,15 +593,44 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
       Eh[k].alloc(8 * (size_t)m * m);
     }
 
-    // diagonalise a Fock-like matrix: C = X eig(X^T F X), Cocc = C[:, :nocc], D = Cocc Cocc^T
+    // occupied orbitals of a Fock-like matrix F: Cocc = X Y with Y the nocc lowest
+    // levels of F' = X^T F X (kept in Fq), D = Cocc Cocc^T.  Purification when a
+    // previous Y exists, else (or if it fails) dsyevd, which also gives C and eps.
+    DevMem Fq(8 * (size_t)m * m), Yo(8 * (size_t)m * nocc), Zo(8 * (size_t)m * nocc),
+        Go(8 * (size_t)nocc * nocc), lohi(16 * (size_t)m);
+    bool have_y = false, cm_valid = false, fq_valid = false;
+    int n_purified = 0, n_eigh = 0, purify_steps = 0;
     auto diag = [&](const double* Fx) {
+      S.eig_spans = nullptr;
+      sp_eig_all.begin();
       S.gemm(m, n, n, X.as<double>(), m, true, Fx, n, false, t1.as<double>(), n);        // X^T F
-      S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Fp.as<double>(), m);
-      S.syevd(Fp.as<double>(), m, eps.as<double>());
-      S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm.as<double>(), m);  // X V
-      hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc)), dim3(256), 0, st, Cm.as<double>(), m,
-                         n, nocc, Cocc.as<double>(), nocc);
+      S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Fq.as<double>(), m);
+      fq_valid = true;
+      int steps = 0;
+      const char* why = "";
+      const bool tried = o.purify && have_y;
+      if (tried && S.purify_occ(Fq.as<double>(), t1.as<double>(), t2.as<double>(), Yo.as<double>(),
+                                Zo.as<double>(), Go.as<double>(), lohi.as<double>(), steps, why)) {
+        if (o.verbose) std::fprintf(stderr, "dfx_scf purification: %d steps\n", steps);
+        S.gemm(n, nocc, m, X.as<double>(), m, false, Yo.as<double>(), nocc, false, Cocc.as<double>(), nocc);
+        cm_valid = false;
+        ++n_purified;
+        purify_steps += steps;
+      } else {
+        if (tried && o.verbose) std::fprintf(stderr, "dfx_scf purification failed (%s), dsyevd\n", why);
+        DFX_HIP(hipMemcpyAsync(Fp.p, Fq.p, 8 * (size_t)m * m, hipMemcpyDeviceToDevice, st));
+        S.syevd(Fp.as<double>(), m, eps.as<double>());
+        S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm.as<double>(), m);  // X V
+        hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc)), dim3(256), 0, st, Cm.as<double>(), m,
+                           n, nocc, Cocc.as<double>(), nocc);
+        hipLaunchKernelGGL(rows_to_cols_kernel, dim3(nblk((int64_t)m * nocc)), dim3(256), 0, st, Fp.as<double>(), m,
+                           0, nocc, Yo.as<double>());
+        have_y = cm_valid = true;
+        ++n_eigh;
+      }
       S.gemm(n, n, nocc, Cocc.as<double>(), nocc, false, Cocc.as<double>(), nocc, true, D.as<double>(), n);
+      sp_eig_all.end();
+      S.eig_spans = &sp_eig_all;
     };
 
     // ---- guess
@@ -451,6 +674,9 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
       S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm.as<double>(), m);
       hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc)), dim3(256), 0, st,
                          Cm.as<double>() + (m - nocc), m, n, nocc, Cocc.as<double>(), nocc);
+      hipLaunchKernelGGL(rows_to_cols_kernel, dim3(nblk((int64_t)m * nocc)), dim3(256), 0, st, Fp.as<double>(), m,
+                         m - nocc, nocc, Yo.as<double>());
+      have_y = true;
       S.gemm(n, n, nocc, Cocc.as<double>(), nocc, false, Cocc.as<double>(), nocc, true, D.as<double>(), n);
     } else {
       throw Error(DFX_EINVAL, "dfx_scf: unknown guess");
@@ -659,6 +885,14 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     const auto t2c = clk::now();
 
     *E_out = E;
+    if ((C_out || eps_out) && !cm_valid && fq_valid) {
+      // orbitals and energies of the Fock matrix whose occupied space gave D
+      DFX_HIP(hipMemcpyAsync(Fp.p, Fq.p, 8 * (size_t)m * m, hipMemcpyDeviceToDevice, st));
+      S.eig_spans = nullptr;
+      S.syevd(Fp.as<double>(), m, eps.as<double>());
+      S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm.as<double>(), m);
+      DFX_HIP(hipStreamSynchronize(st));
+    }
     if (C_out) {
       // full C (n x n): the first m columns from X C', the rest zero
       std::vector<double> Ch((size_t)n * m), Cf((size_t)n * n, 0.0);
@@ -674,6 +908,9 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     }
     inf.niter = it_done;
     inf.guess_fallback = fallback;
+    inf.n_purified = n_purified;
+    inf.n_eigh = n_eigh;
+    inf.purify_steps = purify_steps;
     inf.converged = converged ? 1 : 0;
     inf.n_mixed = n_mixed;
     inf.ndropped = ndrop;

@@ -247,7 +247,7 @@ def test_water_scf_schedules_agree(water, dfx):
     Z = W.charges(water["elems"])
     conv = dict(conv_dE=1e-7, conv_err=1e-5)
     Ep, Cp, _, ip = dfx.scf(xyz, Z, sh, ax, **conv)
-    assert ip["converged"]
+    assert ip["converged"] and ip["n_purified"] >= 1
     nocc = ip["nocc"]
     D = Cp[:, :nocc] @ Cp[:, :nocc].T
     S = dfx.int1e(sh, xyz, Z)[0].cpu().numpy()
@@ -267,7 +267,8 @@ def test_water_scf_schedules_agree(water, dfx):
     El, _, _, il = dfx.scf(xyz, Z, sh, ax, want_c=False, schedule=dfx.SCHED_MIXED, model=m, **conv)
     assert il["converged"] and il["guess_fallback"] == 0
     assert abs(El - Ep) <= 1e-6
-    print(f"(H2O)64: plain {ip['niter']} iterations, mixed core {im['niter']}, mixed learned {il['niter']}")
+    print(f"(H2O)64: plain {ip['niter']} iterations, mixed core {im['niter']}, mixed learned {il['niter']}; "
+          f"purification: {ip['n_purified']} updates, {ip['purify_steps']} squarings")
 
 
 # ---- C30H62 against the oracle's stored energy ---------------------------------

@@ -82,3 +82,25 @@ def test_multi_class_molecule(dfx):
     E, C, _, info = dfx.scf(xyz, Z, sh, ax, max_iter=200)
     assert res.converged and info["converged"]
     assert abs(E - res.E) <= 1e-8
+
+
+@pytest.mark.parametrize("system", ["h4", "mixed"])
+def test_purification_matches_eigensolver(dfx, h4_ref, system):
+    """The occupied space from trace-correcting purification + Cholesky QR gives
+    the energy, density and final orbital energies of dsyevd every iteration."""
+    if system == "h4":
+        xyz, Z, sh, ax, nocc, _ = h4_ref
+    else:
+        xyz, Z, sh, ax = systems.mixed_molecule(seed=3, natom=6, lorb=2, laux=3)
+        Z = np.array([1] * len(Z), np.int32)
+        nocc = 3
+    kw = dict(conv_dE=1e-10, conv_err=1e-8, max_iter=200)
+    E0, C0, e0, i0 = dfx.scf(xyz, Z, sh, ax, purify=0, **kw)
+    E1, C1, e1, i1 = dfx.scf(xyz, Z, sh, ax, purify=1, **kw)
+    assert i0["converged"] and i1["converged"]
+    assert i0["n_purified"] == 0 and i1["n_purified"] >= 1 and i1["n_eigh"] == 1
+    assert abs(E1 - E0) <= 1e-10
+    D0, D1 = C0[:, :nocc] @ C0[:, :nocc].T, C1[:, :nocc] @ C1[:, :nocc].T
+    assert np.abs(D1 - D0).max() <= 1e-7 * max(1.0, np.abs(D0).max())
+    assert np.abs(e1 - e0).max() <= 1e-7
+    print(f"{system}: {i1['n_purified']} purified updates, {i1['purify_steps']} squarings")
