@@ -130,7 +130,8 @@ typedef struct {
   int32_t nbf, naux;
   int64_t ncols_tiled;      /* storage columns of B */
   int64_t bytes_B;          /* kept until dfx_B_free */
-  int64_t bytes_raw;        /* setup only */
+  int64_t bytes_raw;        /* setup only: an upper bound, the raw integrals occupy the
+                               kept packed pair columns (at most the tiled count) */
   int64_t bytes_metric;     /* setup only: J_PQ, L, L^-1 */
   int64_t bytes_setup_peak; /* B + raw + metric */
 } dfx_eri3_sizes;

@@ -254,6 +254,7 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     std::vector<std::vector<int>> cf(16), cs(16);
     std::vector<std::vector<unsigned char>> crow(16);
     std::vector<std::vector<double>> cq(16);
+    std::vector<std::vector<int64_t>> cpc(16);
     int64_t ntrip = 0, nint = 0;
     for (int a = 0; a < nsh; ++a)
       for (int b = 0; b <= a; ++b) {
@@ -262,13 +263,15 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
         B->pa.push_back(a);
         B->pb.push_back(b);
         const int na = 2 * B->bas.l[a] + 1, nb = 2 * B->bas.l[b] + 1;
-        B->col_off.push_back(B->col_off.back() + (int64_t)na * nb);
+        const int64_t first_col = B->col_off.back();
+        B->col_off.push_back(first_col + (int64_t)na * nb);
         const int la = B->bas.l[a], lb = B->bas.l[b];
         const int cls = std::max(la, lb) * 4 + std::min(la, lb);
         cf[cls].push_back(la >= lb ? a : b);
         cs[cls].push_back(la >= lb ? b : a);
         crow[cls].push_back(la >= lb ? 1 : 0);
         cq[cls].push_back(q);
+        cpc[cls].push_back(first_col);
         const int64_t uniq = (a == b) ? (int64_t)na * (na + 1) / 2 : (int64_t)na * nb;
         for (int lc = 0; lc <= 4; ++lc) {
           const int64_t k = count_kept(q, qc_by_l[lc], tau);
@@ -279,8 +282,8 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     B->ncols_p = B->col_off.back();
     B->ncols_t = tiled_cols(nbf);
 
-    // -- raw (mu nu|P), aux-major, tiled columns
-    B->raw.alloc(sizeof(double) * (size_t)naux * B->ncols_t);
+    // -- raw (mu nu|P), aux-major, packed pair columns (screened triplets stay zero)
+    B->raw.alloc(sizeof(double) * (size_t)naux * B->ncols_p);
     DFX_HIP(hipMemsetAsync(B->raw.p, 0, B->raw.n, st));
     std::vector<DevMem> qcl_d(5);
     for (int l = 0; l <= 4; ++l) {
@@ -288,13 +291,14 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
       for (int c : auxby[l]) q.push_back(B->QC[c]);
       qcl_d[l] = upload(q, st);
     }
-    std::vector<DevMem> cf_d(16), cs_d(16), cr_d(16), cq_d(16);
+    std::vector<DevMem> cf_d(16), cs_d(16), cr_d(16), cq_d(16), cpc_d(16);
     for (int cls = 0; cls < 16; ++cls) {
       if (cf[cls].empty()) continue;
       cf_d[cls] = upload(cf[cls], st);
       cs_d[cls] = upload(cs[cls], st);
       cr_d[cls] = upload(crow[cls], st);
       cq_d[cls] = upload(cq[cls], st);
+      cpc_d[cls] = upload(cpc[cls], st);
     }
     tm.stop();
     const double t_metric0 = tm.seconds();
@@ -356,15 +360,16 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
         a.ps = cs_d[cls].as<int>();
         a.rowfirst = cr_d[cls].as<unsigned char>();
         a.pq = cq_d[cls].as<double>();
+        a.pcol = cpc_d[cls].as<int64_t>();
         a.npairs = (int)cf[cls].size();
         a.kl = auxby_d[lc].as<int>();
         a.kq = qcl_d[lc].as<double>();
         a.nk = (int)auxby[lc].size();
         a.tau = tau;
         a.out = B->raw.as<double>();
-        a.ld = B->ncols_t;
+        a.ld = B->ncols_p;
         a.rys = rys;
-        eri3_dispatch(cls / 4, cls % 4, lc, false, STORE_TILED, a, fork.s[k]);
+        eri3_dispatch(cls / 4, cls % 4, lc, false, STORE_PACKED, a, fork.s[k]);
       }
     }
     DFX_HIP(hipGetLastError());
@@ -397,13 +402,37 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     }
     cw.release();
 
-    // -- B = L^-1 raw, split into FP32 hi / lo
+    // -- B = L^-1 raw over the packed columns, split into FP32 hi / lo and
+    // scattered to the tiled layout: packed column -> its tile position (r >= c),
+    // plus the mirror position inside a diagonal tile; of the duplicate columns
+    // (i, j) and (j, i) of a diagonal shell pair only i >= j is stored.  Tile
+    // elements of screened pairs stay zero.
+    std::vector<int64_t> cmap(B->ncols_p), cmap2(B->ncols_p);
+    for (size_t k = 0; k < B->pa.size(); ++k) {
+      const int a = B->pa[k], b = B->pb[k];
+      const int na = 2 * B->bas.l[a] + 1, nb = 2 * B->bas.l[b] + 1;
+      for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j) {
+          const int64_t col = B->col_off[k] + (int64_t)i * nb + j;
+          const int r = B->bas.foff[a] + i, c = B->bas.foff[b] + j;
+          if (r < c) {
+            cmap[col] = cmap2[col] = -1;
+            continue;
+          }
+          const int I = r >> 5, J = c >> 5;
+          cmap[col] = tile_base(I, J) + ((r & 31) << 5) + (c & 31);
+          cmap2[col] = (I == J && r != c) ? tile_base(I, J) + ((c & 31) << 5) + (r & 31) : -1;
+        }
+    }
+    DevMem cmap_d = upload(cmap, st), cmap2_d = upload(cmap2, st);
     GpuTimer tt(st);
     tt.start();
     B->hi.alloc(sizeof(float) * (size_t)naux * B->ncols_t);
     B->lo.alloc(sizeof(float) * (size_t)naux * B->ncols_t);
-    trsm_split(Linv.as<double>(), naux, B->raw.as<double>(), B->ncols_t, B->hi.as<float>(),
-               B->lo.as<float>(), st);
+    DFX_HIP(hipMemsetAsync(B->hi.p, 0, B->hi.n, st));
+    DFX_HIP(hipMemsetAsync(B->lo.p, 0, B->lo.n, st));
+    trsm_split(Linv.as<double>(), naux, B->raw.as<double>(), B->ncols_p, B->hi.as<float>(), B->lo.as<float>(),
+               B->ncols_t, cmap_d.as<int64_t>(), cmap2_d.as<int64_t>(), st);
     DFX_HIP(hipGetLastError());
     tt.stop();
     B->info.trsm_seconds = tt.seconds();

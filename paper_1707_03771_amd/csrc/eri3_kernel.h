@@ -98,6 +98,7 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_kernel(const Eri3Args a) {
   const int foffF = a.F.foff[f], foffS = UNITB ? 0 : a.S.foff[s];
   const bool rowF = UNITB ? true : (a.rowfirst[p] != 0);
   const double qab = a.pq ? a.pq[p] : 1.0;
+  const int64_t pcol = MODE == STORE_PACKED ? a.pcol[p] : 0;
   const double AB0 = A0 - B0, AB1 = A1 - B1, AB2 = A2 - B2;
   const double rAB2 = AB0 * AB0 + AB1 * AB1 + AB2 * AB2;
   constexpr double TWO_PI_52 = 34.98683665524972;  // 2 pi^(5/2)
@@ -105,7 +106,7 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_kernel(const Eri3Args a) {
   const int c0 = blockIdx.y * a.kchunk;
   const int c1 = min(c0 + a.kchunk, a.nk);
   for (int ci = c0; ci < c1; ++ci) {
-    if (MODE == STORE_TILED && !(qab * a.kq[ci] >= a.tau)) continue;
+    if (MODE == STORE_PACKED && !(qab * a.kq[ci] >= a.tau)) continue;
     const int kc = a.kl[ci];
     const double C0 = a.K.ctr[3 * kc], C1 = a.K.ctr[3 * kc + 1], C2 = a.K.ctr[3 * kc + 2];
     const int nkp = a.K.nprim[kc], kpo = a.K.poff[kc];
@@ -189,16 +190,10 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_kernel(const Eri3Args a) {
               });
             }
           });
-          if constexpr (MODE == STORE_TILED) {
-            const int r = rowF ? foffF + ma : foffS + mb;
-            const int c = rowF ? foffS + mb : foffF + ma;
-            if (r >= c) {
-              double* row = out + (int64_t)(kfo + M0 + g) * a.ld;
-              const int I = r >> 5, J = c >> 5;
-              const int64_t base = tile_base(I, J);
-              row[base + ((r & 31) << 5) + (c & 31)] = v;
-              if (I == J) row[base + ((c & 31) << 5) + (r & 31)] = v;
-            }
+          if constexpr (MODE == STORE_PACKED) {
+            // rowF: the lane's first shell is the pair's first (higher-index) shell
+            const int64_t col = pcol + (rowF ? ma * SB + mb : mb * SA + ma);
+            out[(int64_t)(kfo + M0 + g) * a.ld + col] = v;
           } else {
             out[(int64_t)(foffF + ma) * a.ld + kfo + M0 + g] = v;
           }

@@ -4,7 +4,9 @@
 
 namespace dfx {
 
-enum { STORE_TILED = 0, STORE_DENSE = 1 };
+// STORE_PACKED: out[P][pcol[pair] + i nb + j], i over the functions of the pair's
+// first (higher-index) shell, j over the nb of its second; STORE_DENSE: out[mu][P]
+enum { STORE_PACKED = 0, STORE_DENSE = 1 };
 
 struct Eri3Args {
   DevShells F, S, K;         // shells of the first and second bra index and of the ket
@@ -12,6 +14,7 @@ struct Eri3Args {
   const int* ps;             // [npairs] second bra shell (LB); unused with UNITB
   const unsigned char* rowfirst;  // [npairs] 1: first shell indexes rows of B
   const double* pq;          // [npairs] Schwarz factor of the pair, or null
+  const int64_t* pcol;       // [npairs] first packed column of the pair (STORE_PACKED)
   int npairs;
   const int* kl;             // [nk] ket shells of angular momentum LC
   const double* kq;          // [nk] their Schwarz factors

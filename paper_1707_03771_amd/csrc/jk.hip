@@ -145,7 +145,7 @@ void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, 
 }
 
 // ---------------------------------------------------------------------------
-// canonical packed export: out[q - q0][c] = B[q][tileoff[c]]  (hi + lo, or raw)
+// canonical packed export: out[q - q0][c] = B[q][tileoff[c]] (hi + lo), or raw[q][c]
 __global__ void export_kernel(const float* __restrict__ hi, const float* __restrict__ lo,
                               const double* __restrict__ raw, int64_t ncols_t,
                               const int64_t* __restrict__ toff, int64_t ncols_p, int q0,
@@ -154,7 +154,8 @@ __global__ void export_kernel(const float* __restrict__ hi, const float* __restr
   if (c >= ncols_p) return;
   const int q = q0 + blockIdx.y;
   const int64_t o = (int64_t)q * ncols_t + toff[c];
-  out[(int64_t)blockIdx.y * ncols_p + c] = raw ? raw[o] : (double)hi[o] + (lo ? (double)lo[o] : 0.0);
+  out[(int64_t)blockIdx.y * ncols_p + c] =
+      raw ? raw[(int64_t)q * ncols_p + c] : (double)hi[o] + (lo ? (double)lo[o] : 0.0);
 }
 
 // out[q - q0][mu][nu] = B_q (mu, nu) = hi + lo at the packed tile position

@@ -45,6 +45,10 @@ struct GemmF64 {
   bool ta, tb;     // op(A) = A^T, op(B) = B^T
   bool lowerA;     // A is lower triangular (skip zero k-blocks)
   bool lowerC;     // only the lower triangle of C is needed (skip blocks above)
+  // scatter epilogue (B transform): column n of the product goes to column
+  // cmap[n] of hi / lo (none if negative), and also to cmap2[n] if that is >= 0
+  const int64_t* cmap;
+  const int64_t* cmap2;
 };
 void dgemm(const GemmF64& g, hipStream_t st);
 // dgemm, with the k-range split over up to 8 partial products (work: ns M N
@@ -52,10 +56,12 @@ void dgemm(const GemmF64& g, hipStream_t st);
 // fill the chip; the partials are summed in a fixed order
 void dgemm_sk(const GemmF64& g, double* work, int64_t work_elems, hipStream_t st);
 
-// B-transform: out = L^-1 * raw with lower-triangular Linv [n x n], raw [n x ncols],
-// written as hi = fl32(out), lo = fl32(out - hi).
-void trsm_split(const double* Linv, int n, const double* raw, int64_t ncols, float* hi, float* lo,
-                hipStream_t st);
+// B-transform: out = L^-1 * raw with lower-triangular Linv [n x n] and raw
+// [n x ncols] (packed pair columns), written as hi = fl32(out), lo = fl32(out -
+// hi) into rows of length ld_out at the columns cmap (and cmap2, the mirror
+// position inside diagonal tiles).
+void trsm_split(const double* Linv, int n, const double* raw, int64_t ncols, float* hi, float* lo, int64_t ld_out,
+                const int64_t* cmap, const int64_t* cmap2, hipStream_t st);
 
 // Blocked Cholesky J = L L^T in place (lower), then Linv = L^-1.  Returns via
 // *info (device int) the first non-positive pivot + 1, or 0; a pivot below

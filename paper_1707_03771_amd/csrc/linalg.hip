@@ -165,9 +165,16 @@ __global__ void __launch_bounds__(GT, 2) dgemm_kernel(GemmF64 g, float* __restri
             C[o] = v;
           } else {
             const double v = acc[i][j][r];
-            const float h = (float)v;
-            hi[o] = h;
-            lo[o] = (float)(v - (double)h);
+            const float h = (float)v, l = (float)(v - (double)h);
+            const int64_t t = g.cmap[n], t2 = g.cmap2[n];
+            if (t >= 0) {
+              hi[(int64_t)m * g.ldc + t] = h;
+              lo[(int64_t)m * g.ldc + t] = l;
+            }
+            if (t2 >= 0) {
+              hi[(int64_t)m * g.ldc + t2] = h;
+              lo[(int64_t)m * g.ldc + t2] = l;
+            }
           }
         }
       }
@@ -251,8 +258,8 @@ void dgemm_sk(const GemmF64& g, double* work, int64_t work_elems, hipStream_t st
                      g.alpha, g.beta, g.C, g.ldc);
 }
 
-void trsm_split(const double* Linv, int n, const double* raw, int64_t ncols, float* hi, float* lo,
-                hipStream_t st) {
+void trsm_split(const double* Linv, int n, const double* raw, int64_t ncols, float* hi, float* lo, int64_t ld_out,
+                const int64_t* cmap, const int64_t* cmap2, hipStream_t st) {
   // columns in slabs so that the grid stays within one launch's int range
   const int64_t slab = (int64_t)GN * 65536;
   for (int64_t c0 = 0; c0 < ncols; c0 += slab) {
@@ -261,11 +268,13 @@ void trsm_split(const double* Linv, int n, const double* raw, int64_t ncols, flo
     g.M = n; g.N = nc; g.K = n;
     g.A = Linv; g.lda = n;
     g.B = raw + c0; g.ldb = ncols;
-    g.C = nullptr; g.ldc = ncols;
+    g.C = nullptr; g.ldc = ld_out;
     g.alpha = 1.0; g.beta = 0.0; g.batch = 1;
     g.lowerA = true;
+    g.cmap = cmap + c0;
+    g.cmap2 = cmap2 + c0;
     const dim3 grid(gemm_tiles(g.M, g.N));
-    hipLaunchKernelGGL((dgemm_kernel<false, false, EPI_SPLIT>), grid, dim3(GT), 0, st, g, hi + c0, lo + c0);
+    hipLaunchKernelGGL((dgemm_kernel<false, false, EPI_SPLIT>), grid, dim3(GT), 0, st, g, hi, lo);
   }
 }
 
