@@ -50,9 +50,10 @@ extern "C" {
 #define DFX_EUNSUPPORTED (-6)  /* angular momentum beyond the compiled classes */
 
 /* ---- precisions / kinds ---------------------------------------------------- */
+/* precision of K; J always reads B = hi + lo with FP64 accumulation */
 #define DFX_FP64 0   /* B as hi + lo (FP64-equivalent), FP64 MFMA */
-#define DFX_FP32 1   /* B hi word only, FP32 MFMA, FP32 accumulation */
-#define DFX_BF16 2   /* B hi word rounded to BF16, BF16 MFMA, FP32 accumulation */
+#define DFX_FP32 1   /* B hi word only, FP32 MFMA, FP32 sums of 32 products added in FP64 */
+#define DFX_BF16 2   /* B hi word rounded to BF16, BF16 MFMA, the same accumulation */
 
 #define DFX_DENSITY 0  /* dfx_jk input is D (nbf x nbf) */
 #define DFX_COCC 1     /* dfx_jk input is C_occ (nbf x nocc); D = C_occ C_occ^T */
@@ -180,7 +181,10 @@ int dfx_B_free(dfx_B* b);
  *              signed factorisation D = C+ C+^T - C- C-^T from D's
  *              eigenvectors (eigenvalues below 1e-14 of the largest dropped);
  *              that call synchronises the stream.
- *   precision  DFX_FP64 | DFX_FP32 | DFX_BF16
+ *   precision  DFX_FP64 | DFX_FP32 | DFX_BF16, for K.  J reads both words of B
+ *              in every precision: it is bandwidth-bound, and from the hi word
+ *              alone its error, amplified by the conditioning of the metric,
+ *              would exceed that of the FP32 K (by about 100x on (H2O)64)
  *   dev_J, dev_K  nbf x nbf outputs, either may be NULL
  * Errors: DFX_EINVAL, DFX_ENOMEM, DFX_EHIP, DFX_EUNSUPPORTED.
  */

@@ -34,27 +34,21 @@ __global__ void pack_density_kernel(const double* __restrict__ D, int nbf, doubl
   }
 }
 
-// gamma_Q = sum_c B[Q][c] d[c], FP64 accumulation, one workgroup per Q
-template <bool LO>
+// gamma_Q = sum_c B[Q][c] d[c], B = hi + lo, FP64 accumulation, one workgroup per Q
 __global__ void __launch_bounds__(256) j_gamma_kernel(const float* __restrict__ hi,
                                                       const float* __restrict__ lo, int64_t ncols,
                                                       const double* __restrict__ d, double* gam) {
   const int Q = blockIdx.x;
   const float4* h4 = reinterpret_cast<const float4*>(hi + (int64_t)Q * ncols);
-  const float4* l4 = reinterpret_cast<const float4*>((LO ? lo : hi) + (int64_t)Q * ncols);
+  const float4* l4 = reinterpret_cast<const float4*>(lo + (int64_t)Q * ncols);
   const double4* d4 = reinterpret_cast<const double4*>(d);
   const int64_t n4 = ncols >> 2;
   double s = 0.0;
   for (int64_t i = threadIdx.x; i < n4; i += blockDim.x) {
-    const float4 h = h4[i];
+    const float4 h = h4[i], l = l4[i];
     const double4 dd = d4[i];
-    if (LO) {
-      const float4 l = l4[i];
-      s += ((double)h.x + (double)l.x) * dd.x + ((double)h.y + (double)l.y) * dd.y +
-           ((double)h.z + (double)l.z) * dd.z + ((double)h.w + (double)l.w) * dd.w;
-    } else {
-      s += (double)h.x * dd.x + (double)h.y * dd.y + (double)h.z * dd.z + (double)h.w * dd.w;
-    }
+    s += ((double)h.x + (double)l.x) * dd.x + ((double)h.y + (double)l.y) * dd.y +
+         ((double)h.z + (double)l.z) * dd.z + ((double)h.w + (double)l.w) * dd.w;
   }
   __shared__ double red[256];
   red[threadIdx.x] = s;
@@ -66,8 +60,7 @@ __global__ void __launch_bounds__(256) j_gamma_kernel(const float* __restrict__ 
   if (threadIdx.x == 0) gam[Q] = red[0];
 }
 
-// Jvec[c] = sum_Q B[Q][c] gamma_Q, four columns per thread, fixed Q order
-template <bool LO>
+// Jvec[c] = sum_Q B[Q][c] gamma_Q, B = hi + lo, four columns per thread, fixed Q order
 __global__ void __launch_bounds__(256) j_back_kernel(const float* __restrict__ hi,
                                                      const float* __restrict__ lo, int64_t ncols,
                                                      int naux, const double* __restrict__ gam,
@@ -76,23 +69,15 @@ __global__ void __launch_bounds__(256) j_back_kernel(const float* __restrict__ h
   if (c4 >= (ncols >> 2)) return;
   double a0 = 0, a1 = 0, a2 = 0, a3 = 0;
   const float4* h4 = reinterpret_cast<const float4*>(hi) + c4;
-  const float4* l4 = reinterpret_cast<const float4*>(LO ? lo : hi) + c4;
+  const float4* l4 = reinterpret_cast<const float4*>(lo) + c4;
   const int64_t stride = ncols >> 2;
   for (int Q = 0; Q < naux; ++Q) {
     const double g = gam[Q];
-    const float4 h = h4[Q * stride];
-    if (LO) {
-      const float4 l = l4[Q * stride];
-      a0 = fma((double)h.x + (double)l.x, g, a0);
-      a1 = fma((double)h.y + (double)l.y, g, a1);
-      a2 = fma((double)h.z + (double)l.z, g, a2);
-      a3 = fma((double)h.w + (double)l.w, g, a3);
-    } else {
-      a0 = fma((double)h.x, g, a0);
-      a1 = fma((double)h.y, g, a1);
-      a2 = fma((double)h.z, g, a2);
-      a3 = fma((double)h.w, g, a3);
-    }
+    const float4 h = h4[Q * stride], l = l4[Q * stride];
+    a0 = fma((double)h.x + (double)l.x, g, a0);
+    a1 = fma((double)h.y + (double)l.y, g, a1);
+    a2 = fma((double)h.z + (double)l.z, g, a2);
+    a3 = fma((double)h.w + (double)l.w, g, a3);
   }
   reinterpret_cast<double4*>(jv)[c4] = double4{a0, a1, a2, a3};
 }
@@ -116,16 +101,12 @@ void j_build(const JKArgs& a, const double* D, double* J, double* work, hipStrea
   double* gam = work + a.ncols;              // naux
   double* jv = gam + ((a.naux + 3) & ~3);    // ncols
   hipLaunchKernelGGL(pack_density_kernel, dim3(nt * (nt + 1) / 2), dim3(256), 0, st, D, a.nbf, dvec);
-  const bool lo = (a.prec == PREC_FP64);
-  if (lo)
-    hipLaunchKernelGGL(j_gamma_kernel<true>, dim3(a.naux), dim3(256), 0, st, a.hi, a.lo, a.ncols, dvec, gam);
-  else
-    hipLaunchKernelGGL(j_gamma_kernel<false>, dim3(a.naux), dim3(256), 0, st, a.hi, a.lo, a.ncols, dvec, gam);
+  // both words of B in every precision: J is bandwidth-bound, and with the hi
+  // word alone its error (amplified by the conditioning of the metric) exceeds
+  // that of a reduced-precision K
+  hipLaunchKernelGGL(j_gamma_kernel, dim3(a.naux), dim3(256), 0, st, a.hi, a.lo, a.ncols, dvec, gam);
   const unsigned gb = (unsigned)(((a.ncols >> 2) + 255) / 256);
-  if (lo)
-    hipLaunchKernelGGL(j_back_kernel<true>, dim3(gb), dim3(256), 0, st, a.hi, a.lo, a.ncols, a.naux, gam, jv);
-  else
-    hipLaunchKernelGGL(j_back_kernel<false>, dim3(gb), dim3(256), 0, st, a.hi, a.lo, a.ncols, a.naux, gam, jv);
+  hipLaunchKernelGGL(j_back_kernel, dim3(gb), dim3(256), 0, st, a.hi, a.lo, a.ncols, a.naux, gam, jv);
   const int64_t n2 = (int64_t)a.nbf * a.nbf;
   hipLaunchKernelGGL(unpack_sym_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, jv, a.nbf, J);
 }

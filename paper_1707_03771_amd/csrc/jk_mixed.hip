@@ -5,7 +5,8 @@
 // Phase 1 (half transform) reads each packed 32x32 tile of B_Q from HBM and
 // multiplies it by all occupied columns at once, so B is streamed once per use;
 // X is written in the compute precision.  Phase 2 is a split-K SYRK over the
-// (Q, i) index into FP32 partial sums, reduced in FP64 in a fixed order.
+// (Q, i) index: FP32 MFMA sums of KT products, added up in FP64, reduced over
+// the slices in FP64 in a fixed order.
 #include "kernels.h"
 
 namespace dfx {
@@ -172,11 +173,15 @@ __global__ void __launch_bounds__(256) kx_mixed_kernel(const float* __restrict__
 // ---- phase 2: P_s = X_s X_s^T (lower 128x128 tiles) for k-slices s of X.
 // Workgroups are dealt round-robin to the 8 XCDs; the map sends every tile of a
 // slice to one XCD so that the slice of X is fetched from HBM once per XCD L2.
+// Eight waves in a 2 x 4 grid of 64 x 32 sub-tiles.  The MFMAs accumulate one
+// k-stage (KT products) in FP32; each stage's sums are added into FP64
+// registers, so no FP32 accumulator sums more than KT products.  On a diagonal
+// tile the two waves whose sub-tiles lie above the diagonal skip their MFMAs.
+constexpr int SYM_T = 512;
 template <class Tr>
-__global__ void __launch_bounds__(256) syrk_mixed_kernel(const typename Tr::E* __restrict__ X,
-                                                         int64_t ldx, int nbf, int64_t kslice,
-                                                         int64_t kdim, int nslices, int ntl,
-                                                         float* __restrict__ P) {
+__global__ void __launch_bounds__(SYM_T) syrk_mixed_kernel(const typename Tr::E* __restrict__ X, int64_t ldx,
+                                                           int nbf, int64_t kslice, int64_t kdim, int nslices,
+                                                           int ntl, double* __restrict__ P) {
   using E = typename Tr::E;
   __shared__ __align__(16) E As[128][KT + LPAD];
   __shared__ __align__(16) E Bs[128][KT + LPAD];
@@ -194,75 +199,86 @@ __global__ void __launch_bounds__(256) syrk_mixed_kernel(const typename Tr::E* _
   const int64_t k0s = (int64_t)s * kslice;
   const int64_t k1s = k0s + kslice < kdim ? k0s + kslice : kdim;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = (w & 1) * 64, wn = (w >> 1) * 64;
+  const int wm = (w & 1) * 64, wn = (w >> 1) * 32;
+  const bool active = !(ti == tj && wn >= wm + 64);
   const int li = lane & 15, lk = lane >> 4;
-  v4f acc[4][4];
+  // loader: row r of both operands, 8 consecutive k from k8
+  const int r = tid >> 2, k8 = (tid & 3) * 8;
+  const int ma = m0 + r, nb = n0 + r;
+
+  W8<E> va, vb;
+  auto load = [&](int64_t k0) {
+#pragma unroll
+    for (int i = 0; i < W8<E>::N; ++i) va.w[i] = vb.w[i] = make_uint4(0, 0, 0, 0);
+    if (k0 + KT <= k1s) {
+      if (ma < nbf) va = ld8(X + (int64_t)ma * ldx + k0 + k8);
+      if (nb < nbf) vb = ld8(X + (int64_t)nb * ldx + k0 + k8);
+    } else {  // ragged end of the slice: element by element
+      E ea[8], eb[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t k = k0 + k8 + e;
+        ea[e] = (ma < nbf && k < k1s) ? X[(int64_t)ma * ldx + k] : cvt<E>(0.0f);
+        eb[e] = (nb < nbf && k < k1s) ? X[(int64_t)nb * ldx + k] : cvt<E>(0.0f);
+      }
+      __builtin_memcpy(&va, ea, sizeof ea);
+      __builtin_memcpy(&vb, eb, sizeof eb);
+    }
+  };
+
+  double sum[4][2][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sum[a][b][q] = 0.0;
+
+  if (k0s < k1s) load(k0s);
   for (int64_t k0 = k0s; k0 < k1s; k0 += KT) {
-    W8<E> va[2], vb[2];
-    const bool full = k0 + KT <= k1s;
-    if (full) {
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int ch = tid + c * 256;  // 512 chunks of 8 per operand
-        const int r = ch >> 2, k8 = (ch & 3) * 8;
-        const int ma = m0 + r, nb = n0 + r;
-#pragma unroll
-        for (int i = 0; i < W8<E>::N; ++i) va[c].w[i] = vb[c].w[i] = make_uint4(0, 0, 0, 0);
-        if (ma < nbf) va[c] = ld8(X + (int64_t)ma * ldx + k0 + k8);
-        if (nb < nbf) vb[c] = ld8(X + (int64_t)nb * ldx + k0 + k8);
-      }
-    }
+    __syncthreads();  // every wave is done with the previous stage
+    st8(&As[r][k8], va);
+    st8(&Bs[r][k8], vb);
     __syncthreads();
-    if (full) {
-#pragma unroll
-      for (int c = 0; c < 2; ++c) {
-        const int ch = tid + c * 256;
-        const int r = ch >> 2, k8 = (ch & 3) * 8;
-        st8(&As[r][k8], va[c]);
-        st8(&Bs[r][k8], vb[c]);
-      }
-    } else {  // ragged end of the slice: element by element
-      for (int c = 0; c < 2; ++c) {
-        const int ch = tid + c * 256;
-        const int r = ch >> 2, k8 = (ch & 3) * 8;
-        const int ma = m0 + r, nb = n0 + r;
-        for (int e = 0; e < 8; ++e) {
-          const int64_t k = k0 + k8 + e;
-          As[r][k8 + e] = (ma < nbf && k < k1s) ? X[(int64_t)ma * ldx + k] : cvt<E>(0.0f);
-          Bs[r][k8 + e] = (nb < nbf && k < k1s) ? X[(int64_t)nb * ldx + k] : cvt<E>(0.0f);
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < KT; kk += Tr::KM)
+    if (k0 + KT < k1s) load(k0 + KT);  // in flight during the MFMAs below
+    if (active) {
+      v4f acc[4][2];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b)
-          acc[a][b] = Tr::mma(&As[wm + a * 16 + li][kk + Tr::koff(lk)], &Bs[wn + b * 16 + li][kk + Tr::koff(lk)],
-                              acc[a][b]);
-    __syncthreads();
+        for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < KT; kk += Tr::KM)
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            acc[a][b] = Tr::mma(&As[wm + a * 16 + li][kk + Tr::koff(lk)], &Bs[wn + b * 16 + li][kk + Tr::koff(lk)],
+                                acc[a][b]);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) sum[a][b][q] += (double)acc[a][b][q];
+    }
   }
-  float* __restrict__ Ps = P + (int64_t)s * nbf * nbf;
+  if (!active) return;
+  double* __restrict__ Ps = P + (int64_t)s * nbf * nbf;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int m = m0 + wm + a * 16 + lk * 4 + r;
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + wm + a * 16 + lk * 4 + q;
         const int n = n0 + wn + b * 16 + li;
-        if (m < nbf && n < nbf && n <= m) Ps[(int64_t)m * nbf + n] = acc[a][b][r];
+        if (m < nbf && n <= m) Ps[(int64_t)m * nbf + n] = sum[a][b][q];
       }
 }
 
 // K (lower) = sum_s P_s in FP64, fixed order; then mirrored by the caller
-__global__ void k_reduce_mixed_kernel(const float* __restrict__ P, int ns, int nbf, double* __restrict__ K,
+__global__ void k_reduce_mixed_kernel(const double* __restrict__ P, int ns, int nbf, double* __restrict__ K,
                                       int accumulate) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n2 = (int64_t)nbf * nbf;
@@ -270,7 +286,7 @@ __global__ void k_reduce_mixed_kernel(const float* __restrict__ P, int ns, int n
   const int r = (int)(idx / nbf), c = (int)(idx % nbf);
   if (c > r) return;
   double s = accumulate ? K[idx] : 0.0;
-  for (int k = 0; k < ns; ++k) s += (double)P[k * n2 + idx];
+  for (int k = 0; k < ns; ++k) s += P[k * n2 + idx];
   K[idx] = s;
 }
 
@@ -292,13 +308,9 @@ static MixedPlan mixed_plan(const JKArgs& a, int nocc, size_t esize) {
   p.kdim = (int64_t)p.qc * nocc;
   const int mt = (a.nbf + 127) / 128;
   p.ntl = mt * (mt + 1) / 2;
-  // enough slices to fill the chip several times over, a multiple of 8, and short
-  // enough that each FP32 accumulator sums at most ~8192 products before the FP64
-  // reduction (partial sums capped at ~1 GiB)
+  // enough slices to fill the chip several times over, a multiple of 8 (the FP32
+  // sums are already flushed to FP64 every KT products inside the kernel)
   int ns = (2048 + p.ntl - 1) / p.ntl;
-  const int64_t by_len = (p.kdim + 8191) / 8192;
-  const int64_t by_mem = ((int64_t)1 << 30) / ((int64_t)a.nbf * a.nbf * 4);
-  ns = (int)std::max<int64_t>(ns, std::min<int64_t>(by_len, by_mem));
   ns = ((ns + 7) / 8) * 8;
   const int64_t maxs = (p.kdim + KT - 1) / KT;
   if (ns > maxs) ns = (int)(((maxs + 7) / 8) * 8);
@@ -307,7 +319,7 @@ static MixedPlan mixed_plan(const JKArgs& a, int nocc, size_t esize) {
   p.kslice = ((p.kdim + ns - 1) / ns + KT - 1) / KT * KT;
   p.ct_bytes = (size_t)p.npad * p.nbfp * esize;
   p.x_bytes = (size_t)a.nbf * ((p.kdim + 7) / 8 * 8) * esize;
-  p.p_bytes = (size_t)ns * a.nbf * a.nbf * sizeof(float);
+  p.p_bytes = (size_t)ns * a.nbf * a.nbf * sizeof(double);
   return p;
 }
 
@@ -326,7 +338,7 @@ static void k_build_tr(const JKArgs& a, const double* C, int nocc, double* K, vo
   char* w = reinterpret_cast<char*>(work);
   E* Ct = reinterpret_cast<E*>(w);
   E* X = reinterpret_cast<E*>(w + ((p.ct_bytes + 255) & ~(size_t)255));
-  float* P = reinterpret_cast<float*>(w + ((p.ct_bytes + 255) & ~(size_t)255) + ((p.x_bytes + 255) & ~(size_t)255));
+  double* P = reinterpret_cast<double*>(w + ((p.ct_bytes + 255) & ~(size_t)255) + ((p.x_bytes + 255) & ~(size_t)255));
   const int64_t ctn = (int64_t)p.npad * p.nbfp;
   hipLaunchKernelGGL(ct_kernel<E>, dim3((unsigned)((ctn + 255) / 256)), dim3(256), 0, st, C, a.nbf, nocc, p.npad,
                      p.nbfp, Ct);
@@ -351,7 +363,7 @@ static void k_build_tr(const JKArgs& a, const double* C, int nocc, double* K, vo
     int ns = p.ns;
     int64_t kslice = ((kdim + ns - 1) / ns + KT - 1) / KT * KT;
     const int nblocks = ((ns + 7) / 8) * 8 * p.ntl;
-    hipLaunchKernelGGL(syrk_mixed_kernel<Tr>, dim3(nblocks), dim3(256), 0, st, X, ldx, a.nbf, kslice, kdim, ns,
+    hipLaunchKernelGGL(syrk_mixed_kernel<Tr>, dim3(nblocks), dim3(SYM_T), 0, st, X, ldx, a.nbf, kslice, kdim, ns,
                        p.ntl, P);
     hipLaunchKernelGGL(k_reduce_mixed_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, P, ns, a.nbf,
                        K, q0 > 0 ? 1 : 0);
