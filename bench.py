@@ -400,6 +400,8 @@ def main():
             f"j {info['t_j']:.3f} kx {info['t_kx']:.3f} ksyrk {info['t_ksyrk']:.3f} eig {info['t_eig']:.3f}")
         pn = {0: "d", 1: "s", 2: "b"}
         log("   history: " + " ".join(f"{pn.get(p, '?')}{e:.1e}" for p, e in zip(info["prec_hist"], info["err_hist"])))
+        eh = info["E_hist"]
+        log("   |dE|:    " + " ".join(f"{abs(eh[k] - eh[k - 1]):.1e}" for k in range(1, len(eh))))
         if info["guess_fallback"]:
             log(f"   learned guess fell back to the core guess (code {info['guess_fallback']})")
         return E, info, dt

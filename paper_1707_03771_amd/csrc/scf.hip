@@ -817,13 +817,16 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
       Eold = E;
       // next precision stage once the error is below the stage threshold, or the
       // stage has stalled: no factor-2 gain of its best error over the last WIN
-      // iterations, WIN = 8 while the error is above 1e-2 (the erratic start from a
-      // poor guess) and 4 below it, where the reduced-precision floors lie.
+      // iterations.  WIN = 4 once the error is below 1e-2, where the reduced-precision
+      // floors lie.  Above it a stall is the erratic start from a poor guess, which
+      // FP64 would not cure: WIN = 16 in FP32 (its floor is far lower), 8 in BF16.
       // The DIIS history restarts: Fock matrices of the coarser precision would pin
       // the extrapolation at their own error level.
       stage_errs.push_back(emax);
       bool stalled = false;
-      const int WIN = *std::min_element(stage_errs.begin(), stage_errs.end()) < 1e-2 ? 4 : 8;
+      const int WIN = *std::min_element(stage_errs.begin(), stage_errs.end()) < 1e-2 ? 4
+                      : prec == DFX_BF16                                              ? 8
+                                                                                      : 16;
       if (stage_it > WIN) {
         const double recent = *std::min_element(stage_errs.end() - WIN, stage_errs.end());
         const double before = *std::min_element(stage_errs.begin(), stage_errs.end() - WIN);
