@@ -241,7 +241,9 @@ typedef struct {
                             error is below 1e-2, estimate its floor: K in that precision
                             and in FP64 on every 16th auxiliary function, the DIIS-error
                             commutator of the difference scaled by sqrt(16); the stage
-                            ends once its error is below max(switch_err, estimate) */
+                            ends once its error is below max(switch_err, estimate).  Into
+                            FP64 from a stage with an estimate <= 1e-3 the DIIS history
+                            carries over; otherwise DIIS restarts */
   int32_t purify;        /* 1 (default): after the first iteration, the occupied orbitals of
                             X^T F X come from trace-correcting purification (Niklasson,
                             Phys. Rev. B 66, 155115 (2002)) and a Cholesky QR of the

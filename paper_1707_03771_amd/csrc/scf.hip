@@ -820,8 +820,12 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
       // iterations.  WIN = 4 once the error is below 1e-2, where the reduced-precision
       // floors lie.  Above it a stall is the erratic start from a poor guess, which
       // FP64 would not cure: WIN = 16 in FP32 (its floor is far lower), 8 in BF16.
-      // The DIIS history restarts: Fock matrices of the coarser precision would pin
-      // the extrapolation at their own error level.
+      // Into FP64 from a stage whose floor was measured at or below 1e-3, the DIIS
+      // history carries over: those Fock matrices are good enough to extrapolate
+      // with, and the FP64 entries take over as their errors fall below the floor.
+      // Otherwise (BF16, or a stage that stalled before its floor was measured) the
+      // history restarts from a plain diagonalisation, since the coarse Fock
+      // matrices would pin the extrapolation at their own error level.
       stage_errs.push_back(emax);
       bool stalled = false;
       const int WIN = *std::min_element(stage_errs.begin(), stage_errs.end()) < 1e-2 ? 4
@@ -838,10 +842,13 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
         stage_it = 0;
         stage_errs.clear();
         stage_estimated = false;
-        hcount = 0;
-        hpos = 0;
-        diag(F.as<double>());
-        continue;
+        const double fl = floor_est[stages[stage - 1]];
+        if (prec != DFX_FP64 || !(fl > 0.0 && fl <= 1e-3)) {
+          hcount = 0;
+          hpos = 0;
+          diag(F.as<double>());
+          continue;
+        }
       }
       // DIIS history (ring buffer)
       DFX_HIP(hipMemcpyAsync(Fh[hpos].p, F.p, 8 * n2, hipMemcpyDeviceToDevice, st));
