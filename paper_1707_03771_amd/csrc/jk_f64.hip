@@ -15,7 +15,8 @@ namespace dfx {
 typedef double v4d __attribute__((ext_vector_type(4)));
 
 constexpr int S64 = 16;   // k-width of one LDS stage (half a tile column of B_Q)
-constexpr int PA = 2;     // row padding (doubles) of [row][k] tiles: conflict-free A/B fragments
+constexpr int PA = 1;     // row padding (doubles) of [row][k] tiles: odd row strides keep the
+                          // fragment reads of 16 consecutive rows on distinct banks
 constexpr int PB = 16;    // row padding (doubles) of the [k][i] C stage
 
 // C_occ zero-padded to Cp[nbfp][np] (np = 64 NCB, nbfp = 32 ntiles), so that a

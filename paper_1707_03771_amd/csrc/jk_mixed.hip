@@ -37,7 +37,9 @@ struct F32Tr {
 };
 
 constexpr int KT = 32;       // k-width of one LDS stage (one tile column of B_Q)
-constexpr int LPAD = 8;      // LDS row padding (elements)
+// LDS row padding: 16 bytes, so that rows stay 16-byte aligned for vector stores
+// while the FP32 fragment reads of 16 consecutive rows spread over the banks
+template <class E> constexpr int lpad() { return 16 / (int)sizeof(E); }
 
 template <class E> __device__ __forceinline__ E cvt(float x) { return (E)x; }
 
@@ -87,8 +89,8 @@ __global__ void __launch_bounds__(256) kx_mixed_kernel(const float* __restrict__
                                                        int64_t ldx) {
   using E = typename Tr::E;
   constexpr int NP = 64 * NCB;  // padded occupied columns
-  __shared__ __align__(16) E As[64][KT + LPAD];
-  __shared__ __align__(16) E Bs[NP][KT + LPAD];
+  __shared__ __align__(16) E As[64][KT + lpad<E>()];
+  __shared__ __align__(16) E Bs[NP][KT + lpad<E>()];
   const int Q = q0 + blockIdx.y;
   const int m0 = blockIdx.x * 64;
   const int I0 = m0 >> 5;
@@ -183,8 +185,8 @@ __global__ void __launch_bounds__(SYM_T) syrk_mixed_kernel(const typename Tr::E*
                                                            int nbf, int64_t kslice, int64_t kdim, int nslices,
                                                            int ntl, double* __restrict__ P) {
   using E = typename Tr::E;
-  __shared__ __align__(16) E As[128][KT + LPAD];
-  __shared__ __align__(16) E Bs[128][KT + LPAD];
+  __shared__ __align__(16) E As[128][KT + lpad<E>()];
+  __shared__ __align__(16) E Bs[128][KT + lpad<E>()];
   // blockIdx.x -> (slice, lower tile)
   const int bid = blockIdx.x;
   const int xcd = bid & 7, local = bid >> 3;
