@@ -383,7 +383,7 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     DevMem Lw(sizeof(double) * (size_t)naux * naux);
     DFX_HIP(hipMemcpyAsync(Lw.p, B->J2.p, Lw.n, hipMemcpyDeviceToDevice, st));
     DevMem Linv(sizeof(double) * (size_t)naux * naux);
-    DevMem cw(sizeof(double) * (size_t)naux * 65);
+    DevMem cw(sizeof(double) * cholesky_work_elems(naux));
     DevMem info_d(sizeof(int));
     cholesky_inverse(Lw.as<double>(), naux, Linv.as<double>(), cw.as<double>(), info_d.as<int>(), st);
     int info = 0;
@@ -493,7 +493,7 @@ int dfx_cholesky(double* dev_A, int n, double* dev_Linv, void* stream) {
   return guard([&] {
     if (!dev_A || !dev_Linv || n <= 0) throw Error(DFX_EINVAL, "dfx_cholesky: bad argument");
     hipStream_t st = (hipStream_t)stream;
-    DevMem cw(sizeof(double) * (size_t)n * 65);
+    DevMem cw(sizeof(double) * cholesky_work_elems(n));
     DevMem info_d(sizeof(int));
     cholesky_inverse(dev_A, n, dev_Linv, cw.as<double>(), info_d.as<int>(), st);
     int info = 0;

@@ -66,8 +66,9 @@ void trsm_split(const double* Linv, int n, const double* raw, int64_t ncols, flo
 // Blocked Cholesky J = L L^T in place (lower), then Linv = L^-1.  Returns via
 // *info (device int) the first non-positive pivot + 1, or 0; a pivot below
 // 1e-14 of its original diagonal element counts as non-positive.
-// work: n * 65 doubles.
+// work: cholesky_work_elems(n) doubles.
 void cholesky_inverse(double* J, int n, double* Linv, double* work, int* info, hipStream_t st);
+size_t cholesky_work_elems(int n);
 
 // ---- J / K (jk.hip) ----------------------------------------------------------
 enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2 };
