@@ -238,6 +238,24 @@ __global__ void diag_minmax_kernel(const double* __restrict__ G, int k, double* 
   }
 }
 
+// Y[i] uniform in [-1, 1) from a counter hash (SplitMix64 finaliser): a start for
+// the Cholesky QR of P Y when there are no previous orbitals
+__global__ void rand_fill_kernel(double* __restrict__ Y, int64_t n, uint64_t seed) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(i + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z ^= z >> 31;
+  Y[i] = (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
+
+// A = -A (element-wise)
+__global__ void negate_kernel(double* __restrict__ A, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) A[i] = -A[i];
+}
+
 static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 // ---- driver ---------------------------------------------------------------------------
@@ -669,13 +687,37 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
         S.gemm(m, n, n, Uk.as<double>(), m, true, Di.as<double>(), n, false, t1.as<double>(), n);    // U^T P
         S.gemm(m, m, n, t1.as<double>(), n, false, Uk.as<double>(), m, false, Fp.as<double>(), m);
       }
-      S.syevd(Fp.as<double>(), m, eps.as<double>());
-      // eigenvectors of the largest nocc eigenvalues are the last nocc rows
-      S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm.as<double>(), m);
-      hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc)), dim3(256), 0, st,
-                         Cm.as<double>() + (m - nocc), m, n, nocc, Cocc.as<double>(), nocc);
-      hipLaunchKernelGGL(rows_to_cols_kernel, dim3(nblk((int64_t)m * nocc)), dim3(256), 0, st, Fp.as<double>(), m,
-                         m - nocc, nocc, Yo.as<double>());
+      // the top nocc eigenvectors span the occupied space of the lowest levels of
+      // -P': purified from a seeded random start, else dsyevd
+      bool done = false;
+      if (o.purify) {
+        const int64_t mm = (int64_t)m * m, mo = (int64_t)m * nocc;
+        DFX_HIP(hipMemcpyAsync(Fq.p, Fp.p, 8 * (size_t)mm, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(negate_kernel, dim3(nblk(mm)), dim3(256), 0, st, Fq.as<double>(), mm);
+        hipLaunchKernelGGL(rand_fill_kernel, dim3(nblk(mo)), dim3(256), 0, st, Yo.as<double>(), mo,
+                           (uint64_t)0x5DEECE66Dull);
+        int steps = 0;
+        const char* why = "";
+        done = S.purify_occ(Fq.as<double>(), t1.as<double>(), t2.as<double>(), Yo.as<double>(), Zo.as<double>(),
+                            Go.as<double>(), lohi.as<double>(), steps, why);
+        if (o.verbose) {
+          if (done)
+            std::fprintf(stderr, "dfx_scf guess purification: %d steps\n", steps);
+          else
+            std::fprintf(stderr, "dfx_scf guess purification failed (%s)\n", why);
+        }
+        if (done)
+          S.gemm(n, nocc, m, X.as<double>(), m, false, Yo.as<double>(), nocc, false, Cocc.as<double>(), nocc);
+      }
+      if (!done) {
+        S.syevd(Fp.as<double>(), m, eps.as<double>());
+        // eigenvectors of the largest nocc eigenvalues are the last nocc rows
+        S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm.as<double>(), m);
+        hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc)), dim3(256), 0, st,
+                           Cm.as<double>() + (m - nocc), m, n, nocc, Cocc.as<double>(), nocc);
+        hipLaunchKernelGGL(rows_to_cols_kernel, dim3(nblk((int64_t)m * nocc)), dim3(256), 0, st, Fp.as<double>(),
+                           m, m - nocc, nocc, Yo.as<double>());
+      }
       have_y = true;
       S.gemm(n, n, nocc, Cocc.as<double>(), nocc, false, Cocc.as<double>(), nocc, true, D.as<double>(), n);
     } else {

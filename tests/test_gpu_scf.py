@@ -41,10 +41,15 @@ def test_restart_from_converged_orbitals(dfx, h4_ref):
     assert abs(E2 - E) <= 1e-10 and info2["niter"] <= 3
 
 
-def test_density_guess(dfx, h4_ref):
+@pytest.mark.parametrize("purify", [0, 1])
+def test_density_guess(dfx, h4_ref, purify):
+    """The converged density as the start: its occupied space by dsyevd or by
+    purification from a seeded random start converges at once."""
     xyz, Z, sh, ax, nocc, ref = h4_ref
-    E, _, _, info = dfx.scf(xyz, Z, sh, ax, init=ref.D, guess=dfx.GUESS_DENSITY)
+    E, _, _, info = dfx.scf(xyz, Z, sh, ax, init=ref.D, guess=dfx.GUESS_DENSITY, purify=purify)
     assert abs(E - ref.E) <= 1e-8 and info["niter"] <= 3
+    if purify:
+        assert info["n_eigh"] == 0
 
 
 def test_not_converged_is_reported_with_outputs(dfx, h4_ref):
