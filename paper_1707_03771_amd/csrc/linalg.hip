@@ -378,35 +378,9 @@ __global__ void diag_kernel(const double* A, int n, double* d) {
 
 // J (n x n, lower part used) -> L in place (upper zeroed), Linv = L^-1.
 // work: at least n * (CB + 1) doubles.
-// X = L^-1 on the diagonal block [off, off + len) of a lower-triangular L (row-major,
-// leading dimension n), given X's inverted diagonal CB-blocks:
-//   [L11 0; L21 L22]^-1 = [X11 0; -X22 L21 X11  X22]
-// with the split at a multiple of CB near the middle.  work: n2 x n1 doubles.
-static void tri_inverse(const double* L, double* X, int n, int off, int len, double* work, hipStream_t st) {
-  if (len <= CB) return;
-  const int n1 = ((len / 2 + CB - 1) / CB) * CB, n2 = len - n1;
-  tri_inverse(L, X, n, off, n1, work, st);
-  tri_inverse(L, X, n, off + n1, n2, work, st);
-  GemmF64 g{};  // T = L21 X11
-  g.M = n2; g.N = n1; g.K = n1;
-  g.A = L + (int64_t)(off + n1) * n + off; g.lda = n;
-  g.B = X + (int64_t)off * n + off; g.ldb = n;
-  g.C = work; g.ldc = n1;
-  g.alpha = 1.0; g.beta = 0.0; g.batch = 1;
-  dgemm(g, st);
-  GemmF64 h{};  // X21 = -X22 T, X22 lower triangular
-  h.M = n2; h.N = n1; h.K = n2;
-  h.A = X + (int64_t)(off + n1) * n + off + n1; h.lda = n; h.lowerA = true;
-  h.B = work; h.ldb = n1;
-  h.C = X + (int64_t)(off + n1) * n + off; h.ldc = n;
-  h.alpha = -1.0; h.beta = 0.0; h.batch = 1;
-  dgemm(h, st);
-}
-
-size_t cholesky_work_elems(int n) {
-  const size_t h = (size_t)(n / 2 + CB);
-  return std::max((size_t)n * (CB + 1), h * h + (size_t)n);
-}
+// work: the panel (n x CB), the original diagonal (n), and the split-K partial
+// products of the inverse's block rows (8 x CB x n)
+size_t cholesky_work_elems(int n) { return (size_t)n * (CB + 1) + (size_t)8 * CB * n; }
 
 void cholesky_inverse(double* J, int n, double* Linv, double* work, int* info, hipStream_t st) {
   fill_f64(Linv, (size_t)n * n, 0.0, st);
@@ -440,10 +414,30 @@ void cholesky_inverse(double* J, int n, double* Linv, double* work, int* info, h
     const int64_t t = (int64_t)n * n;
     hipLaunchKernelGGL(zero_upper_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, J, n);
   }
-  // off-diagonal blocks of L^-1 by recursive halving (the diagonal 64-blocks are
-  // already inverted): big products at the top levels instead of one thin
-  // product per block row
-  tri_inverse(J, Linv, n, 0, n, work, st);
+  // off-diagonal blocks of L^-1, block row by block row (row-wise substitution,
+  // which keeps the inverse accurate for an ill-conditioned metric; a recursive
+  // X21 = -X22 L21 X11 lost two to three digits on kappa = 8.6e9):
+  // X_i,0:i = -inv(L_ii) (L_i,0:i X_0:i,0:i).  The first product is thin (64
+  // rows) but long: its k-range is split over up to 8 partial products.
+  double* part = work + (size_t)n * (CB + 1);
+  const int64_t part_elems = (int64_t)8 * CB * n;
+  for (int i0 = CB; i0 < n; i0 += CB) {
+    const int ib = std::min(CB, n - i0);
+    GemmF64 g{};
+    g.M = ib; g.N = i0; g.K = i0;
+    g.A = J + (int64_t)i0 * n; g.lda = n;
+    g.B = Linv; g.ldb = n;
+    g.C = work; g.ldc = i0;
+    g.alpha = 1.0; g.beta = 0.0; g.batch = 1;
+    dgemm_sk(g, part, part_elems, st);
+    GemmF64 h{};
+    h.M = ib; h.N = i0; h.K = ib;
+    h.A = Linv + (int64_t)i0 * n + i0; h.lda = n;
+    h.B = work; h.ldb = i0;
+    h.C = Linv + (int64_t)i0 * n; h.ldc = n;
+    h.alpha = -1.0; h.beta = 0.0; h.batch = 1;
+    dgemm(h, st);
+  }
 }
 
 }  // namespace dfx
