@@ -43,14 +43,19 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILES = {"K half-transform X_Q = B_Q C, FP64": "kx64_water64_pmc.txt",
+                    "trsm_split (B = L^-1 raw)": "trsm_water64_pmc.txt"}
+
+
 def measured_traffic(kernel_label):
-    """HBM bytes per launch from the committed counter summary of the FP64 half
-    transform, or None if the kernel's source has changed since the counters
-    were taken (or the summary is for another kernel)."""
+    """HBM bytes per launch from the committed counter summary of the kernel
+    (the FP64 half transform or the B transform), or None if there is none or
+    the kernel's source has changed since the counters were taken."""
     import hashlib
-    if not kernel_label.startswith("K half-transform X_Q = B_Q C, FP64"):
+    name = next((f for k, f in TRAFFIC_PROFILES.items() if kernel_label.startswith(k)), None)
+    if name is None:
         return None
-    path = os.path.join(ROOT, "profiles", "kx64_water64_pmc.txt")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
