@@ -294,6 +294,38 @@ def eval_alkane(dfx):
                       "oracle_E": E_or, "runs": runs}))
 
 
+def eval_mp2(dfx, workloads=("alkane", "water4")):
+    """DF-MP2 (FP64) after a converged plain FP64 SCF: energy, time and the
+    FP64 MFMA rate of the whole MP2 step (both transformations and the pair
+    products, 2 nbf^2 o Q + 2 v nbf o Q + v^2 Q o (o + 1) FLOP, o = correlated
+    occupied, v = virtual, Q = auxiliary functions)."""
+    import torch
+    rows = []
+    for wl in workloads:
+        elems, xyz, sh, ax = W.workload(wl, seed=0) if wl == "alkane" else W.workload(wl)
+        Z = W.charges(elems)
+        E, C, eps, info = dfx.scf(xyz, Z, sh, ax, conv_dE=1e-9, conv_err=1e-7)
+        nocc, nbf, naux = info["nocc"], info["nbf"], info["naux"]
+        nmo = nbf - info["ndropped"]
+        nfrozen = sum(1 for z in Z if z > 2)  # 1s cores of C and O
+        Ct = torch.tensor(np.ascontiguousarray(C[:, :nmo]), device="cuda")
+        B = dfx.eri3(sh, ax)
+        dfx.mp2(B, Ct, eps, nocc, nfrozen)                                    # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        E2 = dfx.mp2(B, Ct, eps, nocc, nfrozen)
+        dt = time.perf_counter() - t0
+        B.free()
+        o, v = nocc - nfrozen, nmo - nocc
+        flop = 2.0 * nbf * nbf * o * naux + 2.0 * v * nbf * o * naux + float(v) * v * naux * o * (o + 1)
+        row = {"workload": wl, "nbf": nbf, "naux": naux, "nocc": nocc, "nfrozen": nfrozen, "nvir": v,
+               "E_scf": E, "E2": E2, "mp2_s": round(dt, 4), "TFLOP/s": round(flop / dt / 1e12, 2),
+               "frac_fp64_peak": round(flop / dt / PEAK_FP64, 4)}
+        log(json.dumps(row))
+        rows.append(row)
+    print(json.dumps({"metric": "DF-MP2 correlation energy after DF-RHF, FP64 MFMA", "runs": rows}))
+
+
 def eval_trajectory(dfx, nframes):
     """(H2O)64 over a seeded trajectory: per frame, mixed + learned (timed) and
     plain FP64 from the core guess; as context, mixed from the previous frame's
@@ -343,7 +375,7 @@ def main():
                     help="step k runs frame k of a seeded trajectory (per-atom sigma 0.02 bohr)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 reference run")
     ap.add_argument("--no-context", action="store_true", help="skip the core-guess context run")
-    ap.add_argument("--eval", default=None, choices=["ring-guess", "alkane", "trajectory"],
+    ap.add_argument("--eval", default=None, choices=["ring-guess", "alkane", "trajectory", "mp2"],
                     help="evaluation runs beside the benchmark line (each prints its own JSON line)")
     ap.add_argument("--ntrain", type=int, default=1600)
     ap.add_argument("--ntest", type=int, default=400)
@@ -371,6 +403,9 @@ def main():
         return
     if a.eval == "alkane":
         eval_alkane(dfx)
+        return
+    if a.eval == "mp2":
+        eval_mp2(dfx)
         return
     if a.eval == "trajectory":
         eval_trajectory(dfx, a.frames)

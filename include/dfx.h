@@ -192,6 +192,26 @@ int dfx_jk(const dfx_B* b, const double* dev_in, int kind, int nocc, int precisi
            double* dev_K, void* stream);
 
 /*
+ * dfx_mp2 -- DF-MP2 correlation energy of a closed-shell RHF reference (section
+ * "Standard algorithms": MP2 as a post-HF method, on the density-fitting
+ * operations of Eqs. (1) and (2)):
+ *   (ia|Q) = sum C_mu,i B_Q,mu nu C_nu,a,  (ia|jb) = sum_Q (ia|Q)(jb|Q),
+ *   E2 = sum_{ij,ab} (ia|jb) [2 (ia|jb) - (ib|ja)] / (e_i + e_j - e_a - e_b),
+ * i, j over occupied orbitals nfrozen..nocc-1, a, b over nocc..nmo-1.  FP64.
+ *   dev_C   device [nbf][nmo] row-major, column p = canonical orbital p (as dfx_scf
+ *           returns C, its first nmo = nbf - ndropped columns)
+ *   eps     host [nmo] orbital energies, ascending
+ *   E2      host scalar out
+ * Allocates device memory for (ia|Q) (nocc' x nvir x naux doubles) and one
+ * block of (ia|jb) (nvir x nocc' x nvir doubles), nocc' = nocc - nfrozen <= 512.
+ * Synchronises the stream.  Errors: DFX_EINVAL, DFX_ENOMEM, DFX_EHIP,
+ * DFX_EUNSUPPORTED (more than 512 correlated occupied orbitals).
+ */
+int dfx_mp2(const dfx_B* b, const double* dev_C, int nmo, const double* eps, int nocc, int nfrozen, double* E2,
+            void* stream);
+
+/*
+ * dfx_int1e -- overlap S, kinetic T and nuclear attraction/*
  * dfx_int1e -- overlap S, kinetic T and nuclear attraction
  * V = -sum_A Z_A <mu| 1/|r - R_A| |nu> (device outputs, nbf x nbf).
  */

@@ -112,6 +112,7 @@ _SIGS = {
     "dfx_B_metric": [_vp, _i, _vp, _vp],
     "dfx_B_free": [_vp],
     "dfx_jk": [_vp, _vp, _i, _i, _i, _vp, _vp, _vp],
+    "dfx_mp2": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp],
     "dfx_int1e": [_vp, _i, _vp, _vp, _vp, _vp, _vp],
     "dfx_scf": [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp],
     "dfx_scf_default_opts": [_vp],
@@ -278,6 +279,20 @@ def jk(B, x, kind=COCC, nocc=None, precision=FP64, want_j=True, want_k=True, str
     _check(_lib.dfx_jk(B.h, _ptr(x), kind, nocc, precision, _ptr(J) if want_j else None,
                        _ptr(K) if want_k else None, _stream(stream)))
     return J, K
+
+
+def mp2(B, C, eps, nocc, nfrozen=0, stream=None):
+    """dfx_mp2: DF-MP2 correlation energy from B and canonical orbitals C (an
+    (nbf, nmo) float64 cuda tensor or array, columns = orbitals) with energies eps."""
+    import torch
+    C = torch.as_tensor(C, dtype=torch.float64, device="cuda").contiguous()
+    e = np.ascontiguousarray(eps, dtype=np.float64)
+    nmo = C.shape[1]
+    if e.shape[0] < nmo:
+        raise ValueError("mp2: eps shorter than the number of orbitals")
+    E2 = ctypes.c_double()
+    _check(_lib.dfx_mp2(B.h, _ptr(C), nmo, e.ctypes.data, nocc, nfrozen, ctypes.byref(E2), _stream(stream)))
+    return E2.value
 
 
 def int1e(shells, xyz, Z, stream=None):

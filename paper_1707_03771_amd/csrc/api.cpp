@@ -640,6 +640,18 @@ int dfx_jk(const dfx_B* bc, const double* dev_in, int kind, int nocc, int precis
   });
 }
 
+int dfx_mp2(const dfx_B* bc, const double* dev_C, int nmo, const double* eps, int nocc, int nfrozen, double* E2,
+            void* stream) {
+  return guard([&] {
+    if (!bc || !dev_C || !eps || !E2) throw Error(DFX_EINVAL, "dfx_mp2: NULL argument");
+    dfx_B* b = const_cast<dfx_B*>(bc);
+    if (nmo <= 0 || nmo > b->nbf || nocc <= 0 || nocc >= nmo || nfrozen < 0 || nfrozen >= nocc)
+      throw Error(DFX_EINVAL, "dfx_mp2: bad orbital counts");
+    JKArgs a{b->hi.as<float>(), b->lo.as<float>(), b->naux, b->nbf, b->ncols_t, DFX_FP64};
+    *E2 = mp2_energy(a, dev_C, nmo, eps, nocc, nfrozen, (hipStream_t)stream);
+  });
+}
+
 int dfx_int1e(const dfx_shell* shells, int nsh, const dfx_geom* geom, double* dev_S, double* dev_T,
               double* dev_V, void* stream) {
   return guard([&] {

@@ -297,6 +297,34 @@ static F64Plan f64_plan(const JKArgs& a, int nocc) {
 
 static size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
 
+size_t half_transform_f64_work(const JKArgs& a, int nocc) {
+  const F64Plan p = f64_plan(a, nocc);
+  return p.c_bytes;
+}
+
+void half_transform_f64(const JKArgs& a, const double* C, int nocc, int q0, int nq, double* X, int64_t ldx,
+                        void* work, hipStream_t st) {
+  const F64Plan p = f64_plan(a, nocc);
+  const int ncb = (nocc + 63) / 64;
+  if (ncb > 8) throw Error(-6, "half transform: more than 512 columns");
+  if (q0 < 0 || nq <= 0 || q0 + nq > a.naux || ldx < (int64_t)nq * nocc) throw Error(-1, "half transform: bad range");
+  double* Cp = reinterpret_cast<double*>(work);
+  const int64_t ncp = (int64_t)p.nbfp * p.np;
+  hipLaunchKernelGGL(cpad_kernel, dim3((unsigned)((ncp + 255) / 256)), dim3(256), 0, st, C, a.nbf, nocc, p.nbfp,
+                     p.np, Cp);
+  const int mr = 64 * kx_rb(ncb);
+  const dim3 g1((a.nbf + mr - 1) / mr, nq);
+  switch (ncb) {
+#define KX64(N)                                                                                                   \
+  case N:                                                                                                         \
+    hipLaunchKernelGGL((kx64_kernel<N, kx_rb(N)>), g1, dim3(KX_T), 0, st, a.hi, a.lo, a.ncols, a.nbf, q0, Cp, nocc, \
+                       X, ldx);                                                                                   \
+    break;
+    KX64(1) KX64(2) KX64(3) KX64(4) KX64(5) KX64(6) KX64(7) KX64(8)
+#undef KX64
+  }
+}
+
 size_t k_work_bytes_f64(const JKArgs& a, int nocc) {
   const F64Plan p = f64_plan(a, nocc);
   return a256(p.x_bytes) + a256(p.p_bytes) + p.c_bytes + 256;

@@ -94,6 +94,14 @@ void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, 
              KTimer* timer = nullptr);
 // FP64 K (jk_f64.hip), dispatched by k_build for PREC_FP64
 size_t k_work_bytes_f64(const JKArgs& a, int nocc);
+// X[mu][(Q - q0) nocc + i] = sum_nu B_Q[mu][nu] C[nu][i], Q in [q0, q0 + nq): the FP64
+// half transform of the exchange build on its own (work: half_transform_f64_work bytes)
+size_t half_transform_f64_work(const JKArgs& a, int nocc);
+void half_transform_f64(const JKArgs& a, const double* C, int nocc, int q0, int nq, double* X, int64_t ldx,
+                        void* work, hipStream_t st);
+// DF-MP2 correlation energy from B and canonical orbitals (mp2.hip)
+double mp2_energy(const JKArgs& a, const double* C, int nmo, const double* eps, int nocc, int nfrozen,
+                  hipStream_t st);
 void k_build_f64(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st,
                  KTimer* timer);
 // reduced-precision K (jk_mixed.hip), dispatched by k_build for PREC_FP32 / PREC_BF16
