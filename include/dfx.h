@@ -328,6 +328,29 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
             const dfx_scf_opts* opts, const double* init, double* E, double* C, double* eps,
             dfx_scf_info* info);
 
+/*
+ * dfx_uhf -- DF-UHF (section "Standard algorithms" lists unrestricted Hartree-Fock
+ * among the SCF methods): the Pople-Nesbet equations on the same fitted tensor as
+ * dfx_scf.  With n_alpha = (nelec + multiplicity - 1) / 2 and n_beta = nelec - n_alpha,
+ *   D_s = C_s,occ C_s,occ^T,  F_s = h + J[D_alpha + D_beta] - K[D_s]  (s = alpha, beta),
+ *   E = 1/2 sum_s tr D_s (h + F_s) + E_nn,
+ * one Pulay DIIS over both spins (error overlaps summed, both Fock matrices
+ * extrapolated with the same coefficients), aufbau per spin with dsyevd, start
+ * from the core Hamiltonian for both spins.  FP64 J and K throughout.
+ *   opts          as for dfx_scf; guess must be DFX_GUESS_CORE and schedule
+ *                 DFX_SCHED_FP64 (DFX_EINVAL otherwise); the purification, learned
+ *                 guess and precision switches do not apply
+ *   multiplicity  2S + 1 >= 1; DFX_EINVAL if its parity does not match the electron
+ *                 count, or if it exceeds nelec + 1
+ *   E             host scalar out; info (may be NULL): niter, converged, nbf, naux,
+ *                 nocc (= n_alpha), E_nuc, err_max (larger of the two spins),
+ *                 E_hist / err_hist, timings
+ * Synchronous.  DFX_ENOCONV: not converged within max_iter (E written).
+ * A closed shell (multiplicity 1) gives the dfx_scf energy for the same options.
+ */
+int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
+            const dfx_scf_opts* opts, int multiplicity, double* E, dfx_scf_info* info);
+
 /* ---- learned starting guess ---------------------------------------------------
  * Replaces the core-Hamiltonian start of the SCF ("Standard algorithms") with a
  * density predicted block by block: for every atom pair (a, b) closer than the

@@ -115,6 +115,7 @@ _SIGS = {
     "dfx_mp2": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp],
     "dfx_int1e": [_vp, _i, _vp, _vp, _vp, _vp, _vp],
     "dfx_scf": [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp],
+    "dfx_uhf": [_vp, _vp, _i, _vp, _i, _vp, _i, _vp, _vp],
     "dfx_scf_default_opts": [_vp],
     "dfx_metric": [_vp, _i, _vp, _vp],
     "dfx_cholesky": [_vp, _i, _vp, _vp],
@@ -366,6 +367,28 @@ def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, model=None, **opt
     info["prec_hist"] = list(inf.prec_hist)[: inf.niter]
     info["status"] = code
     return E.value, C, eps, info
+
+
+def uhf(xyz, Z, shells, aux, charge=0, multiplicity=1, **opts):
+    """dfx_uhf: DF-UHF (FP64, core guess).  Returns (E, info dict)."""
+    o = scf_default_opts()
+    for k, v in opts.items():
+        if not hasattr(o, k) or k == "model":
+            raise TypeError(f"unknown SCF option {k!r}")
+        setattr(o, k, v)
+    s, a = _ShellArray(shells), _ShellArray(aux)
+    g = _GeomC(xyz, Z, charge)
+    E = ctypes.c_double()
+    inf = ScfInfo()
+    code = _lib.dfx_uhf(ctypes.byref(g.g), s.arr, s.n, a.arr, a.n, ctypes.byref(o), int(multiplicity),
+                        ctypes.byref(E), ctypes.byref(inf))
+    if code not in (OK, ENOCONV):
+        _check(code)
+    info = {k: getattr(inf, k) for k, _ in ScfInfo._fields_ if not k.endswith("_hist")}
+    info["E_hist"] = list(inf.E_hist)[: inf.niter]
+    info["err_hist"] = list(inf.err_hist)[: inf.niter]
+    info["status"] = code
+    return E.value, info
 
 
 # ---- learned starting guess ------------------------------------------------------

@@ -33,6 +33,12 @@ __global__ void fock_kernel(const double* h, const double* J, const double* K, d
   if (i < n2) F[i] = h[i] + 2.0 * J[i] - K[i];
 }
 
+// F = h + J - K (one spin of the unrestricted Fock matrices)
+__global__ void uhf_fock_kernel(const double* h, const double* J, const double* K, double* F, int64_t n2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n2) F[i] = h[i] + J[i] - K[i];
+}
+
 __global__ void add_kernel(const double* a, const double* b, double* c, int64_t n2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n2) c[i] = a[i] + b[i];
@@ -999,6 +1005,238 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     if (!converged) {
       status = DFX_ENOCONV;
       set_last_error("dfx_scf: not converged in " + std::to_string(o.max_iter) + " iterations");
+    }
+  });
+  return rc != DFX_OK ? rc : status;
+}
+
+int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
+            const dfx_scf_opts* opts_in, int multiplicity, double* E_out, dfx_scf_info* info) {
+  int status = DFX_OK;
+  const int rc = guard([&] {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    if (!geom || !E_out) throw Error(DFX_EINVAL, "dfx_uhf: NULL argument");
+    if (geom->natom <= 0 || !geom->xyz || !geom->Z) throw Error(DFX_EINVAL, "dfx_uhf: bad geometry");
+    dfx_scf_opts o;
+    dfx_scf_default_opts(&o);
+    if (opts_in) o = *opts_in;
+    if (o.diis_size < 1 || o.diis_size > 16 || o.max_iter < 1) throw Error(DFX_EINVAL, "dfx_uhf: bad options");
+    if (o.guess != DFX_GUESS_CORE || o.schedule != DFX_SCHED_FP64)
+      throw Error(DFX_EINVAL, "dfx_uhf: core guess and FP64 schedule only");
+    int nelec = -geom->charge;
+    for (int a = 0; a < geom->natom; ++a) nelec += geom->Z[a];
+    if (multiplicity < 1 || nelec <= 0 || (nelec + multiplicity - 1) % 2 || multiplicity - 1 > nelec)
+      throw Error(DFX_EINVAL, "dfx_uhf: electron count and multiplicity do not match");
+    const int na = (nelec + multiplicity - 1) / 2, nb = nelec - na;
+    HostShells hb = make_shells(shells, nsh, 3, "orbital basis");
+    HostShells ha = make_shells(aux, nauxsh, 4, "auxiliary basis");
+    const int n = hb.nbf;
+    if (na > n) throw Error(DFX_EINVAL, "dfx_uhf: more occupied orbitals than basis functions");
+
+    Scf S;
+    DFX_HIP(hipStreamCreate(&S.st));
+    struct Cleanup {
+      Scf& s;
+      ~Cleanup() {
+        if (s.rb) rocblas_destroy_handle(s.rb);
+        if (s.st) (void)hipStreamDestroy(s.st);
+      }
+    } cleanup{S};
+    if (rocblas_create_handle(&S.rb) != rocblas_status_success) throw Error(DFX_EHIP, "rocblas_create_handle failed");
+    rocblas_set_stream(S.rb, S.st);
+    hipStream_t st = S.st;
+    S.n = n;
+    S.nocc = na;
+    S.part.alloc(sizeof(double) * 512);
+    S.gw.alloc(sizeof(double) * 4 * (size_t)n * n);
+    S.eig_info.alloc(sizeof(int));
+    const int64_t n2 = (int64_t)n * n;
+
+    // setup: fitted integrals, one-electron matrices, E_nn, canonical orthogonaliser
+    std::unique_ptr<dfx_B> B = build_B(std::move(hb), std::move(ha), o.tau, 0, st);
+    DevMem Sm(8 * n2), Tm(8 * n2), Vm(8 * n2), h(8 * n2);
+    int1e_build(B->bas, geom, Sm.as<double>(), Tm.as<double>(), Vm.as<double>(), st);
+    hipLaunchKernelGGL(add_kernel, dim3(nblk(n2)), dim3(256), 0, st, Tm.as<double>(), Vm.as<double>(),
+                       h.as<double>(), n2);
+    Tm.release();
+    Vm.release();
+    double Enuc = 0.0;
+    for (int a = 0; a < geom->natom; ++a)
+      for (int b = 0; b < a; ++b) {
+        const double* A = geom->xyz + 3 * a;
+        const double* Bx = geom->xyz + 3 * b;
+        const double r = std::sqrt((A[0] - Bx[0]) * (A[0] - Bx[0]) + (A[1] - Bx[1]) * (A[1] - Bx[1]) +
+                                   (A[2] - Bx[2]) * (A[2] - Bx[2]));
+        Enuc += (double)geom->Z[a] * geom->Z[b] / r;
+      }
+    DevMem W(8 * n2), sv(8 * (size_t)n);
+    DFX_HIP(hipMemcpyAsync(W.p, Sm.p, 8 * n2, hipMemcpyDeviceToDevice, st));
+    S.syevd(W.as<double>(), n, sv.as<double>());
+    std::vector<double> s_h(n);
+    DFX_HIP(hipMemcpyAsync(s_h.data(), sv.p, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+    DFX_HIP(hipStreamSynchronize(st));
+    int ndrop = 0;
+    while (ndrop < n && s_h[ndrop] < o.ortho_thresh) ++ndrop;
+    const int m = n - ndrop;
+    if (m < na) throw Error(DFX_EINVAL, "dfx_uhf: basis too linearly dependent");
+    S.m = m;
+    DevMem X(8 * (size_t)n * m);
+    hipLaunchKernelGGL(build_x_kernel, dim3(nblk((int64_t)n * m)), dim3(256), 0, st, W.as<double>(),
+                       sv.as<double>(), n, ndrop, m, X.as<double>());
+    W.release();
+
+    // per spin: occupied orbitals, density, K, Fock matrix, DIIS error
+    const int nocc_s[2] = {na, nb};
+    DevMem J(8 * n2), Dt(8 * n2), t1(8 * n2), t2(8 * n2), Fp(8 * (size_t)m * m), eps(8 * (size_t)m),
+        Cm(8 * (size_t)n * m);
+    DevMem Cocc[2], D[2], K[2], F[2];
+    for (int s2 = 0; s2 < 2; ++s2) {
+      Cocc[s2].alloc(8 * (size_t)n * std::max(1, nocc_s[s2]));
+      D[s2].alloc(8 * n2);
+      K[s2].alloc(8 * n2);
+      F[s2].alloc(8 * n2);
+    }
+    const int dsz = o.diis_size;
+    std::vector<DevMem> Fh(2 * dsz), Eh(2 * dsz);
+    for (int k = 0; k < 2 * dsz; ++k) {
+      Fh[k].alloc(8 * n2);
+      Eh[k].alloc(8 * (size_t)m * m);
+    }
+    // occupied orbitals of spin s2 from a Fock-like matrix (dsyevd of X^T F X)
+    auto diag = [&](int s2, const double* Fx) {
+      S.gemm(m, n, n, X.as<double>(), m, true, Fx, n, false, t1.as<double>(), n);
+      S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Fp.as<double>(), m);
+      S.syevd(Fp.as<double>(), m, eps.as<double>());
+      S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm.as<double>(), m);
+      if (nocc_s[s2] > 0) {
+        hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc_s[s2])), dim3(256), 0, st, Cm.as<double>(),
+                           m, n, nocc_s[s2], Cocc[s2].as<double>(), nocc_s[s2]);
+        S.gemm(n, n, nocc_s[s2], Cocc[s2].as<double>(), nocc_s[s2], false, Cocc[s2].as<double>(), nocc_s[s2], true,
+               D[s2].as<double>(), n);
+      } else {
+        DFX_HIP(hipMemsetAsync(D[s2].p, 0, 8 * n2, st));
+      }
+    };
+    diag(0, h.as<double>());
+    diag(1, h.as<double>());
+    DFX_HIP(hipStreamSynchronize(st));
+    const auto t1c = clk::now();
+
+    JKArgs ja{B->hi.as<float>(), B->lo.as<float>(), B->naux, n, B->ncols_t, PREC_FP64};
+    dfx_scf_info inf{};
+    std::vector<double> Bdiis((size_t)dsz * dsz, 0.0);
+    int hcount = 0, hpos = 0, it = 0;
+    double E = 0.0, Eold = 0.0, emax = 0.0;
+    bool converged = false;
+    for (it = 1; it <= o.max_iter; ++it) {
+      // the K plan chunks Q by the occupied count, so size the work for both spins
+      void* w = B->ensure_work(std::max({sizeof(double) * (2 * (size_t)B->ncols_t + B->naux + 8),
+                                         k_work_bytes(ja, std::max(1, na)), k_work_bytes(ja, std::max(1, nb))}));
+      hipLaunchKernelGGL(add_kernel, dim3(nblk(n2)), dim3(256), 0, st, D[0].as<double>(), D[1].as<double>(),
+                         Dt.as<double>(), n2);
+      j_build(ja, Dt.as<double>(), J.as<double>(), reinterpret_cast<double*>(w), st);
+      double sum = 0.0;
+      for (int s2 = 0; s2 < 2; ++s2) {
+        if (nocc_s[s2] > 0)
+          k_build(ja, Cocc[s2].as<double>(), nocc_s[s2], K[s2].as<double>(), w, st, nullptr);
+        else
+          DFX_HIP(hipMemsetAsync(K[s2].p, 0, 8 * n2, st));
+        hipLaunchKernelGGL(uhf_fock_kernel, dim3(nblk(n2)), dim3(256), 0, st, h.as<double>(), J.as<double>(),
+                           K[s2].as<double>(), F[s2].as<double>(), n2);
+        sum += S.reduce_sum(D[s2].as<double>(), h.as<double>(), F[s2].as<double>(), n2);
+      }
+      E = 0.5 * sum + Enuc;
+      // e_s = X^T (F_s D_s S - S D_s F_s) X into the ring slot of each spin
+      emax = 0.0;
+      for (int s2 = 0; s2 < 2; ++s2) {
+        S.gemm(n, n, n, F[s2].as<double>(), n, false, D[s2].as<double>(), n, false, t1.as<double>(), n);
+        S.gemm(n, n, n, t1.as<double>(), n, false, Sm.as<double>(), n, false, t2.as<double>(), n);
+        hipLaunchKernelGGL(antisym_kernel, dim3(nblk(n2)), dim3(256), 0, st, t2.as<double>(), t1.as<double>(), n);
+        S.gemm(m, n, n, X.as<double>(), m, true, t1.as<double>(), n, false, t2.as<double>(), n);
+        S.gemm(m, m, n, t2.as<double>(), n, false, X.as<double>(), m, false, Eh[2 * hpos + s2].as<double>(), m);
+        emax = std::max(emax, S.reduce_max(Eh[2 * hpos + s2].as<double>(), (int64_t)m * m));
+      }
+      if (it <= DFX_MAXHIST) {
+        inf.E_hist[it - 1] = E;
+        inf.err_hist[it - 1] = emax;
+        inf.prec_hist[it - 1] = (int8_t)DFX_FP64;
+      }
+      if (o.verbose)
+        std::fprintf(stderr, "dfx_uhf it %3d  E = %.12f  dE = %.3e  err = %.3e\n", it, E, E - Eold, emax);
+      if (it >= 2 && std::fabs(E - Eold) < o.conv_dE && emax < o.conv_err) {
+        converged = true;
+        break;
+      }
+      Eold = E;
+      // DIIS over both spins: one set of coefficients from the summed error overlaps
+      for (int s2 = 0; s2 < 2; ++s2)
+        DFX_HIP(hipMemcpyAsync(Fh[2 * hpos + s2].p, F[s2].p, 8 * n2, hipMemcpyDeviceToDevice, st));
+      hcount = std::min(hcount + 1, dsz);
+      for (int k = 0; k < hcount; ++k) {
+        double b = 0.0;
+        for (int s2 = 0; s2 < 2; ++s2)
+          b += S.reduce_sum(Eh[2 * k + s2].as<double>(), Eh[2 * hpos + s2].as<double>(), nullptr, (int64_t)m * m);
+        Bdiis[(size_t)hpos * dsz + k] = Bdiis[(size_t)k * dsz + hpos] = b;
+      }
+      const double* Fuse[2] = {F[0].as<double>(), F[1].as<double>()};
+      DevMem* Fext[2] = {&t1, &t2};
+      if (hcount > 1) {
+        std::vector<int> slots;
+        for (int k = 0; k < hcount; ++k) slots.push_back((hpos + 1 + k + (dsz - hcount)) % dsz);
+        while (slots.size() > 1) {
+          const int mm = (int)slots.size();
+          std::vector<double> Bm((size_t)mm * mm), c;
+          for (int i = 0; i < mm; ++i)
+            for (int j = 0; j < mm; ++j) Bm[i * mm + j] = Bdiis[(size_t)slots[i] * dsz + slots[j]];
+          if (diis_solve(Bm, mm, c)) {
+            for (int s2 = 0; s2 < 2; ++s2) {
+              Comb cb{};
+              cb.m = mm;
+              for (int i = 0; i < mm; ++i) {
+                cb.F[i] = Fh[2 * slots[i] + s2].as<double>();
+                cb.c[i] = c[i];
+              }
+              hipLaunchKernelGGL(lincomb_kernel, dim3(nblk(n2)), dim3(256), 0, st, cb, Fext[s2]->as<double>(), n2);
+              Fuse[s2] = Fext[s2]->as<double>();
+            }
+            break;
+          }
+          slots.erase(slots.begin());
+        }
+      }
+      hpos = (hpos + 1) % dsz;
+      // diag overwrites t1 (X^T F): extrapolated alpha Fock matrix goes to F[0] first
+      if (Fuse[0] != F[0].as<double>())
+        DFX_HIP(hipMemcpyAsync(F[0].p, Fuse[0], 8 * n2, hipMemcpyDeviceToDevice, st));
+      if (Fuse[1] != F[1].as<double>())
+        DFX_HIP(hipMemcpyAsync(F[1].p, Fuse[1], 8 * n2, hipMemcpyDeviceToDevice, st));
+      diag(0, F[0].as<double>());
+      diag(1, F[1].as<double>());
+    }
+    DFX_HIP(hipStreamSynchronize(st));
+    const auto t2c = clk::now();
+    *E_out = E;
+    inf.niter = std::min(it, o.max_iter);
+    inf.converged = converged ? 1 : 0;
+    inf.ndropped = ndrop;
+    inf.nbf = n;
+    inf.naux = B->naux;
+    inf.nocc = na;
+    inf.E_nuc = Enuc;
+    inf.err_max = emax;
+    inf.t_setup = std::chrono::duration<double>(t1c - t0).count();
+    inf.t_scf = std::chrono::duration<double>(t2c - t1c).count();
+    inf.t_total = std::chrono::duration<double>(clk::now() - t0).count();
+    inf.t_eri = B->info.eri_seconds;
+    inf.t_metric = B->info.metric_seconds;
+    inf.t_trsm = B->info.trsm_seconds;
+    inf.nintegrals = B->info.nintegrals;
+    inf.ncols = B->info.ncols;
+    if (info) *info = inf;
+    if (!converged) {
+      status = DFX_ENOCONV;
+      set_last_error("dfx_uhf: not converged in " + std::to_string(o.max_iter) + " iterations");
     }
   });
   return rc != DFX_OK ? rc : status;
