@@ -351,6 +351,24 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
 int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
             const dfx_scf_opts* opts, int multiplicity, double* E, dfx_scf_info* info);
 
+/*
+ * dfx_rohf -- DF-ROHF (section "Standard algorithms" lists restricted open-shell
+ * Hartree-Fock among the SCF methods): one orbital set C, the n_beta lowest doubly
+ * occupied (core), the next n_alpha - n_beta singly (open), n_alpha and n_beta as
+ * for dfx_uhf.  D_alpha = C_(core+open) C_(core+open)^T, D_beta = C_core C_core^T;
+ * F_s and E as for dfx_uhf.  The orbitals are the eigenvectors of Roothaan's
+ * effective Fock matrix: in the basis of the current orbitals its core-open block
+ * is that of F_beta, its open-virtual block that of F_alpha, every other block that
+ * of (F_alpha + F_beta) / 2.  It is formed and diagonalised in the orthonormal
+ * basis of X, and Pulay DIIS extrapolates it with the error F_eff D - D F_eff of
+ * D = D_alpha + D_beta in that basis (zero exactly when the core-open, core-virtual
+ * and open-virtual blocks are).  Arguments, options, errors and info as for
+ * dfx_uhf (err_max: the one error matrix).  A closed shell gives the dfx_scf
+ * energy; with n_beta = 0 it is the dfx_uhf determinant.
+ */
+int dfx_rohf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
+             const dfx_scf_opts* opts, int multiplicity, double* E, dfx_scf_info* info);
+
 /* ---- learned starting guess ---------------------------------------------------
  * Replaces the core-Hamiltonian start of the SCF ("Standard algorithms") with a
  * density predicted block by block: for every atom pair (a, b) closer than the

@@ -116,6 +116,7 @@ _SIGS = {
     "dfx_int1e": [_vp, _i, _vp, _vp, _vp, _vp, _vp],
     "dfx_scf": [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp],
     "dfx_uhf": [_vp, _vp, _i, _vp, _i, _vp, _i, _vp, _vp],
+    "dfx_rohf": [_vp, _vp, _i, _vp, _i, _vp, _i, _vp, _vp],
     "dfx_scf_default_opts": [_vp],
     "dfx_metric": [_vp, _i, _vp, _vp],
     "dfx_cholesky": [_vp, _i, _vp, _vp],
@@ -369,8 +370,7 @@ def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, model=None, **opt
     return E.value, C, eps, info
 
 
-def uhf(xyz, Z, shells, aux, charge=0, multiplicity=1, **opts):
-    """dfx_uhf: DF-UHF (FP64, core guess).  Returns (E, info dict)."""
+def _open_shell(fn, xyz, Z, shells, aux, charge, multiplicity, opts):
     o = scf_default_opts()
     for k, v in opts.items():
         if not hasattr(o, k) or k == "model":
@@ -380,8 +380,8 @@ def uhf(xyz, Z, shells, aux, charge=0, multiplicity=1, **opts):
     g = _GeomC(xyz, Z, charge)
     E = ctypes.c_double()
     inf = ScfInfo()
-    code = _lib.dfx_uhf(ctypes.byref(g.g), s.arr, s.n, a.arr, a.n, ctypes.byref(o), int(multiplicity),
-                        ctypes.byref(E), ctypes.byref(inf))
+    code = fn(ctypes.byref(g.g), s.arr, s.n, a.arr, a.n, ctypes.byref(o), int(multiplicity), ctypes.byref(E),
+              ctypes.byref(inf))
     if code not in (OK, ENOCONV):
         _check(code)
     info = {k: getattr(inf, k) for k, _ in ScfInfo._fields_ if not k.endswith("_hist")}
@@ -389,6 +389,16 @@ def uhf(xyz, Z, shells, aux, charge=0, multiplicity=1, **opts):
     info["err_hist"] = list(inf.err_hist)[: inf.niter]
     info["status"] = code
     return E.value, info
+
+
+def uhf(xyz, Z, shells, aux, charge=0, multiplicity=1, **opts):
+    """dfx_uhf: DF-UHF (FP64, core guess).  Returns (E, info dict)."""
+    return _open_shell(_lib.dfx_uhf, xyz, Z, shells, aux, charge, multiplicity, opts)
+
+
+def rohf(xyz, Z, shells, aux, charge=0, multiplicity=1, **opts):
+    """dfx_rohf: DF-ROHF (FP64, core guess).  Returns (E, info dict)."""
+    return _open_shell(_lib.dfx_rohf, xyz, Z, shells, aux, charge, multiplicity, opts)
 
 
 # ---- learned starting guess ------------------------------------------------------

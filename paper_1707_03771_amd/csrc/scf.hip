@@ -39,6 +39,18 @@ __global__ void uhf_fock_kernel(const double* h, const double* J, const double* 
   if (i < n2) F[i] = h[i] + J[i] - K[i];
 }
 
+// Roothaan's effective Fock matrix in the orbital basis from F_alpha and F_beta
+// there: core (k < nb), open (nb <= k < na), virtual; core-open blocks F_beta,
+// open-virtual F_alpha, all others (F_alpha + F_beta) / 2
+__global__ void rohf_blocks_kernel(const double* Fa, const double* Fb, int m, int nb, int na, double* R) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)m * m) return;
+  const int r = (int)(i / m), c = (int)(i % m);
+  const int sr = r < nb ? 0 : (r < na ? 1 : 2), sc = c < nb ? 0 : (c < na ? 1 : 2);
+  const int lo = sr < sc ? sr : sc, hi = sr < sc ? sc : sr;
+  R[i] = (lo == 0 && hi == 1) ? Fb[i] : (lo == 1 && hi == 2) ? Fa[i] : 0.5 * (Fa[i] + Fb[i]);
+}
+
 __global__ void add_kernel(const double* a, const double* b, double* c, int64_t n2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n2) c[i] = a[i] + b[i];
@@ -1010,29 +1022,37 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
   return rc != DFX_OK ? rc : status;
 }
 
-int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
-            const dfx_scf_opts* opts_in, int multiplicity, double* E_out, dfx_scf_info* info) {
+// Open-shell SCF on the fitted J and K.  restricted = false: UHF, one orbital set
+// per spin, each diagonalising its own Fock matrix.  restricted = true: ROHF, one
+// orbital set whose n_beta lowest are doubly and the next n_alpha - n_beta singly
+// occupied, the eigenvectors of Roothaan's effective Fock matrix (the diagonal
+// blocks take (F_alpha + F_beta) / 2; core-open F_beta, open-virtual F_alpha),
+// formed and extrapolated in the orthonormal basis of X.
+static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux,
+                          int nauxsh, const dfx_scf_opts* opts_in, int multiplicity, double* E_out,
+                          dfx_scf_info* info, bool restricted) {
+  const std::string fn = restricted ? "dfx_rohf" : "dfx_uhf";
   int status = DFX_OK;
   const int rc = guard([&] {
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();
-    if (!geom || !E_out) throw Error(DFX_EINVAL, "dfx_uhf: NULL argument");
-    if (geom->natom <= 0 || !geom->xyz || !geom->Z) throw Error(DFX_EINVAL, "dfx_uhf: bad geometry");
+    if (!geom || !E_out) throw Error(DFX_EINVAL, fn + ": NULL argument");
+    if (geom->natom <= 0 || !geom->xyz || !geom->Z) throw Error(DFX_EINVAL, fn + ": bad geometry");
     dfx_scf_opts o;
     dfx_scf_default_opts(&o);
     if (opts_in) o = *opts_in;
-    if (o.diis_size < 1 || o.diis_size > 16 || o.max_iter < 1) throw Error(DFX_EINVAL, "dfx_uhf: bad options");
+    if (o.diis_size < 1 || o.diis_size > 16 || o.max_iter < 1) throw Error(DFX_EINVAL, fn + ": bad options");
     if (o.guess != DFX_GUESS_CORE || o.schedule != DFX_SCHED_FP64)
-      throw Error(DFX_EINVAL, "dfx_uhf: core guess and FP64 schedule only");
+      throw Error(DFX_EINVAL, fn + ": core guess and FP64 schedule only");
     int nelec = -geom->charge;
     for (int a = 0; a < geom->natom; ++a) nelec += geom->Z[a];
     if (multiplicity < 1 || nelec <= 0 || (nelec + multiplicity - 1) % 2 || multiplicity - 1 > nelec)
-      throw Error(DFX_EINVAL, "dfx_uhf: electron count and multiplicity do not match");
+      throw Error(DFX_EINVAL, fn + ": electron count and multiplicity do not match");
     const int na = (nelec + multiplicity - 1) / 2, nb = nelec - na;
     HostShells hb = make_shells(shells, nsh, 3, "orbital basis");
     HostShells ha = make_shells(aux, nauxsh, 4, "auxiliary basis");
     const int n = hb.nbf;
-    if (na > n) throw Error(DFX_EINVAL, "dfx_uhf: more occupied orbitals than basis functions");
+    if (na > n) throw Error(DFX_EINVAL, fn + ": more occupied orbitals than basis functions");
 
     Scf S;
     DFX_HIP(hipStreamCreate(&S.st));
@@ -1079,7 +1099,7 @@ int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     int ndrop = 0;
     while (ndrop < n && s_h[ndrop] < o.ortho_thresh) ++ndrop;
     const int m = n - ndrop;
-    if (m < na) throw Error(DFX_EINVAL, "dfx_uhf: basis too linearly dependent");
+    if (m < na) throw Error(DFX_EINVAL, fn + ": basis too linearly dependent");
     S.m = m;
     DevMem X(8 * (size_t)n * m);
     hipLaunchKernelGGL(build_x_kernel, dim3(nblk((int64_t)n * m)), dim3(256), 0, st, W.as<double>(),
@@ -1118,8 +1138,40 @@ int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
         DFX_HIP(hipMemsetAsync(D[s2].p, 0, 8 * n2, st));
       }
     };
-    diag(0, h.as<double>());
-    diag(1, h.as<double>());
+    // ROHF: eigenvectors of an m x m matrix of the orthonormal basis; rows of Fp
+    // (the eigenvectors) are kept as the current orbitals V, C = X V^T
+    const int64_t m2 = (int64_t)m * m;
+    DevMem Fo[2], tm, Rm, Feff, Dp;
+    if (restricted) {
+      for (auto& f : Fo) f.alloc(8 * m2);
+      tm.alloc(8 * m2);
+      Rm.alloc(8 * m2);
+      Feff.alloc(8 * m2);
+      Dp.alloc(8 * m2);
+    }
+    auto diag_orth = [&](const double* Fm) {
+      DFX_HIP(hipMemcpyAsync(Fp.p, Fm, 8 * m2, hipMemcpyDeviceToDevice, st));
+      S.syevd(Fp.as<double>(), m, eps.as<double>());
+      S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm.as<double>(), m);
+      for (int s2 = 0; s2 < 2; ++s2) {
+        if (nocc_s[s2] > 0) {
+          hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc_s[s2])), dim3(256), 0, st,
+                             Cm.as<double>(), m, n, nocc_s[s2], Cocc[s2].as<double>(), nocc_s[s2]);
+          S.gemm(n, n, nocc_s[s2], Cocc[s2].as<double>(), nocc_s[s2], false, Cocc[s2].as<double>(), nocc_s[s2],
+                 true, D[s2].as<double>(), n);
+        } else {
+          DFX_HIP(hipMemsetAsync(D[s2].p, 0, 8 * n2, st));
+        }
+      }
+    };
+    if (restricted) {
+      S.gemm(m, n, n, X.as<double>(), m, true, h.as<double>(), n, false, t1.as<double>(), n);
+      S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Feff.as<double>(), m);
+      diag_orth(Feff.as<double>());
+    } else {
+      diag(0, h.as<double>());
+      diag(1, h.as<double>());
+    }
     DFX_HIP(hipStreamSynchronize(st));
     const auto t1c = clk::now();
 
@@ -1147,9 +1199,30 @@ int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
         sum += S.reduce_sum(D[s2].as<double>(), h.as<double>(), F[s2].as<double>(), n2);
       }
       E = 0.5 * sum + Enuc;
-      // e_s = X^T (F_s D_s S - S D_s F_s) X into the ring slot of each spin
       emax = 0.0;
-      for (int s2 = 0; s2 < 2; ++s2) {
+      if (restricted) {
+        // F_s' = V X^T F_s X V^T (orbital basis), R by blocks, F_eff' = V^T R V
+        for (int s2 = 0; s2 < 2; ++s2) {
+          S.gemm(m, n, n, X.as<double>(), m, true, F[s2].as<double>(), n, false, t1.as<double>(), n);
+          S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Fo[s2].as<double>(), m);
+          S.gemm(m, m, m, Fp.as<double>(), m, false, Fo[s2].as<double>(), m, false, tm.as<double>(), m);
+          S.gemm(m, m, m, tm.as<double>(), m, false, Fp.as<double>(), m, true, Fo[s2].as<double>(), m);
+        }
+        hipLaunchKernelGGL(rohf_blocks_kernel, dim3(nblk(m2)), dim3(256), 0, st, Fo[0].as<double>(),
+                           Fo[1].as<double>(), m, nb, na, Rm.as<double>());
+        S.gemm(m, m, m, Fp.as<double>(), m, true, Rm.as<double>(), m, false, tm.as<double>(), m);
+        S.gemm(m, m, m, tm.as<double>(), m, false, Fp.as<double>(), m, false, Feff.as<double>(), m);
+        // D' = V^T diag(occupations) V = V_a^T V_a + V_b^T V_b; e = F_eff' D' - D' F_eff'
+        S.gemm(m, m, na, Fp.as<double>(), m, true, Fp.as<double>(), m, false, Dp.as<double>(), m);
+        if (nb > 0)
+          S.gemm(m, m, nb, Fp.as<double>(), m, true, Fp.as<double>(), m, false, Dp.as<double>(), m, 1.0, 1.0);
+        S.gemm(m, m, m, Feff.as<double>(), m, false, Dp.as<double>(), m, false, tm.as<double>(), m);
+        hipLaunchKernelGGL(antisym_kernel, dim3(nblk(m2)), dim3(256), 0, st, tm.as<double>(),
+                           Eh[2 * hpos].as<double>(), m);
+        emax = S.reduce_max(Eh[2 * hpos].as<double>(), m2);
+      }
+      // UHF: e_s = X^T (F_s D_s S - S D_s F_s) X into the ring slot of each spin
+      for (int s2 = 0; s2 < 2 && !restricted; ++s2) {
         S.gemm(n, n, n, F[s2].as<double>(), n, false, D[s2].as<double>(), n, false, t1.as<double>(), n);
         S.gemm(n, n, n, t1.as<double>(), n, false, Sm.as<double>(), n, false, t2.as<double>(), n);
         hipLaunchKernelGGL(antisym_kernel, dim3(nblk(n2)), dim3(256), 0, st, t2.as<double>(), t1.as<double>(), n);
@@ -1163,23 +1236,28 @@ int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
         inf.prec_hist[it - 1] = (int8_t)DFX_FP64;
       }
       if (o.verbose)
-        std::fprintf(stderr, "dfx_uhf it %3d  E = %.12f  dE = %.3e  err = %.3e\n", it, E, E - Eold, emax);
+        std::fprintf(stderr, "%s it %3d  E = %.12f  dE = %.3e  err = %.3e\n", fn.c_str(), it, E, E - Eold, emax);
       if (it >= 2 && std::fabs(E - Eold) < o.conv_dE && emax < o.conv_err) {
         converged = true;
         break;
       }
       Eold = E;
       // DIIS over both spins: one set of coefficients from the summed error overlaps
-      for (int s2 = 0; s2 < 2; ++s2)
-        DFX_HIP(hipMemcpyAsync(Fh[2 * hpos + s2].p, F[s2].p, 8 * n2, hipMemcpyDeviceToDevice, st));
+      const int nsp = restricted ? 1 : 2;
+      const int64_t fsz = restricted ? m2 : n2;
+      if (restricted)
+        DFX_HIP(hipMemcpyAsync(Fh[2 * hpos].p, Feff.p, 8 * m2, hipMemcpyDeviceToDevice, st));
+      else
+        for (int s2 = 0; s2 < 2; ++s2)
+          DFX_HIP(hipMemcpyAsync(Fh[2 * hpos + s2].p, F[s2].p, 8 * n2, hipMemcpyDeviceToDevice, st));
       hcount = std::min(hcount + 1, dsz);
       for (int k = 0; k < hcount; ++k) {
         double b = 0.0;
-        for (int s2 = 0; s2 < 2; ++s2)
-          b += S.reduce_sum(Eh[2 * k + s2].as<double>(), Eh[2 * hpos + s2].as<double>(), nullptr, (int64_t)m * m);
+        for (int s2 = 0; s2 < nsp; ++s2)
+          b += S.reduce_sum(Eh[2 * k + s2].as<double>(), Eh[2 * hpos + s2].as<double>(), nullptr, m2);
         Bdiis[(size_t)hpos * dsz + k] = Bdiis[(size_t)k * dsz + hpos] = b;
       }
-      const double* Fuse[2] = {F[0].as<double>(), F[1].as<double>()};
+      const double* Fuse[2] = {restricted ? Feff.as<double>() : F[0].as<double>(), F[1].as<double>()};
       DevMem* Fext[2] = {&t1, &t2};
       if (hcount > 1) {
         std::vector<int> slots;
@@ -1190,14 +1268,14 @@ int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
           for (int i = 0; i < mm; ++i)
             for (int j = 0; j < mm; ++j) Bm[i * mm + j] = Bdiis[(size_t)slots[i] * dsz + slots[j]];
           if (diis_solve(Bm, mm, c)) {
-            for (int s2 = 0; s2 < 2; ++s2) {
+            for (int s2 = 0; s2 < nsp; ++s2) {
               Comb cb{};
               cb.m = mm;
               for (int i = 0; i < mm; ++i) {
                 cb.F[i] = Fh[2 * slots[i] + s2].as<double>();
                 cb.c[i] = c[i];
               }
-              hipLaunchKernelGGL(lincomb_kernel, dim3(nblk(n2)), dim3(256), 0, st, cb, Fext[s2]->as<double>(), n2);
+              hipLaunchKernelGGL(lincomb_kernel, dim3(nblk(fsz)), dim3(256), 0, st, cb, Fext[s2]->as<double>(), fsz);
               Fuse[s2] = Fext[s2]->as<double>();
             }
             break;
@@ -1206,6 +1284,10 @@ int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
         }
       }
       hpos = (hpos + 1) % dsz;
+      if (restricted) {
+        diag_orth(Fuse[0]);
+        continue;
+      }
       // diag overwrites t1 (X^T F): extrapolated alpha Fock matrix goes to F[0] first
       if (Fuse[0] != F[0].as<double>())
         DFX_HIP(hipMemcpyAsync(F[0].p, Fuse[0], 8 * n2, hipMemcpyDeviceToDevice, st));
@@ -1236,10 +1318,20 @@ int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     if (info) *info = inf;
     if (!converged) {
       status = DFX_ENOCONV;
-      set_last_error("dfx_uhf: not converged in " + std::to_string(o.max_iter) + " iterations");
+      set_last_error(fn + ": not converged in " + std::to_string(o.max_iter) + " iterations");
     }
   });
   return rc != DFX_OK ? rc : status;
+}
+
+int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
+            const dfx_scf_opts* opts, int multiplicity, double* E, dfx_scf_info* info) {
+  return open_shell_scf(geom, shells, nsh, aux, nauxsh, opts, multiplicity, E, info, false);
+}
+
+int dfx_rohf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
+             const dfx_scf_opts* opts, int multiplicity, double* E, dfx_scf_info* info) {
+  return open_shell_scf(geom, shells, nsh, aux, nauxsh, opts, multiplicity, E, info, true);
 }
 
 int dfx_lowdin(const dfx_geom* geom, const dfx_shell* shells, int nsh, const double* D, double* P, void* stream) {

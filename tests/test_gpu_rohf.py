@@ -1,0 +1,91 @@
+"""DF-ROHF through the C-ABI (dfx_rohf) against the oracle's (oracle/rohf.py).
+
+Same start (core Hamiltonian), same effective Fock matrix and DIIS on both
+sides, so the same path to the same state; energies agree to 1e-8 Eh.  Plus
+the properties that hold at any size: a closed shell is RHF, no beta electrons
+is UHF, and UHF is a lower bound.
+"""
+import numpy as np
+import pytest
+
+import systems
+import workloads as W
+from oracle import rohf as R
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+CONV = dict(conv_dE=1e-11, conv_err=1e-9, max_iter=200)
+
+
+@pytest.fixture(scope="module")
+def dfx():
+    import paper_1707_03771_amd as m
+    return m
+
+
+def _spins(Z, charge, mult):
+    nelec = int(np.sum(Z)) - charge
+    na = (nelec + mult - 1) // 2
+    return na, nelec - na
+
+
+def _system(name):
+    if name == "h4":
+        xyz, Z, sh, ax, _ = systems.h4()
+    elif name == "mixed":
+        xyz, Z, sh, ax = systems.mixed_molecule(seed=3, natom=6, lorb=2, laux=3)
+        Z = np.array([1] * len(Z), np.int32)
+    else:
+        e, xyz, sh, ax = W.workload("water1")
+        Z = W.charges(e)
+    return xyz, Z, sh, ax
+
+
+@pytest.mark.parametrize("name,charge,mult", [("h4", 1, 2), ("h4", 0, 3), ("h4", 3, 2), ("mixed", 1, 2),
+                                              ("mixed", 0, 3), ("water1", 1, 2)])
+def test_rohf_matches_oracle(dfx, name, charge, mult):
+    """mixed: 126 functions (three full 32-wide tiles and a ragged one), core,
+    open and virtual spaces all present."""
+    xyz, Z, sh, ax = _system(name)
+    na, nb = _spins(Z, charge, mult)
+    ref, _ = R.df_rohf(Z, xyz, sh, ax, na, nb, **CONV)
+    assert ref.converged
+    print(f"{name} q={charge} 2S+1={mult}: n_alpha {na} n_beta {nb}", flush=True)
+    E, info = dfx.rohf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, **CONV)
+    print(f"  E {E:.12f} oracle {ref.E:.12f} diff {E - ref.E:.2e} it {info['niter']} / {ref.niter}")
+    assert info["status"] == dfx.OK and info["converged"]
+    assert abs(E - ref.E) <= 1e-8
+
+
+def test_closed_shell_equals_rhf(dfx):
+    xyz, Z, sh, ax = _system("mixed")
+    E_o, io = dfx.rohf(xyz, Z, sh, ax, multiplicity=1, **CONV)
+    E_r, _, _, ir = dfx.scf(xyz, Z, sh, ax, want_c=False, **CONV)
+    assert io["converged"] and ir["converged"]
+    assert abs(E_o - E_r) <= 1e-9
+
+
+@pytest.mark.parametrize("charge,mult", [(2, 3), (1, 4)])
+def test_no_beta_electrons_equals_uhf(dfx, charge, mult):
+    xyz, Z, sh, ax = _system("h4")
+    assert _spins(Z, charge, mult)[1] == 0
+    E_o, io = dfx.rohf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, **CONV)
+    E_u, iu = dfx.uhf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, **CONV)
+    assert io["converged"] and iu["converged"]
+    assert abs(E_o - E_u) <= 1e-9
+
+
+def test_uhf_is_a_lower_bound(dfx):
+    xyz, Z, sh, ax = _system("mixed")
+    E_o, io = dfx.rohf(xyz, Z, sh, ax, multiplicity=3, **CONV)
+    E_u, iu = dfx.uhf(xyz, Z, sh, ax, multiplicity=3, **CONV)
+    assert io["converged"] and iu["converged"]
+    assert E_u <= E_o + 1e-10
+
+
+@pytest.mark.parametrize("charge,mult", [(0, 2), (0, 6)])
+def test_bad_spin_state_raises(dfx, charge, mult):
+    xyz, Z, sh, ax = _system("h4")
+    with pytest.raises(dfx.DfxError):
+        dfx.rohf(xyz, Z, sh, ax, charge=charge, multiplicity=mult)
