@@ -326,16 +326,16 @@ def eval_mp2(dfx, workloads=("alkane", "water4")):
     print(json.dumps({"metric": "DF-MP2 correlation energy after DF-RHF, FP64 MFMA", "runs": rows}))
 
 
-def eval_open_shell(dfx, runs=(("alkane", 0, 1, 150), ("alkane", 0, 3, 150), ("alkane", 1, 2, 150),
-                                 ("water4", 1, 2, 30))):
+def eval_open_shell(dfx, runs=(("alkane", 0, 1, 150, 0.0), ("alkane", 0, 3, 150, 0.0), ("alkane", 1, 2, 150, 0.0),
+                                 ("water4", 1, 2, 30, 0.0), ("water4", 1, 2, 80, 0.3))):
     """DF-UHF and DF-ROHF (FP64, core guess) at full size: energy, iterations and
     seconds per iteration beside the DF-RHF of the same molecule.  Closed shells
     must give the RHF energy and UHF must lie at or below ROHF.  The (H2O)64
     cation runs a fixed 30 iterations for the per-iteration time only: from the
     core guess with plain DIIS it does not converge (the oracle does not on the
-    (H2O)8 cation either)."""
+    (H2O)8 cation either); the last row adds a level shift of 0.3 Eh."""
     rows, rhf = [], {}
-    for wl, charge, mult, max_iter in runs:
+    for wl, charge, mult, max_iter, shift in runs:
         conv = dict(conv_dE=1e-9, conv_err=1e-7, max_iter=max_iter)
         elems, xyz, sh, ax = W.workload(wl, seed=0) if wl == "alkane" else W.workload(wl)
         Z = W.charges(elems)
@@ -345,11 +345,11 @@ def eval_open_shell(dfx, runs=(("alkane", 0, 1, 150), ("alkane", 0, 3, 150), ("a
         Er, ir = rhf[wl]
         ne = int(Z.sum()) - charge
         row = {"workload": wl, "charge": charge, "multiplicity": mult, "n_alpha": (ne + mult - 1) // 2,
-               "n_beta": ne - (ne + mult - 1) // 2, "max_iter": max_iter, "E_rhf": Er,
+               "n_beta": ne - (ne + mult - 1) // 2, "max_iter": max_iter, "level_shift": shift, "E_rhf": Er,
                "rhf_s_per_iter": round(ir["t_scf"] / max(1, ir["niter"]), 4)}
         for name, fn in (("uhf", dfx.uhf), ("rohf", dfx.rohf)):
             t0 = time.perf_counter()
-            E, info = fn(xyz, Z, sh, ax, charge=charge, multiplicity=mult, **conv)
+            E, info = fn(xyz, Z, sh, ax, charge=charge, multiplicity=mult, level_shift=shift, **conv)
             dt = time.perf_counter() - t0
             row.update({"nbf": info["nbf"], f"E_{name}": E, f"{name}_converged": info["converged"],
                         f"{name}_iters": info["niter"], f"{name}_s": round(dt, 3),

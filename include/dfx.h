@@ -270,6 +270,14 @@ typedef struct {
                             projector times the previous ones; dsyevd where it does not
                             settle.  0: dsyevd every iteration.  C and eps are the
                             eigenvectors and eigenvalues of the last X^T F X either way */
+  double level_shift;    /* dfx_uhf / dfx_rohf only (dfx_scf: must be 0): b >= 0 added to the
+                            virtual levels before each diagonalisation (Saunders and Hillier,
+                            Int. J. Quantum Chem. 7, 699 (1973)).  UHF: F_s + b (S - S D_s S);
+                            ROHF, in the orthonormal basis: F_eff + b (I - D/2), i.e. b on the
+                            virtual and b/2 on the open levels.  The shift commutes with the
+                            density at self-consistency, so it moves the path, not the
+                            converged state; the DIIS error is that of the unshifted matrices.
+                            0 (default): none */
 } dfx_scf_opts;
 
 #define DFX_MAXHIST 256
@@ -339,7 +347,7 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
  * from the core Hamiltonian for both spins.  FP64 J and K throughout.
  *   opts          as for dfx_scf; guess must be DFX_GUESS_CORE and schedule
  *                 DFX_SCHED_FP64 (DFX_EINVAL otherwise); the purification, learned
- *                 guess and precision switches do not apply
+ *                 guess and precision switches do not apply; level_shift applies
  *   multiplicity  2S + 1 >= 1; DFX_EINVAL if its parity does not match the electron
  *                 count, or if it exceeds nelec + 1
  *   E             host scalar out; info (may be NULL): niter, converged, nbf, naux,

@@ -70,7 +70,8 @@ class ScfOpts(ctypes.Structure):
                 ("ortho_thresh", ctypes.c_double), ("switch_err", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("diis_size", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("mixed_prec", ctypes.c_int32), ("guess", ctypes.c_int32), ("verbose", ctypes.c_int32),
-                ("model", ctypes.c_void_p), ("switch_auto", ctypes.c_int32), ("purify", ctypes.c_int32)]
+                ("model", ctypes.c_void_p), ("switch_auto", ctypes.c_int32), ("purify", ctypes.c_int32),
+                ("level_shift", ctypes.c_double)]
 
 
 class ScfInfo(ctypes.Structure):

@@ -51,6 +51,19 @@ __global__ void rohf_blocks_kernel(const double* Fa, const double* Fb, int m, in
   R[i] = (lo == 0 && hi == 1) ? Fb[i] : (lo == 1 && hi == 2) ? Fa[i] : 0.5 * (Fa[i] + Fb[i]);
 }
 
+// F += b (S - T): the level shift of one UHF spin, T = S D_s S
+__global__ void shift_ao_kernel(double* F, const double* S, const double* T, double b, int64_t n2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n2) F[i] += b * (S[i] - T[i]);
+}
+
+// F += b (I - D / 2) on an m x m matrix of the orthonormal basis (ROHF level shift)
+__global__ void shift_orth_kernel(double* F, const double* D, double b, int m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)m * m) return;
+  F[i] += b * ((i / m == i % m ? 1.0 : 0.0) - 0.5 * D[i]);
+}
+
 __global__ void add_kernel(const double* a, const double* b, double* c, int64_t n2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n2) c[i] = a[i] + b[i];
@@ -542,6 +555,7 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     dfx_scf_opts o;
     dfx_scf_default_opts(&o);
     if (opts_in) o = *opts_in;
+    if (o.level_shift != 0.0) throw Error(DFX_EINVAL, "dfx_scf: level_shift applies to dfx_uhf / dfx_rohf only");
     if (o.diis_size < 1 || o.diis_size > 16 || o.max_iter < 1) throw Error(DFX_EINVAL, "dfx_scf: bad options");
     if ((o.guess == DFX_GUESS_CINIT || o.guess == DFX_GUESS_DENSITY) && !init)
       throw Error(DFX_EINVAL, "dfx_scf: guess needs init");
@@ -1044,6 +1058,8 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
     if (o.diis_size < 1 || o.diis_size > 16 || o.max_iter < 1) throw Error(DFX_EINVAL, fn + ": bad options");
     if (o.guess != DFX_GUESS_CORE || o.schedule != DFX_SCHED_FP64)
       throw Error(DFX_EINVAL, fn + ": core guess and FP64 schedule only");
+    if (!(o.level_shift >= 0.0) || !std::isfinite(o.level_shift))
+      throw Error(DFX_EINVAL, fn + ": level_shift must be finite and >= 0");
     int nelec = -geom->charge;
     for (int a = 0; a < geom->natom; ++a) nelec += geom->Z[a];
     if (multiplicity < 1 || nelec <= 0 || (nelec + multiplicity - 1) % 2 || multiplicity - 1 > nelec)
@@ -1285,6 +1301,14 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
       }
       hpos = (hpos + 1) % dsz;
       if (restricted) {
+        if (o.level_shift > 0.0) {
+          // Dp still holds the density of the current orbitals in the orthonormal basis
+          if (Fuse[0] != t1.as<double>())
+            DFX_HIP(hipMemcpyAsync(t1.p, Fuse[0], 8 * m2, hipMemcpyDeviceToDevice, st));
+          hipLaunchKernelGGL(shift_orth_kernel, dim3(nblk(m2)), dim3(256), 0, st, t1.as<double>(), Dp.as<double>(),
+                             o.level_shift, m);
+          Fuse[0] = t1.as<double>();
+        }
         diag_orth(Fuse[0]);
         continue;
       }
@@ -1293,6 +1317,13 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
         DFX_HIP(hipMemcpyAsync(F[0].p, Fuse[0], 8 * n2, hipMemcpyDeviceToDevice, st));
       if (Fuse[1] != F[1].as<double>())
         DFX_HIP(hipMemcpyAsync(F[1].p, Fuse[1], 8 * n2, hipMemcpyDeviceToDevice, st));
+      if (o.level_shift > 0.0)
+        for (int s2 = 0; s2 < 2; ++s2) {
+          S.gemm(n, n, n, Sm.as<double>(), n, false, D[s2].as<double>(), n, false, t1.as<double>(), n);
+          S.gemm(n, n, n, t1.as<double>(), n, false, Sm.as<double>(), n, false, t2.as<double>(), n);
+          hipLaunchKernelGGL(shift_ao_kernel, dim3(nblk(n2)), dim3(256), 0, st, F[s2].as<double>(), Sm.as<double>(),
+                             t2.as<double>(), o.level_shift, n2);
+        }
       diag(0, F[0].as<double>());
       diag(1, F[1].as<double>());
     }

@@ -89,3 +89,30 @@ def test_bad_spin_state_raises(dfx, charge, mult):
     xyz, Z, sh, ax = _system("h4")
     with pytest.raises(dfx.DfxError):
         dfx.rohf(xyz, Z, sh, ax, charge=charge, multiplicity=mult)
+
+
+@pytest.mark.parametrize("method", ["uhf", "rohf"])
+@pytest.mark.parametrize("name,charge,mult", [("h4", 1, 2), ("mixed", 0, 3), ("water1", 1, 2)])
+def test_level_shift_keeps_the_converged_state(dfx, method, name, charge, mult):
+    """A level shift changes the path, not the fixed point: the shifted runs reach
+    the oracle's unshifted energy."""
+    xyz, Z, sh, ax = _system(name)
+    na, nb = _spins(Z, charge, mult)
+    if method == "uhf":
+        from oracle import uhf as U
+        ref, _ = U.df_uhf(Z, xyz, sh, ax, na, nb, **CONV)
+    else:
+        ref, _ = R.df_rohf(Z, xyz, sh, ax, na, nb, **CONV)
+    assert ref.converged
+    E, info = getattr(dfx, method)(xyz, Z, sh, ax, charge=charge, multiplicity=mult, level_shift=0.5, **CONV)
+    print(f"{method} {name}: shifted E {E:.12f} oracle {ref.E:.12f} diff {E - ref.E:.2e} it {info['niter']}")
+    assert info["converged"]
+    assert abs(E - ref.E) <= 1e-8
+
+
+def test_level_shift_validation(dfx):
+    xyz, Z, sh, ax = _system("h4")
+    with pytest.raises(dfx.DfxError):
+        dfx.rohf(xyz, Z, sh, ax, charge=1, multiplicity=2, level_shift=-0.1)
+    with pytest.raises(dfx.DfxError):
+        dfx.scf(xyz, Z, sh, ax, level_shift=0.2)
