@@ -116,3 +116,25 @@ def test_level_shift_validation(dfx):
         dfx.rohf(xyz, Z, sh, ax, charge=1, multiplicity=2, level_shift=-0.1)
     with pytest.raises(dfx.DfxError):
         dfx.scf(xyz, Z, sh, ax, level_shift=0.2)
+
+
+def test_open_shell_at_full_size(dfx):
+    """C30H62 (730 functions, 3106 auxiliary; the size the alkane evaluation
+    runs), where the oracle would take half an hour per SCF: the properties
+    that hold at any size.  Closed-shell UHF and ROHF give the RHF energy; the
+    triplet converges in both, with UHF at or below ROHF."""
+    elems, xyz, sh, ax = W.workload("alkane", seed=0)
+    Z = W.charges(elems)
+    conv = dict(conv_dE=1e-9, conv_err=1e-7, max_iter=150)
+    E_r, _, _, ir = dfx.scf(xyz, Z, sh, ax, want_c=False, **conv)
+    assert ir["converged"]
+    for fn in (dfx.uhf, dfx.rohf):
+        E, info = fn(xyz, Z, sh, ax, multiplicity=1, **conv)
+        print(f"{fn.__name__} singlet: E - E_RHF = {E - E_r:.2e} ({info['niter']} iterations)", flush=True)
+        assert info["converged"] and abs(E - E_r) <= 1e-8
+    E_u, iu = dfx.uhf(xyz, Z, sh, ax, multiplicity=3, **conv)
+    E_o, io = dfx.rohf(xyz, Z, sh, ax, multiplicity=3, **conv)
+    print(f"triplet: UHF {E_u:.9f} ({iu['niter']} it), ROHF {E_o:.9f} ({io['niter']} it)")
+    assert iu["converged"] and io["converged"]
+    assert iu["nbf"] == 730 and E_u <= E_o + 1e-9
+    assert E_o - E_u < 0.05
