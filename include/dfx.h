@@ -263,7 +263,10 @@ typedef struct {
                             commutator of the difference scaled by sqrt(16); the stage
                             ends once its error is below max(switch_err, estimate).  Into
                             FP64 from a stage with an estimate <= 1e-3 the DIIS history
-                            carries over; otherwise DIIS restarts */
+                            carries over; otherwise DIIS restarts.  A BF16 stage is also
+                            estimated on entry and skipped if its floor is above its 1e-2
+                            threshold (a nearly linearly dependent basis amplifies BF16's
+                            rounding); floor_est[DFX_BF16] then holds that estimate */
   int32_t purify;        /* 1 (default): after the first iteration, the occupied orbitals of
                             X^T F X come from trace-correcting purification (Niklasson,
                             Phys. Rev. B 66, 155115 (2002)) and a Cholesky QR of the

@@ -803,33 +803,21 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     std::vector<double> Bdiis((size_t)dsz * dsz, 0.0);
     for (it = 1; it <= o.max_iter; ++it) {
       const int ih = it_done + it;  // iteration number over both passes
-      ja.prec = prec;
-      size_t need = std::max(sizeof(double) * (2 * (size_t)B->ncols_t + B->naux + 8), k_work_bytes(ja, nocc));
-      // the floor is estimated once per stage, at the first iteration after the
-      // stage's error fell below 1e-2: by then DIIS converges steadily and the
-      // density is close enough to the solution for the estimate to be the floor
-      // (at a poor starting density it overshoots and would end the stage early)
-      const bool estimate = mixed && o.switch_auto && prec != DFX_FP64 && !stage_estimated && !stage_errs.empty() &&
-                            stage_errs.back() < 1e-2;
-      JKArgs sub = ja;
-      if (estimate) {
-        // every S-th auxiliary function: rows S q of B, as a tensor with row stride S ncols
+      // the floor of reduced precision p at the current density: how far its K
+      // moves the DIIS error, measured on every S-th auxiliary function (rows S q
+      // of B, a tensor with row stride S ncols) and scaled to all of them
+      // (independent rounding errors add in quadrature)
+      auto estimate_floor = [&](int p) {
+        JKArgs sub = ja;
+        sub.prec = p;
         const int Sg = std::max(1, std::min(16, B->naux / 64));
         sub.naux = (B->naux + Sg - 1) / Sg;
         sub.ncols = ja.ncols * Sg;
         JKArgs s64 = sub;
         s64.prec = PREC_FP64;
-        need = std::max(need, std::max(k_work_bytes(sub, nocc), k_work_bytes(s64, nocc)));
-      }
-      void* w = B->ensure_work(need);
-      if (estimate) {
-        // the stage's floor: how far its K moves the DIIS error, measured at this
-        // density on the sample and scaled to all functions (independent rounding
-        // errors add in quadrature)
-        k_build(sub, Cocc.as<double>(), nocc, Km.as<double>(), w, st, nullptr);
-        JKArgs s64 = sub;
-        s64.prec = PREC_FP64;
-        k_build(s64, Cocc.as<double>(), nocc, Jm.as<double>(), w, st, nullptr);
+        void* ws = B->ensure_work(std::max(k_work_bytes(sub, nocc), k_work_bytes(s64, nocc)));
+        k_build(sub, Cocc.as<double>(), nocc, Km.as<double>(), ws, st, nullptr);
+        k_build(s64, Cocc.as<double>(), nocc, Jm.as<double>(), ws, st, nullptr);
         Comb cd{};
         cd.m = 2;
         cd.F[0] = Km.as<double>();
@@ -842,12 +830,38 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
         hipLaunchKernelGGL(antisym_kernel, dim3(nblk(n2)), dim3(256), 0, st, t2.as<double>(), t1.as<double>(), n);
         S.gemm(m, n, n, X.as<double>(), m, true, t1.as<double>(), n, false, t2.as<double>(), n);
         S.gemm(m, m, n, t2.as<double>(), n, false, X.as<double>(), m, false, Fp.as<double>(), m);
-        const double est = S.reduce_max(Fp.as<double>(), (int64_t)m * m) * std::sqrt((double)B->naux / sub.naux);
+        return S.reduce_max(Fp.as<double>(), (int64_t)m * m) * std::sqrt((double)B->naux / sub.naux);
+      };
+      // a BF16 stage is checked on entry: where the basis is nearly linearly
+      // dependent, X^T (.) X amplifies BF16's rounding of K beyond the stage's own
+      // threshold, and its Fock matrices would lead the SCF away (measured on
+      // (H2O)64: DIIS errors of 10 and more).  Such a stage is skipped.
+      if (mixed && o.switch_auto && prec == DFX_BF16 && stage_it == 0) {
+        const double est = estimate_floor(DFX_BF16);
+        floor_est[DFX_BF16] = est;
+        if (o.verbose) std::fprintf(stderr, "dfx_scf BF16 stage: estimated floor %.3e on entry\n", est);
+        if (est > stage_thr[stage]) {
+          if (o.verbose) std::fprintf(stderr, "dfx_scf BF16 stage skipped\n");
+          ++stage;
+          prec = stages[stage];
+        }
+      }
+      ja.prec = prec;
+      size_t need = std::max(sizeof(double) * (2 * (size_t)B->ncols_t + B->naux + 8), k_work_bytes(ja, nocc));
+      // the floor is estimated once per stage, at the first iteration after the
+      // stage's error fell below 1e-2: by then DIIS converges steadily and the
+      // density is close enough to the solution for the estimate to be the floor
+      // (at a poor starting density it overshoots and would end the stage early)
+      const bool estimate = mixed && o.switch_auto && prec != DFX_FP64 && !stage_estimated && !stage_errs.empty() &&
+                            stage_errs.back() < 1e-2;
+      if (estimate) {
+        const double est = estimate_floor(prec);
         floor_est[prec] = est;
         stage_thr[stage] = std::max(stage_thr[stage], est);
         stage_estimated = true;
         if (o.verbose) std::fprintf(stderr, "dfx_scf stage %d: estimated floor %.3e\n", stage, est);
       }
+      void* w = B->ensure_work(need);
       sp_j.begin();
       j_build(ja, D.as<double>(), Jm.as<double>(), reinterpret_cast<double*>(w), st);
       sp_j.end();

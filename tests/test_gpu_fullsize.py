@@ -271,6 +271,24 @@ def test_water_scf_schedules_agree(water, dfx):
           f"purification: {ip['n_purified']} updates, {ip['purify_steps']} squarings")
 
 
+def test_water_bf16_stage_skipped_on_entry(water, dfx):
+    """(H2O)64's overlap has eigenvalues down to 1.4e-5, so X^T (.) X amplifies
+    BF16's rounding of K beyond the BF16 stage's 1e-2 threshold (run anyway,
+    its first Fock build had a DIIS error of 10).  The stage's floor is
+    estimated on entry and the stage skipped: the run is then the FP32 -> FP64
+    schedule, iteration for iteration."""
+    xyz, sh, ax = water["xyz"], water["sh"], water["ax"]
+    Z = W.charges(water["elems"])
+    conv = dict(conv_dE=1e-7, conv_err=1e-5, want_c=False, schedule=dfx.SCHED_MIXED)
+    Eb, _, _, ib = dfx.scf(xyz, Z, sh, ax, mixed_prec=dfx.BF16, **conv)
+    Ef, _, _, i_f = dfx.scf(xyz, Z, sh, ax, mixed_prec=dfx.FP32, **conv)
+    print(f"(H2O)64 BF16 entry estimate {ib['floor_est'][dfx.BF16]:.2e}; iterations {ib['niter']} / {i_f['niter']}")
+    assert ib["converged"] and i_f["converged"]
+    assert ib["floor_est"][dfx.BF16] > 1e-2
+    assert dfx.BF16 not in ib["prec_hist"]
+    assert ib["niter"] == i_f["niter"] and abs(Eb - Ef) <= 1e-9
+
+
 # ---- C30H62 against the oracle's stored energy ---------------------------------
 
 def test_alkane_energy_against_oracle(dfx):

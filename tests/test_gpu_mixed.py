@@ -86,3 +86,7 @@ def test_mixed_scf_energy_is_the_fp64_energy(dfx, prec):
     E, _, _, info = dfx.scf(xyz, Z, sh, ax, schedule=dfx.SCHED_MIXED, mixed_prec=getattr(dfx, prec))
     assert info["converged"] and info["n_mixed"] >= 1
     assert abs(E - ref.E) <= 1e-8
+    if prec == "BF16":
+        # a well-conditioned basis: the BF16 stage passes its entry check and runs
+        assert 0.0 < info["floor_est"][dfx.BF16] <= 1e-2
+        assert dfx.BF16 in info["prec_hist"]
