@@ -272,7 +272,7 @@ def test_water_scf_schedules_agree(water, dfx):
 
 
 def test_water_bf16_stage_skipped_on_entry(water, dfx):
-    """(H2O)64's overlap has eigenvalues down to 1.4e-5, so X^T (.) X amplifies
+    """(H2O)64's overlap has eigenvalues down to 1.9e-6, so X^T (.) X amplifies
     BF16's rounding of K beyond the BF16 stage's 1e-2 threshold (run anyway,
     its first Fock build had a DIIS error of 10).  The stage's floor is
     estimated on entry and the stage skipped: the run is then the FP32 -> FP64
