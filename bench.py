@@ -349,7 +349,8 @@ def eval_open_shell(dfx, runs=(("alkane", 0, 1, 150, 0.0), ("alkane", 0, 3, 150,
                "rhf_s_per_iter": round(ir["t_scf"] / max(1, ir["niter"]), 4)}
         for name, fn in (("uhf", dfx.uhf), ("rohf", dfx.rohf)):
             t0 = time.perf_counter()
-            E, info = fn(xyz, Z, sh, ax, charge=charge, multiplicity=mult, level_shift=shift, **conv)
+            E, _, _, info = fn(xyz, Z, sh, ax, charge=charge, multiplicity=mult, level_shift=shift, want_c=False,
+                               **conv)
             dt = time.perf_counter() - t0
             row.update({"nbf": info["nbf"], f"E_{name}": E, f"{name}_converged": info["converged"],
                         f"{name}_iters": info["niter"], f"{name}_s": round(dt, 3),

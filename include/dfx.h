@@ -353,14 +353,20 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
  *                 guess and precision switches do not apply; level_shift applies
  *   multiplicity  2S + 1 >= 1; DFX_EINVAL if its parity does not match the electron
  *                 count, or if it exceeds nelec + 1
- *   E             host scalar out; info (may be NULL): niter, converged, nbf, naux,
- *                 nocc (= n_alpha), E_nuc, err_max (larger of the two spins),
- *                 E_hist / err_hist, timings
- * Synchronous.  DFX_ENOCONV: not converged within max_iter (E written).
+ *   E             host scalar out
+ *   C             host [2][nbf][nbf] out (may be NULL): alpha then beta orbitals whose
+ *                 densities gave E, columns in ascending level order; the last
+ *                 ndropped columns are zero (canonical orthogonalisation)
+ *   eps           host [2][nbf] out (may be NULL): the levels of those orbitals, the
+ *                 eigenvalues of the (DIIS-extrapolated, level-shifted) X^T F_s X
+ *                 last diagonalised; zero beyond nbf - ndropped
+ *   info          may be NULL: niter, converged, nbf, naux, nocc (= n_alpha), E_nuc,
+ *                 err_max (larger of the two spins), E_hist / err_hist, timings
+ * Synchronous.  DFX_ENOCONV: not converged within max_iter (E, C and eps written).
  * A closed shell (multiplicity 1) gives the dfx_scf energy for the same options.
  */
 int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
-            const dfx_scf_opts* opts, int multiplicity, double* E, dfx_scf_info* info);
+            const dfx_scf_opts* opts, int multiplicity, double* E, double* C, double* eps, dfx_scf_info* info);
 
 /*
  * dfx_rohf -- DF-ROHF (section "Standard algorithms" lists restricted open-shell
@@ -374,11 +380,14 @@ int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
  * basis of X, and Pulay DIIS extrapolates it with the error F_eff D - D F_eff of
  * D = D_alpha + D_beta in that basis (zero exactly when the core-open, core-virtual
  * and open-virtual blocks are).  Arguments, options, errors and info as for
- * dfx_uhf (err_max: the one error matrix).  A closed shell gives the dfx_scf
+ * dfx_uhf (err_max: the one error matrix), except that C is one set, host
+ * [nbf][nbf] (core, open, virtual columns in that order), and eps host [nbf], the
+ * eigenvalues of the effective Fock matrix last diagonalised (Roothaan's
+ * canonicalisation: unlike E and D they depend on the diagonal-block choice).  A closed shell gives the dfx_scf
  * energy; with n_beta = 0 it is the dfx_uhf determinant.
  */
 int dfx_rohf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
-             const dfx_scf_opts* opts, int multiplicity, double* E, dfx_scf_info* info);
+             const dfx_scf_opts* opts, int multiplicity, double* E, double* C, double* eps, dfx_scf_info* info);
 
 /* ---- learned starting guess ---------------------------------------------------
  * Replaces the core-Hamiltonian start of the SCF ("Standard algorithms") with a

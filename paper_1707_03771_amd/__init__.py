@@ -116,8 +116,8 @@ _SIGS = {
     "dfx_mp2": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp],
     "dfx_int1e": [_vp, _i, _vp, _vp, _vp, _vp, _vp],
     "dfx_scf": [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp],
-    "dfx_uhf": [_vp, _vp, _i, _vp, _i, _vp, _i, _vp, _vp],
-    "dfx_rohf": [_vp, _vp, _i, _vp, _i, _vp, _i, _vp, _vp],
+    "dfx_uhf": [_vp, _vp, _i, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp],
+    "dfx_rohf": [_vp, _vp, _i, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp],
     "dfx_scf_default_opts": [_vp],
     "dfx_metric": [_vp, _i, _vp, _vp],
     "dfx_cholesky": [_vp, _i, _vp, _vp],
@@ -371,7 +371,7 @@ def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, model=None, **opt
     return E.value, C, eps, info
 
 
-def _open_shell(fn, xyz, Z, shells, aux, charge, multiplicity, opts):
+def _open_shell(fn, nset, xyz, Z, shells, aux, charge, multiplicity, want_c, opts):
     o = scf_default_opts()
     for k, v in opts.items():
         if not hasattr(o, k) or k == "model":
@@ -379,27 +379,34 @@ def _open_shell(fn, xyz, Z, shells, aux, charge, multiplicity, opts):
         setattr(o, k, v)
     s, a = _ShellArray(shells), _ShellArray(aux)
     g = _GeomC(xyz, Z, charge)
+    n = sum(2 * int(q["l"]) + 1 for q in shells)
     E = ctypes.c_double()
+    C = np.zeros((nset, n, n)) if want_c else None
+    eps = np.zeros((nset, n)) if want_c else None
     inf = ScfInfo()
     code = fn(ctypes.byref(g.g), s.arr, s.n, a.arr, a.n, ctypes.byref(o), int(multiplicity), ctypes.byref(E),
-              ctypes.byref(inf))
+              C.ctypes.data if want_c else None, eps.ctypes.data if want_c else None, ctypes.byref(inf))
     if code not in (OK, ENOCONV):
         _check(code)
     info = {k: getattr(inf, k) for k, _ in ScfInfo._fields_ if not k.endswith("_hist")}
     info["E_hist"] = list(inf.E_hist)[: inf.niter]
     info["err_hist"] = list(inf.err_hist)[: inf.niter]
     info["status"] = code
-    return E.value, info
+    if want_c and nset == 1:
+        C, eps = C[0], eps[0]
+    return E.value, C, eps, info
 
 
-def uhf(xyz, Z, shells, aux, charge=0, multiplicity=1, **opts):
-    """dfx_uhf: DF-UHF (FP64, core guess).  Returns (E, info dict)."""
-    return _open_shell(_lib.dfx_uhf, xyz, Z, shells, aux, charge, multiplicity, opts)
+def uhf(xyz, Z, shells, aux, charge=0, multiplicity=1, want_c=True, **opts):
+    """dfx_uhf: DF-UHF (FP64, core guess).  Returns (E, C, eps, info dict) with
+    C [2][nbf][nbf] (alpha, beta) and eps [2][nbf] (None with want_c=False)."""
+    return _open_shell(_lib.dfx_uhf, 2, xyz, Z, shells, aux, charge, multiplicity, want_c, opts)
 
 
-def rohf(xyz, Z, shells, aux, charge=0, multiplicity=1, **opts):
-    """dfx_rohf: DF-ROHF (FP64, core guess).  Returns (E, info dict)."""
-    return _open_shell(_lib.dfx_rohf, xyz, Z, shells, aux, charge, multiplicity, opts)
+def rohf(xyz, Z, shells, aux, charge=0, multiplicity=1, want_c=True, **opts):
+    """dfx_rohf: DF-ROHF (FP64, core guess).  Returns (E, C, eps, info dict) with
+    C [nbf][nbf] (core, open, virtual) and eps [nbf] (None with want_c=False)."""
+    return _open_shell(_lib.dfx_rohf, 1, xyz, Z, shells, aux, charge, multiplicity, want_c, opts)
 
 
 # ---- learned starting guess ------------------------------------------------------

@@ -1058,7 +1058,7 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
 // formed and extrapolated in the orthonormal basis of X.
 static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux,
                           int nauxsh, const dfx_scf_opts* opts_in, int multiplicity, double* E_out,
-                          dfx_scf_info* info, bool restricted) {
+                          double* C_out, double* eps_out, dfx_scf_info* info, bool restricted) {
   const std::string fn = restricted ? "dfx_rohf" : "dfx_uhf";
   int status = DFX_OK;
   const int rc = guard([&] {
@@ -1138,10 +1138,13 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
 
     // per spin: occupied orbitals, density, K, Fock matrix, DIIS error
     const int nocc_s[2] = {na, nb};
-    DevMem J(8 * n2), Dt(8 * n2), t1(8 * n2), t2(8 * n2), Fp(8 * (size_t)m * m), eps(8 * (size_t)m),
-        Cm(8 * (size_t)n * m);
-    DevMem Cocc[2], D[2], K[2], F[2];
+    DevMem J(8 * n2), Dt(8 * n2), t1(8 * n2), t2(8 * n2), Fp(8 * (size_t)m * m);
+    // orbitals (n x m, C = X V^T) and levels of the last solve: one per spin (UHF),
+    // one set (ROHF)
+    DevMem Cm[2], eps[2], Cocc[2], D[2], K[2], F[2];
     for (int s2 = 0; s2 < 2; ++s2) {
+      Cm[s2].alloc(8 * (size_t)n * m);
+      eps[s2].alloc(8 * (size_t)m);
       Cocc[s2].alloc(8 * (size_t)n * std::max(1, nocc_s[s2]));
       D[s2].alloc(8 * n2);
       K[s2].alloc(8 * n2);
@@ -1157,11 +1160,11 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
     auto diag = [&](int s2, const double* Fx) {
       S.gemm(m, n, n, X.as<double>(), m, true, Fx, n, false, t1.as<double>(), n);
       S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Fp.as<double>(), m);
-      S.syevd(Fp.as<double>(), m, eps.as<double>());
-      S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm.as<double>(), m);
+      S.syevd(Fp.as<double>(), m, eps[s2].as<double>());
+      S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm[s2].as<double>(), m);
       if (nocc_s[s2] > 0) {
-        hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc_s[s2])), dim3(256), 0, st, Cm.as<double>(),
-                           m, n, nocc_s[s2], Cocc[s2].as<double>(), nocc_s[s2]);
+        hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc_s[s2])), dim3(256), 0, st,
+                           Cm[s2].as<double>(), m, n, nocc_s[s2], Cocc[s2].as<double>(), nocc_s[s2]);
         S.gemm(n, n, nocc_s[s2], Cocc[s2].as<double>(), nocc_s[s2], false, Cocc[s2].as<double>(), nocc_s[s2], true,
                D[s2].as<double>(), n);
       } else {
@@ -1181,12 +1184,12 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
     }
     auto diag_orth = [&](const double* Fm) {
       DFX_HIP(hipMemcpyAsync(Fp.p, Fm, 8 * m2, hipMemcpyDeviceToDevice, st));
-      S.syevd(Fp.as<double>(), m, eps.as<double>());
-      S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm.as<double>(), m);
+      S.syevd(Fp.as<double>(), m, eps[0].as<double>());
+      S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm[0].as<double>(), m);
       for (int s2 = 0; s2 < 2; ++s2) {
         if (nocc_s[s2] > 0) {
           hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc_s[s2])), dim3(256), 0, st,
-                             Cm.as<double>(), m, n, nocc_s[s2], Cocc[s2].as<double>(), nocc_s[s2]);
+                             Cm[0].as<double>(), m, n, nocc_s[s2], Cocc[s2].as<double>(), nocc_s[s2]);
           S.gemm(n, n, nocc_s[s2], Cocc[s2].as<double>(), nocc_s[s2], false, Cocc[s2].as<double>(), nocc_s[s2],
                  true, D[s2].as<double>(), n);
         } else {
@@ -1344,6 +1347,23 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
     DFX_HIP(hipStreamSynchronize(st));
     const auto t2c = clk::now();
     *E_out = E;
+    // the orbitals whose densities gave E: [nbf][nbf] per set, the first m columns
+    // X V^T and the rest zero; levels [nbf], zero beyond m
+    const int nset = restricted ? 1 : 2;
+    for (int s2 = 0; s2 < nset; ++s2) {
+      if (C_out) {
+        std::vector<double> Ch((size_t)n * m);
+        DFX_HIP(hipMemcpy(Ch.data(), Cm[s2].p, 8 * (size_t)n * m, hipMemcpyDeviceToHost));
+        double* Co = C_out + (size_t)s2 * n2;
+        for (int r = 0; r < n; ++r)
+          for (int c = 0; c < n; ++c) Co[(size_t)r * n + c] = c < m ? Ch[(size_t)r * m + c] : 0.0;
+      }
+      if (eps_out) {
+        std::vector<double> e(m);
+        DFX_HIP(hipMemcpy(e.data(), eps[s2].p, 8 * (size_t)m, hipMemcpyDeviceToHost));
+        for (int i = 0; i < n; ++i) eps_out[(size_t)s2 * n + i] = i < m ? e[i] : 0.0;
+      }
+    }
     inf.niter = std::min(it, o.max_iter);
     inf.converged = converged ? 1 : 0;
     inf.ndropped = ndrop;
@@ -1370,13 +1390,13 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
 }
 
 int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
-            const dfx_scf_opts* opts, int multiplicity, double* E, dfx_scf_info* info) {
-  return open_shell_scf(geom, shells, nsh, aux, nauxsh, opts, multiplicity, E, info, false);
+            const dfx_scf_opts* opts, int multiplicity, double* E, double* C, double* eps, dfx_scf_info* info) {
+  return open_shell_scf(geom, shells, nsh, aux, nauxsh, opts, multiplicity, E, C, eps, info, false);
 }
 
 int dfx_rohf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
-             const dfx_scf_opts* opts, int multiplicity, double* E, dfx_scf_info* info) {
-  return open_shell_scf(geom, shells, nsh, aux, nauxsh, opts, multiplicity, E, info, true);
+             const dfx_scf_opts* opts, int multiplicity, double* E, double* C, double* eps, dfx_scf_info* info) {
+  return open_shell_scf(geom, shells, nsh, aux, nauxsh, opts, multiplicity, E, C, eps, info, true);
 }
 
 int dfx_lowdin(const dfx_geom* geom, const dfx_shell* shells, int nsh, const double* D, double* P, void* stream) {

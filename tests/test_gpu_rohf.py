@@ -52,15 +52,21 @@ def test_rohf_matches_oracle(dfx, name, charge, mult):
     ref, _ = R.df_rohf(Z, xyz, sh, ax, na, nb, **CONV)
     assert ref.converged
     print(f"{name} q={charge} 2S+1={mult}: n_alpha {na} n_beta {nb}", flush=True)
-    E, info = dfx.rohf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, **CONV)
+    E, C, eps, info = dfx.rohf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, **CONV)
     print(f"  E {E:.12f} oracle {ref.E:.12f} diff {E - ref.E:.2e} it {info['niter']} / {ref.niter}")
     assert info["status"] == dfx.OK and info["converged"]
     assert abs(E - ref.E) <= 1e-8
+    # spin densities from the one orbital set, and the effective Fock levels of the
+    # occupied orbitals (same construction on both sides)
+    for s_, n_ in enumerate((na, nb)):
+        D = C[:, :n_] @ C[:, :n_].T
+        assert np.abs(D - ref.D[s_]).max() <= 1e-6 * max(1.0, np.abs(ref.D[s_]).max())
+    assert np.abs(eps[:na] - ref.eps[:na]).max() <= 1e-6
 
 
 def test_closed_shell_equals_rhf(dfx):
     xyz, Z, sh, ax = _system("mixed")
-    E_o, io = dfx.rohf(xyz, Z, sh, ax, multiplicity=1, **CONV)
+    E_o, _, _, io = dfx.rohf(xyz, Z, sh, ax, multiplicity=1, want_c=False, **CONV)
     E_r, _, _, ir = dfx.scf(xyz, Z, sh, ax, want_c=False, **CONV)
     assert io["converged"] and ir["converged"]
     assert abs(E_o - E_r) <= 1e-9
@@ -70,16 +76,16 @@ def test_closed_shell_equals_rhf(dfx):
 def test_no_beta_electrons_equals_uhf(dfx, charge, mult):
     xyz, Z, sh, ax = _system("h4")
     assert _spins(Z, charge, mult)[1] == 0
-    E_o, io = dfx.rohf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, **CONV)
-    E_u, iu = dfx.uhf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, **CONV)
+    E_o, _, _, io = dfx.rohf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, want_c=False, **CONV)
+    E_u, _, _, iu = dfx.uhf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, want_c=False, **CONV)
     assert io["converged"] and iu["converged"]
     assert abs(E_o - E_u) <= 1e-9
 
 
 def test_uhf_is_a_lower_bound(dfx):
     xyz, Z, sh, ax = _system("mixed")
-    E_o, io = dfx.rohf(xyz, Z, sh, ax, multiplicity=3, **CONV)
-    E_u, iu = dfx.uhf(xyz, Z, sh, ax, multiplicity=3, **CONV)
+    E_o, _, _, io = dfx.rohf(xyz, Z, sh, ax, multiplicity=3, want_c=False, **CONV)
+    E_u, _, _, iu = dfx.uhf(xyz, Z, sh, ax, multiplicity=3, want_c=False, **CONV)
     assert io["converged"] and iu["converged"]
     assert E_u <= E_o + 1e-10
 
@@ -104,7 +110,8 @@ def test_level_shift_keeps_the_converged_state(dfx, method, name, charge, mult):
     else:
         ref, _ = R.df_rohf(Z, xyz, sh, ax, na, nb, **CONV)
     assert ref.converged
-    E, info = getattr(dfx, method)(xyz, Z, sh, ax, charge=charge, multiplicity=mult, level_shift=0.5, **CONV)
+    E, _, _, info = getattr(dfx, method)(xyz, Z, sh, ax, charge=charge, multiplicity=mult, level_shift=0.5,
+                                         want_c=False, **CONV)
     print(f"{method} {name}: shifted E {E:.12f} oracle {ref.E:.12f} diff {E - ref.E:.2e} it {info['niter']}")
     assert info["converged"]
     assert abs(E - ref.E) <= 1e-8
@@ -129,11 +136,11 @@ def test_open_shell_at_full_size(dfx):
     E_r, _, _, ir = dfx.scf(xyz, Z, sh, ax, want_c=False, **conv)
     assert ir["converged"]
     for fn in (dfx.uhf, dfx.rohf):
-        E, info = fn(xyz, Z, sh, ax, multiplicity=1, **conv)
+        E, _, _, info = fn(xyz, Z, sh, ax, multiplicity=1, want_c=False, **conv)
         print(f"{fn.__name__} singlet: E - E_RHF = {E - E_r:.2e} ({info['niter']} iterations)", flush=True)
         assert info["converged"] and abs(E - E_r) <= 1e-8
-    E_u, iu = dfx.uhf(xyz, Z, sh, ax, multiplicity=3, **conv)
-    E_o, io = dfx.rohf(xyz, Z, sh, ax, multiplicity=3, **conv)
+    E_u, _, _, iu = dfx.uhf(xyz, Z, sh, ax, multiplicity=3, want_c=False, **conv)
+    E_o, _, _, io = dfx.rohf(xyz, Z, sh, ax, multiplicity=3, want_c=False, **conv)
     print(f"triplet: UHF {E_u:.9f} ({iu['niter']} it), ROHF {E_o:.9f} ({io['niter']} it)")
     assert iu["converged"] and io["converged"]
     assert iu["nbf"] == 730 and E_u <= E_o + 1e-9

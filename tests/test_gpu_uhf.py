@@ -53,16 +53,21 @@ def test_uhf_matches_oracle(dfx, name, charge, mult):
     ref, _ = U.df_uhf(Z, xyz, sh, ax, na, nb, **CONV)
     assert ref.converged
     print(f"{name} q={charge} 2S+1={mult}: n_alpha {na} n_beta {nb}", flush=True)
-    E, info = dfx.uhf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, **CONV)
+    E, C, eps, info = dfx.uhf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, **CONV)
     print(f"  E {E:.12f} oracle {ref.E:.12f} diff {E - ref.E:.2e} it {info['niter']} / {ref.niter}")
     assert info["status"] == dfx.OK and info["converged"]
     assert info["nocc"] == na
     assert abs(E - ref.E) <= 1e-8
+    # the spin densities (projectors: unique) and the occupied levels
+    for s_, n_ in enumerate((na, nb)):
+        D = C[s_][:, :n_] @ C[s_][:, :n_].T
+        assert np.abs(D - ref.D[s_]).max() <= 1e-6 * max(1.0, np.abs(ref.D[s_]).max())
+        assert np.abs(eps[s_][:n_] - ref.eps[s_][:n_]).max(initial=0.0) <= 1e-6
 
 
 def test_closed_shell_equals_rhf(dfx):
     xyz, Z, sh, ax = _mixed()
-    E_u, iu = dfx.uhf(xyz, Z, sh, ax, multiplicity=1, **CONV)
+    E_u, _, _, iu = dfx.uhf(xyz, Z, sh, ax, multiplicity=1, want_c=False, **CONV)
     E_r, _, _, ir = dfx.scf(xyz, Z, sh, ax, want_c=False, **CONV)
     print(f"UHF {E_u:.12f} RHF {E_r:.12f} diff {E_u - E_r:.2e}")
     assert iu["converged"] and ir["converged"]
@@ -72,7 +77,7 @@ def test_closed_shell_equals_rhf(dfx):
 def test_one_electron_is_core_ground_state(dfx):
     """A single electron feels no two-electron energy: J and K of B cancel exactly."""
     xyz, Z, sh, ax, _ = systems.h4()
-    E, info = dfx.uhf(xyz, Z, sh, ax, charge=3, multiplicity=2, **CONV)
+    E, _, _, info = dfx.uhf(xyz, Z, sh, ax, charge=3, multiplicity=2, want_c=False, **CONV)
     bas = O.Basis(sh)
     S, T, V = O.int1e(bas, xyz, Z)
     import scipy.linalg as sla
