@@ -42,23 +42,57 @@ __global__ void mp2_scatter_kernel(const double* __restrict__ T, int nv, int no,
 // (e_i + e_j - e_a - e_b), weight 2 for j < i; M = (ia|jb) for one i.  Fixed grid and
 // tree order: out[blockIdx.x]
 constexpr int MP2_RB = 1024;
+constexpr int MP2_T = 32;
+// Work item (j, A <= B): the 32 x 32 tiles X = M_j[A][B] and Y = M_j[B][A] of the
+// nv x nv block M_j[a][b] = (ia|jb), both read as rows (coalesced) into padded
+// LDS.  Off the tile diagonal the item adds the (a, b) and (b, a) terms of the
+// pair at once: x (2x - y) + y (2y - x) = 2 (x^2 - x y + y^2), x = (ia|jb),
+// y = (ib|ja), over the common denominator.  Blocks take items blockIdx.x,
+// blockIdx.x + MP2_RB, ... so the order of every sum is fixed.
 __global__ void __launch_bounds__(256) mp2_pair_kernel(const double* __restrict__ M, int nv, int i,
                                                        const double* __restrict__ eo, const double* __restrict__ ev,
                                                        double* __restrict__ out) {
-  const int64_t ld = (int64_t)(i + 1) * nv;
-  const int64_t tot = ld * nv;
-  double s = 0.0;
-  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < tot;
-       idx += (int64_t)gridDim.x * blockDim.x) {
-    const int a = (int)(idx / ld);
-    const int64_t jb = idx % ld;
-    const int j = (int)(jb / nv), b = (int)(jb % nv);
-    const double t = M[(int64_t)a * ld + jb];
-    const double u = M[(int64_t)b * ld + (int64_t)j * nv + a];
-    const double w = j < i ? 2.0 : 1.0;
-    s += w * t * (2.0 * t - u) / (eo[i] + eo[j] - ev[a] - ev[b]);
-  }
+  __shared__ double X[MP2_T][MP2_T + 1], Y[MP2_T][MP2_T + 1];
   __shared__ double red[256];
+  const int nt = (nv + MP2_T - 1) / MP2_T;
+  const int64_t ntp = (int64_t)nt * (nt + 1) / 2;
+  const int64_t nwork = ntp * (i + 1);
+  const int64_t ld = (int64_t)(i + 1) * nv;
+  const double ei = eo[i];
+  double s = 0.0;
+  for (int64_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const int j = (int)(w / ntp);
+    const int tp = (int)(w % ntp);
+    int Bt = (int)((sqrt(8.0 * tp + 1.0) - 1.0) * 0.5);
+    while ((Bt + 1) * (Bt + 2) / 2 <= tp) ++Bt;
+    while (Bt * (Bt + 1) / 2 > tp) --Bt;
+    const int At = tp - Bt * (Bt + 1) / 2;  // At <= Bt
+    const int a0 = At * MP2_T, b0 = Bt * MP2_T;
+    const double* Mj = M + (int64_t)j * nv;
+    for (int e = threadIdx.x; e < MP2_T * MP2_T; e += blockDim.x) {
+      const int r = e / MP2_T, c = e % MP2_T;
+      X[r][c] = (a0 + r < nv && b0 + c < nv) ? Mj[(int64_t)(a0 + r) * ld + b0 + c] : 0.0;
+      if (At != Bt) Y[r][c] = (b0 + r < nv && a0 + c < nv) ? Mj[(int64_t)(b0 + r) * ld + a0 + c] : 0.0;
+    }
+    __syncthreads();
+    const double eij = ei + eo[j], wj = j < i ? 2.0 : 1.0;
+    for (int e = threadIdx.x; e < MP2_T * MP2_T; e += blockDim.x) {
+      const int r = e / MP2_T, c = e % MP2_T;
+      const int aa = a0 + r, bb = b0 + c;
+      if (aa < nv && bb < nv) {
+        const double d = eij - ev[aa] - ev[bb];
+        const double x = X[r][c];
+        if (At == Bt) {
+          const double y = X[c][r];
+          s += wj * x * (2.0 * x - y) / d;
+        } else {
+          const double y = Y[c][r];
+          s += wj * 2.0 * (x * x - x * y + y * y) / d;
+        }
+      }
+    }
+    __syncthreads();
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
