@@ -169,3 +169,54 @@ def test_not_positive_definite_metric_is_reported(dfx):
     with pytest.raises(dfx.DfxError) as e:
         dfx.eri3(sh, ax)
     assert e.value.code == dfx.ENOTPOSDEF
+
+
+def test_edge_zero_density_and_every_orbital_occupied(case, dfx):
+    """A zero density gives J = K = 0 exactly (no eigenvalue passes the
+    factorisation's threshold, no K launch); with every orbital occupied
+    (nocc = nbf, C orthogonal) J and K match the oracle to 1e-9."""
+    name, sh, ax, ref, B = case
+    bas, aux, Qab, QC, scr, raw, J2, L, Bref = ref
+    n = bas.nbf
+    J0, K0 = dfx.jk(B, torch.zeros((n, n), dtype=torch.float64, device="cuda"), kind=dfx.DENSITY)
+    assert torch.count_nonzero(J0).item() == 0 and torch.count_nonzero(K0).item() == 0
+    C = np.linalg.qr(np.random.default_rng(7).normal(size=(n, n)))[0]
+    Jr, Kr = O.jk(O.DF(bas, aux, scr, Bref, L), C=C)
+    Jg, Kg = dfx.jk(B, torch.tensor(C, device="cuda"))
+    assert np.abs(_np(Jg) - Jr).max() <= 1e-9 and np.abs(_np(Kg) - Kr).max() <= 1e-9
+
+
+def test_edge_empty_occupied_space_is_rejected(dfx):
+    sh, ax = SYSTEMS["h4"]()
+    B = dfx.eri3(sh, ax)
+    try:
+        C = torch.zeros((B.nbf, 1), dtype=torch.float64, device="cuda")
+        with pytest.raises(dfx.DfxError) as e:
+            dfx.jk(B, C, nocc=0)
+        assert e.value.code == dfx.EINVAL
+        with pytest.raises(dfx.DfxError):
+            dfx.jk(B, torch.zeros((B.nbf, B.nbf + 1), dtype=torch.float64, device="cuda"))
+    finally:
+        B.free()
+
+
+def test_edge_one_function_system(dfx):
+    """The smallest input: one s function and one auxiliary s function, a single
+    32-wide tile holding one element.  (00|P), B = (00|P)/sqrt((P|P)), J and K
+    against the oracle."""
+    sh = [systems.shell([0.0, 0.0, 0.0], 0, [0.8])]
+    ax = [systems.shell([0.0, 0.0, 0.3], 0, [1.7])]
+    bas, aux, Qab, QC, scr, raw, J2, L, Bref = _ref_df(sh, ax)
+    B = dfx.eri3(sh, ax, flags=dfx.KEEP_RAW | dfx.KEEP_METRIC)
+    try:
+        assert B.nbf == 1 and B.naux == 1
+        assert abs(_np(B.export(what=0))[0, 0] - Bref[0, 0]) <= 1e-13 * abs(Bref[0, 0])
+        C = np.ones((1, 1))
+        Jr, Kr = O.jk(O.DF(bas, aux, scr, Bref, L), C=C)
+        Jg, Kg = dfx.jk(B, torch.tensor(C, device="cuda"))
+        assert abs(_np(Jg)[0, 0] - Jr[0, 0]) <= 1e-13 * abs(Jr[0, 0])
+        assert abs(_np(Kg)[0, 0] - Kr[0, 0]) <= 1e-13 * abs(Kr[0, 0])
+        # one electron pair in one function: J = K
+        assert abs(Jr[0, 0] - Kr[0, 0]) <= 1e-14 * abs(Jr[0, 0])
+    finally:
+        B.free()
