@@ -98,3 +98,31 @@ def test_options_outside_uhf_raise(dfx):
     xyz, Z, sh, ax, _ = systems.h4()
     with pytest.raises(dfx.DfxError):
         dfx.uhf(xyz, Z, sh, ax, charge=1, multiplicity=2, schedule=dfx.SCHED_MIXED)
+
+
+def test_h2_triplet_single_determinant(dfx):
+    """Minimal-basis H2 triplet (tests/golden/h2_sto3g.json geometry and basis,
+    exact DF with the primitive-product auxiliary basis): both alpha electrons
+    fill the two-function space, so the UHF energy is that one determinant's,
+    sum_i h_ii + 1/2 sum_ij [(ii|jj) - (ij|ji)] + E_nn in any orthonormal basis,
+    from the oracle's four-index integrals."""
+    import json
+    import os
+    import scipy.linalg as sla
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "h2_sto3g.json")))
+    xyz = np.array([[0.0, 0.0, 0.0], [0.0, 0.0, g["R_bohr"]]])
+    prims = [(xyz[i], e) for i in range(2) for e in g["exps"]]
+    aux = [systems.shell((a * A + b * B) / (a + b), 0, [a + b])
+           for i, (A, a) in enumerate(prims) for (B, b) in prims[:i + 1]]
+    sh = [systems.shell(xyz[i], 0, g["exps"], g["coefs"]) for i in range(2)]
+    Z = np.array([1, 1], np.int32)
+    E, _, _, info = dfx.uhf(xyz, Z, sh, aux, multiplicity=3, tau=0.0, want_c=False, **CONV)
+    assert info["converged"]
+    bas = O.Basis(sh)
+    S, T, V = O.int1e(bas, xyz, Z)
+    Xs = sla.inv(sla.sqrtm(S)).real
+    h = Xs.T @ (T + V) @ Xs
+    Gm = np.einsum("mnls,mp,nq,lr,st->pqrt", O.eri4(bas), Xs, Xs, Xs, Xs)
+    Ed = sum(h[i, i] for i in range(2)) + 0.5 * sum(Gm[i, i, j, j] - Gm[i, j, j, i] for i in range(2)
+                                                    for j in range(2))
+    assert abs(E - (Ed + 1.0 / g["R_bohr"])) <= 1e-8   # exact fit up to kappa u, kappa = 2.8e7
