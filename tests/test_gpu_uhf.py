@@ -100,10 +100,12 @@ def test_options_outside_uhf_raise(dfx):
         dfx.uhf(xyz, Z, sh, ax, charge=1, multiplicity=2, schedule=dfx.SCHED_MIXED)
 
 
-def test_h2_triplet_single_determinant(dfx):
+@pytest.mark.parametrize("method", ["uhf", "rohf"])
+def test_h2_triplet_single_determinant(dfx, method):
     """Minimal-basis H2 triplet (tests/golden/h2_sto3g.json geometry and basis,
     exact DF with the primitive-product auxiliary basis): both alpha electrons
-    fill the two-function space, so the UHF energy is that one determinant's,
+    fill the two-function space, so the UHF and ROHF energies are that one
+    determinant's,
     sum_i h_ii + 1/2 sum_ij [(ii|jj) - (ij|ji)] + E_nn in any orthonormal basis,
     from the oracle's four-index integrals."""
     import json
@@ -116,7 +118,7 @@ def test_h2_triplet_single_determinant(dfx):
            for i, (A, a) in enumerate(prims) for (B, b) in prims[:i + 1]]
     sh = [systems.shell(xyz[i], 0, g["exps"], g["coefs"]) for i in range(2)]
     Z = np.array([1, 1], np.int32)
-    E, _, _, info = dfx.uhf(xyz, Z, sh, aux, multiplicity=3, tau=0.0, want_c=False, **CONV)
+    E, _, _, info = getattr(dfx, method)(xyz, Z, sh, aux, multiplicity=3, tau=0.0, want_c=False, **CONV)
     assert info["converged"]
     bas = O.Basis(sh)
     S, T, V = O.int1e(bas, xyz, Z)
