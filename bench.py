@@ -426,8 +426,8 @@ def main():
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build measures one GPU; run with --gpus 1 (the multi-GPU "
-                                   "sharding is a design, not a measured path)"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU; run with --gpus 1 (sharding the "
+                                   "auxiliary index over several GPUs is designed, not implemented)"}))
         sys.exit(2)
 
     import torch
