@@ -1,5 +1,5 @@
 /*
- * dfx -- density-fitted restricted Hartree-Fock hot path on AMD MI355X (gfx950).
+ * dfx -- density-fitted Hartree-Fock hot path on AMD MI355X (gfx950).
  *
  * C-ABI of libdfx.so.  Plain pointers and sizes only.  The operations follow
  * the paper (T. Shiozaki, "BAGEL: Brilliantly Advanced General
@@ -9,7 +9,9 @@
  *   - the density-fitting tensor operations of section "Density fitting
  *     utilities", Eqs. (1)-(3);
  *   - a DF-based restricted Hartree-Fock Fock builder (section "Standard
- *     algorithms").
+ *     algorithms"), and on the same fitted tensor the unrestricted and
+ *     restricted open-shell variants and the MP2 correlation energy that
+ *     section lists beside it.
  *
  * Conventions (all entry points):
  *   units       bohr and hartree.
