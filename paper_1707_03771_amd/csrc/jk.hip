@@ -34,30 +34,45 @@ __global__ void pack_density_kernel(const double* __restrict__ D, int nbf, doubl
   }
 }
 
-// gamma_Q = sum_c B[Q][c] d[c], B = hi + lo, FP64 accumulation, one workgroup per Q
+// gamma_Q = sum_c B[Q][c] d[c], B = hi + lo, FP64 accumulation.  A workgroup
+// takes JG_Q consecutive Q, so each element of d is fetched once per JG_Q rows
+// of B (d is as long as a row of B: read once per Q it doubled the kernel's
+// traffic).  Every Q keeps the same per-thread column order and tree, so the
+// result does not depend on JG_Q.
+constexpr int JG_Q = 4;
 __global__ void __launch_bounds__(256) j_gamma_kernel(const float* __restrict__ hi,
-                                                      const float* __restrict__ lo, int64_t ncols,
+                                                      const float* __restrict__ lo, int64_t ncols, int naux,
                                                       const double* __restrict__ d, double* gam) {
-  const int Q = blockIdx.x;
-  const float4* h4 = reinterpret_cast<const float4*>(hi + (int64_t)Q * ncols);
-  const float4* l4 = reinterpret_cast<const float4*>(lo + (int64_t)Q * ncols);
+  const int Q0 = blockIdx.x * JG_Q;
+  const int nq = min(JG_Q, naux - Q0);
   const double4* d4 = reinterpret_cast<const double4*>(d);
   const int64_t n4 = ncols >> 2;
-  double s = 0.0;
+  double s[JG_Q];
+#pragma unroll
+  for (int k = 0; k < JG_Q; ++k) s[k] = 0.0;
   for (int64_t i = threadIdx.x; i < n4; i += blockDim.x) {
-    const float4 h = h4[i], l = l4[i];
     const double4 dd = d4[i];
-    s += ((double)h.x + (double)l.x) * dd.x + ((double)h.y + (double)l.y) * dd.y +
-         ((double)h.z + (double)l.z) * dd.z + ((double)h.w + (double)l.w) * dd.w;
+#pragma unroll
+    for (int k = 0; k < JG_Q; ++k) {
+      if (k < nq) {
+        const float4 h = reinterpret_cast<const float4*>(hi + (int64_t)(Q0 + k) * ncols)[i];
+        const float4 l = reinterpret_cast<const float4*>(lo + (int64_t)(Q0 + k) * ncols)[i];
+        s[k] += ((double)h.x + (double)l.x) * dd.x + ((double)h.y + (double)l.y) * dd.y +
+                ((double)h.z + (double)l.z) * dd.z + ((double)h.w + (double)l.w) * dd.w;
+      }
+    }
   }
-  __shared__ double red[256];
-  red[threadIdx.x] = s;
+  __shared__ double red[JG_Q][256];
+#pragma unroll
+  for (int k = 0; k < JG_Q; ++k) red[k][threadIdx.x] = s[k];
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
-    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    if (threadIdx.x < o)
+#pragma unroll
+      for (int k = 0; k < JG_Q; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0) gam[Q] = red[0];
+  if (threadIdx.x < nq) gam[Q0 + threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Jvec[c] = sum_Q B[Q][c] gamma_Q, B = hi + lo, four columns per thread, fixed Q order
@@ -104,7 +119,8 @@ void j_build(const JKArgs& a, const double* D, double* J, double* work, hipStrea
   // both words of B in every precision: J is bandwidth-bound, and with the hi
   // word alone its error (amplified by the conditioning of the metric) exceeds
   // that of a reduced-precision K
-  hipLaunchKernelGGL(j_gamma_kernel, dim3(a.naux), dim3(256), 0, st, a.hi, a.lo, a.ncols, dvec, gam);
+  hipLaunchKernelGGL(j_gamma_kernel, dim3((a.naux + JG_Q - 1) / JG_Q), dim3(256), 0, st, a.hi, a.lo, a.ncols, a.naux,
+                     dvec, gam);
   const unsigned gb = (unsigned)(((a.ncols >> 2) + 255) / 256);
   hipLaunchKernelGGL(j_back_kernel, dim3(gb), dim3(256), 0, st, a.hi, a.lo, a.ncols, a.naux, gam, jv);
   const int64_t n2 = (int64_t)a.nbf * a.nbf;
