@@ -295,6 +295,7 @@ struct Scf {
   rocblas_handle rb{};
   int n = 0, m = 0, nocc = 0;
   DevMem part, eig_e, eig_info, gw;  // gw: split-K partial products
+  DevMem qr_linv, qr_work, qr_z, qr_info;  // Cholesky QR of the purified occupied space
   std::vector<double> hpart;
   EventSpans* eig_spans = nullptr;
   int verbose = 0;
@@ -334,7 +335,8 @@ struct Scf {
   // Gershgorin bounds, then P <- P^2 or 2P - P^2, whichever moves tr P toward
   // nocc, until sum lambda (1 - lambda) = tr P - tr P^2 < 1e-9 nocc, plus three
   // more steps.  The projector times the previous occupied orbitals Y, put
-  // through a Cholesky QR twice, is the new Y (m x nocc, orthonormal columns).
+  // through a Cholesky QR twice (the library's blocked Cholesky and L^-1, no
+  // vendor solver), is the new Y (m x nocc, orthonormal columns).
   // P and P2 are m x m work, Z m x nocc, G nocc x nocc, lohi 2m.  Returns false,
   // Y unchanged, if the iteration does not settle in 100 steps, the trace
   // misses nocc, or Z = P Y is too ill-conditioned (a Cholesky pivot below
@@ -372,26 +374,31 @@ struct Scf {
         hipLaunchKernelGGL(tc2_raise_kernel, dim3(nblk(mm)), dim3(256), 0, st, P, P2, mm);
     }
     if (!ok) return false;
-    gemm(m, nocc, m, P, m, false, Y, nocc, false, Z, nocc);  // Z = P Y
+    // Cholesky QR, twice, with the library's own factorisation: G = Z^T Z = L L^T,
+    // Z <- Z L^-T (then Z^T Z = L^-1 G L^-T = I)
+    const size_t mo = (size_t)m * nocc;
+    if (qr_linv.n < sizeof(double) * (size_t)nocc * nocc) qr_linv.alloc(sizeof(double) * (size_t)nocc * nocc);
+    if (qr_work.n < sizeof(double) * cholesky_work_elems(nocc))
+      qr_work.alloc(sizeof(double) * cholesky_work_elems(nocc));
+    if (qr_z.n < sizeof(double) * mo) qr_z.alloc(sizeof(double) * mo);
+    if (!qr_info.p) qr_info.alloc(sizeof(int));
+    double* Zc = Z;
+    double* Zn = qr_z.as<double>();
+    gemm(m, nocc, m, P, m, false, Y, nocc, false, Zc, nocc);  // Z = P Y
     for (int pass = 0; pass < 2; ++pass) {
-      gemm(nocc, nocc, m, Z, nocc, true, Z, nocc, false, G, nocc);  // G = Z^T Z = U^T U
-      if (rocsolver_dpotrf(rb, rocblas_fill_upper, nocc, G, nocc, eig_info.as<rocblas_int>()) !=
-          rocblas_status_success)
-        return false;
-      hipLaunchKernelGGL(diag_minmax_kernel, dim3(1), dim3(256), 0, st, G, nocc, part.as<double>());
+      gemm(nocc, nocc, m, Zc, nocc, true, Zc, nocc, false, G, nocc);  // G = Z^T Z
+      cholesky_inverse(G, nocc, qr_linv.as<double>(), qr_work.as<double>(), qr_info.as<int>(), st);
+      hipLaunchKernelGGL(diag_minmax_kernel, dim3(1), dim3(256), 0, st, G, nocc, part.as<double>());  // diag of L
       int info = 0;
-      DFX_HIP(hipMemcpyAsync(&info, eig_info.p, sizeof(int), hipMemcpyDeviceToHost, st));
+      DFX_HIP(hipMemcpyAsync(&info, qr_info.p, sizeof(int), hipMemcpyDeviceToHost, st));
       DFX_HIP(hipMemcpyAsync(b, part.p, sizeof b, hipMemcpyDeviceToHost, st));
       DFX_HIP(hipStreamSynchronize(st));
       why = "Cholesky QR";
       if (info != 0 || !(b[0] > 1e-4 * b[1])) return false;
-      // Z <- Z U^-1: in column-major terms Z^T <- U^-T Z^T
-      const double one = 1.0;
-      if (rocblas_dtrsm(rb, rocblas_side_left, rocblas_fill_upper, rocblas_operation_transpose,
-                        rocblas_diagonal_non_unit, nocc, m, &one, G, nocc, Z, nocc) != rocblas_status_success)
-        return false;
+      gemm(m, nocc, nocc, Zc, nocc, false, qr_linv.as<double>(), nocc, true, Zn, nocc);  // Z L^-T
+      std::swap(Zc, Zn);
     }
-    DFX_HIP(hipMemcpyAsync(Y, Z, sizeof(double) * (size_t)m * nocc, hipMemcpyDeviceToDevice, st));
+    DFX_HIP(hipMemcpyAsync(Y, Zc, sizeof(double) * mo, hipMemcpyDeviceToDevice, st));
     return true;
   }
   // symmetric eigen-decomposition in place: A (k x k) -> rows are eigenvectors, w ascending
