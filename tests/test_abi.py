@@ -84,3 +84,31 @@ def test_eri3_plan_sizes_host_only():
     with pytest.raises(dfx.DfxError) as e:
         dfx.eri3_plan(bad, ax)
     assert e.value.code == dfx.EUNSUPPORTED
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdfx.so not built")
+def test_open_shell_and_mp2_argument_errors_before_device_work():
+    """dfx_uhf / dfx_rohf / dfx_scf / dfx_mp2 validate their arguments before any
+    HIP call: NULL pointers, a multiplicity whose parity does not match the
+    electron count or that exceeds it, a negative level shift, a level shift
+    given to RHF, options the open-shell drivers do not support."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import systems
+    import paper_1707_03771_amd as dfx
+    lib = dfx._lib
+    E = ctypes.c_double()
+    assert lib.dfx_uhf(None, None, 0, None, 0, None, 1, ctypes.byref(E), None, None, None) == dfx.EINVAL
+    assert lib.dfx_rohf(None, None, 0, None, 0, None, 1, ctypes.byref(E), None, None, None) == dfx.EINVAL
+    assert lib.dfx_mp2(None, None, 1, None, 1, 0, ctypes.byref(E), None) == dfx.EINVAL
+    xyz, Z, sh, ax, _ = systems.h4()                   # 4 electrons
+    for fn in (dfx.uhf, dfx.rohf):
+        for kw in (dict(multiplicity=2), dict(multiplicity=6), dict(multiplicity=0),
+                   dict(multiplicity=1, level_shift=-0.5), dict(multiplicity=1, schedule=dfx.SCHED_MIXED),
+                   dict(multiplicity=1, guess=dfx.GUESS_DENSITY)):
+            with pytest.raises(dfx.DfxError) as e:
+                fn(xyz, Z, sh, ax, want_c=False, **kw)
+            assert e.value.code == dfx.EINVAL, kw
+    with pytest.raises(dfx.DfxError) as e:
+        dfx.scf(xyz, Z, sh, ax, want_c=False, level_shift=0.3)
+    assert e.value.code == dfx.EINVAL and "level_shift" in dfx.last_error()
