@@ -43,8 +43,9 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRSM_LABEL = "B transform block updates R_i -= L_i,<i B_<i (dgemm_kernel EPI_SUB)"
 TRAFFIC_PROFILES = {"K half-transform X_Q = B_Q C, FP64": "kx64_water64_pmc.txt",
-                    "trsm_split (B = L^-1 raw)": "trsm_water64_pmc.txt"}
+                    TRSM_LABEL: "trsm_update_water64_pmc.txt"}
 
 
 def measured_traffic(kernel_label):
@@ -76,8 +77,10 @@ def roofline(info, nbf, naux, nocc):
     timings the library reports per kernel and precision: algorithmic FLOPs per
     launch / average launch time, against the peak of the precision used."""
     peaks = {0: ("FP64", PEAK_FP64), 1: ("FP32", PEAK_FP32_MFMA), 2: ("BF16", PEAK_BF16_MFMA)}
-    cands = {"trsm_split (B = L^-1 raw), FP64 MFMA":
-             (info["t_trsm"], naux * (naux + 1.0) * info["ncols"], 1, PEAK_FP64)}
+    # the B transform's block updates (the substitution's MFMA products): their
+    # FLOPs as the library counts them, 2 M K N per launch, and their own GPU time
+    cands = {f"{TRSM_LABEL}, FP64 MFMA":
+             (info["t_trsm_update"], info["trsm_update_flops"], info["n_trsm_update"], PEAK_FP64)}
     for p, (pname, peak) in peaks.items():
         nj = info["n_jk_p"][p]
         nl = info["n_kx_launch_p"][p]
@@ -101,11 +104,23 @@ def roofline(info, nbf, naux, nocc):
                         "frac": round(v[1] / v[0] / v[3], 4) if v[0] > 0 else None} for k, v in cands.items()}}
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(elems, xyz, sh, ax, niter, budget_pairs=250, q_rows=16, seed=0):
     """The oracle, timed on bounded samples of the same workload and scaled to
-    one full DF-RHF: ERIs over a random sample of shell pairs, the fit on their
-    columns, J/K on a sample of aux rows times the GPU's iteration count, and
-    the dense eigen/matrix work of one iteration times the iteration count."""
+    one full DF-RHF (an extrapolation, not a run): ERIs over a random sample of
+    shell pairs, the fit on their columns, J/K on a sample of aux rows times
+    niter (the iteration count of the plain FP64 schedule from the core guess,
+    which is what the oracle runs), and the dense eigen/matrix work of one
+    iteration times niter."""
     import oracle as O
     import scipy.linalg as sla
     import threadpoolctl  # noqa: F401  (BLAS threads = cores)
@@ -155,9 +170,11 @@ def cpu_baseline(elems, xyz, sh, ax, niter, budget_pairs=250, q_rows=16, seed=0)
     del e, w, D
     total = sum(t_all.values())
     return {"value": total, "unit": "s", "cores": os.cpu_count(), "kind": "oracle",
-            "sample": (f"oracle on the same workload: ERIs of {len(pick)} random shell pairs of {npairs} "
-                       f"(scaled), metric + Cholesky in full, triangular solve on their columns (scaled), "
-                       f"J/K on {q_rows} of {aux.nbf} aux rows (scaled) x {niter} iterations, one iteration's "
+            "extrapolated": True, "cpu_model": cpu_model(),
+            "sample": (f"estimate, extrapolated from bounded samples of the oracle on the same workload: ERIs "
+                       f"of {len(pick)} random shell pairs of {npairs} (scaled), metric + Cholesky in full, "
+                       f"triangular solve on their columns (scaled), J/K on {q_rows} of {aux.nbf} aux rows "
+                       f"(scaled) x {niter} iterations (plain FP64 from the core guess), one iteration's "
                        f"dense eigen/matrix work x {niter}"),
             "phases_s": {k: round(v, 3) for k, v in t_all.items()}}
 
@@ -478,6 +495,7 @@ def main():
         dt = time.perf_counter() - t0
         log(f"{tag}: E = {E:.10f}  iters {info['niter']} (mixed {info['n_mixed']})  "
             f"wall {dt:.2f} s  guess {info['t_guess']:.3f} eri {info['t_eri']:.3f} trsm {info['t_trsm']:.3f} "
+            f"(updates {info['t_trsm_update']:.3f}) "
             f"j {info['t_j']:.3f} kx {info['t_kx']:.3f} ksyrk {info['t_ksyrk']:.3f} eig {info['t_eig']:.3f}")
         pn = {0: "d", 1: "s", 2: "b"}
         log("   history: " + " ".join(f"{pn.get(p, '?')}{e:.1e}" for p, e in zip(info["prec_hist"], info["err_hist"])))
@@ -495,7 +513,10 @@ def main():
     res = [step(f"step {k}", k, **gk) for k in range(a.steps)]
     torch.cuda.synchronize()
     T = (time.perf_counter() - t0) / max(1, a.steps)
-    E, info, _ = res[-1]
+    walls = [r[2] for r in res]
+    # the roofline and the reported phases come from the step of median wall time
+    k_med = int(np.argsort(walls)[(len(walls) - 1) // 2])
+    E, info, _ = res[k_med]
     k_last = a.steps - 1
 
     context = None
@@ -517,6 +538,9 @@ def main():
         "steps": a.steps,
         "warmup": a.warmup,
         "ms_per_step": round(1e3 * T, 2),
+        "step_wall_s": {"mean": round(float(np.mean(walls)), 4), "median": round(float(np.median(walls)), 4),
+                        "min": round(float(np.min(walls)), 4), "max": round(float(np.max(walls)), 4),
+                        "median_step": k_med},
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
@@ -535,13 +559,13 @@ def main():
         "context_core_guess": context,
         "eri_per_s": info["nintegrals"] / info["t_eri"] if info["t_eri"] > 0 else None,
         "phases_s": {k: round(info[k], 4) for k in ("t_setup", "t_scf", "t_eri", "t_metric", "t_trsm",
-                                                     "t_j", "t_kx", "t_ksyrk", "t_eig")},
+                                                     "t_trsm_update", "t_j", "t_kx", "t_ksyrk", "t_eig")},
         "roofline": roofline(info, nbf, naux, nocc),
         "plain_fp64": plain,
     }
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle on samples) ...")
-        out["cpu_baseline"] = cpu_baseline(elems, xyz, sh, ax, info["niter"])
+        out["cpu_baseline"] = cpu_baseline(elems, xyz, sh, ax, plain["niter"] if plain else info["niter"])
     print(json.dumps(out))
 
 

@@ -28,9 +28,18 @@
  *   errors      every call returns 0 (DFX_OK) or a negative DFX_E* code;
  *               dfx_last_error() returns the message of the calling thread's
  *               last failure.  No C++ exception crosses this boundary.
- *   ownership   device pointers passed in are owned by the caller and never
- *               freed by the library.  A dfx_B owns the device memory it
- *               allocates (B, pair lists, metric) until dfx_B_free.
+ *   ownership   device memory is the caller's.  Device pointers passed in are
+ *               never freed by the library.  dfx_eri3 builds B inside a
+ *               workspace the caller allocates (sized by dfx_eri3_plan); the
+ *               dfx_B handle only describes it and draws dfx_jk's work from the
+ *               same workspace, so the library allocates no device memory for
+ *               them.  dfx_scf / dfx_uhf / dfx_rohf do the same with
+ *               dfx_scf_opts.workspace (sized by dfx_scf_plan); without one
+ *               they allocate per call.  The remaining entry points
+ *               (dfx_mp2, dfx_lowdin, dfx_int1e, dfx_metric, dfx_cholesky, the
+ *               learned guess) allocate their own scratch and free it before
+ *               returning, except a guess model's weights, which it holds
+ *               until dfx_guess_free.
  */
 #ifndef DFX_H
 #define DFX_H
@@ -97,8 +106,11 @@ typedef struct {
   int64_t nintegrals;    /* unique evaluated integrals: sum over triplets of n_a n_b n_C (a > b), n_a (n_a + 1)/2 n_C (a = b) */
   double eri_seconds;    /* GPU time of the three-index ERI kernels */
   double metric_seconds; /* metric + Cholesky + inverse */
-  double trsm_seconds;   /* B = L^-1 raw with FP32 split */
+  double trsm_seconds;   /* B = L^-1 raw (blocked forward substitution) with the FP32 split */
   double kappa_lb;       /* lower bound (max L_ii / min L_ii)^2 of cond(J_PQ) */
+  double trsm_update_seconds;  /* the substitution's block updates R_i -= L_i,<i B_<i alone */
+  double trsm_update_flops;    /* their FLOPs, 2 M K N summed */
+  int32_t trsm_update_launches;
 } dfx_B_info;
 
 /*
@@ -109,36 +121,49 @@ typedef struct {
  *
  *   shells/nsh, aux/nauxsh   orbital and auxiliary shells (host)
  *   opts                     may be NULL (tau = 1e-12, flags = 0)
+ *   dev_workspace, ws_bytes  device memory owned by the caller, at least
+ *                            dfx_eri3_plan's bytes_workspace for the same
+ *                            shells and flags; any alignment.  It must stay
+ *                            allocated and untouched until dfx_B_free: B, the
+ *                            setup's scratch and dfx_jk's work all live in it,
+ *                            and the library allocates no device memory for
+ *                            them.  The call checks the size before any device
+ *                            work: smaller -> DFX_ENOMEM, nothing written.
  *   stream                   hipStream_t; the call synchronises it
  *   out                      receives a new handle (free with dfx_B_free)
  *
  * Screening: Q_ab = sqrt(max_{mu in a, nu in b} (mu nu|mu nu)), Q_C =
  * sqrt(max_{P in C} (P|P)); pair a >= b kept iff Q_ab max_C Q_C >= tau; its
  * block with C evaluated iff Q_ab Q_C >= tau, else zero.
- * Errors: DFX_EINVAL, DFX_EUNSUPPORTED, DFX_ENOTPOSDEF (no handle returned),
- * DFX_ENOMEM, DFX_EHIP.
+ * Errors: DFX_EINVAL (also a NULL workspace), DFX_EUNSUPPORTED, DFX_ENOTPOSDEF
+ * (no handle returned), DFX_ENOMEM, DFX_EHIP.
  */
-int dfx_eri3(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
-             const dfx_eri3_opts* opts, void* stream, dfx_B** out);
+int dfx_eri3(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh, const dfx_eri3_opts* opts,
+             void* dev_workspace, size_t ws_bytes, void* stream, dfx_B** out);
 
 int dfx_B_info_get(const dfx_B* b, dfx_B_info* info);
 
 /*
- * dfx_eri3_plan -- sizes of dfx_eri3's device memory, host only (no GPU
- * work): function counts and the bytes of B (hi + lo over the packed 32x32
- * tile layout, independent of screening), of the raw integrals held during
- * setup, and of the metric, its factor and inverse.  Errors as dfx_eri3.
+ * dfx_eri3_plan -- the workspace dfx_eri3 needs, host only (no GPU work, no
+ * screening): function counts and upper bounds in bytes.  opts may be NULL
+ * (its flags matter: kept raw integrals or metric stay in the workspace).
+ * Errors as dfx_eri3.
  */
 typedef struct {
   int32_t nbf, naux;
   int64_t ncols_tiled;      /* storage columns of B */
-  int64_t bytes_B;          /* kept until dfx_B_free */
-  int64_t bytes_raw;        /* setup only: an upper bound, the raw integrals occupy the
-                               kept packed pair columns (at most the tiled count) */
-  int64_t bytes_metric;     /* setup only: J_PQ, L, L^-1 */
-  int64_t bytes_setup_peak; /* B + raw + metric */
+  int64_t bytes_B;          /* B's two FP32 words over the packed 32x32 tile layout */
+  int64_t bytes_raw;        /* raw integrals during setup, as if no pair were screened */
+  int64_t bytes_metric;     /* J_PQ and L during setup */
+  int64_t bytes_persistent; /* in use from dfx_eri3's return until dfx_B_free: shells,
+                               B, the metric's slot, kept metric / raw */
+  int64_t bytes_jk;         /* the largest work of dfx_jk on this B (any kind,
+                               precision, nocc <= 512) */
+  int64_t bytes_workspace;  /* what to pass to dfx_eri3: persistent + the larger of
+                               the setup scratch and dfx_jk's work, plus slack */
 } dfx_eri3_sizes;
-int dfx_eri3_plan(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh, dfx_eri3_sizes* out);
+int dfx_eri3_plan(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh, const dfx_eri3_opts* opts,
+                  dfx_eri3_sizes* out);
 
 /*
  * dfx_B_unpack -- rows q0..q1-1 of B as dense symmetric matrices,
@@ -213,7 +238,6 @@ int dfx_mp2(const dfx_B* b, const double* dev_C, int nmo, const double* eps, int
             void* stream);
 
 /*
- * dfx_int1e -- overlap S, kinetic T and nuclear attraction/*
  * dfx_int1e -- overlap S, kinetic T and nuclear attraction
  * V = -sum_A Z_A <mu| 1/|r - R_A| |nu> (device outputs, nbf x nbf).
  */
@@ -283,6 +307,15 @@ typedef struct {
                             density at self-consistency, so it moves the path, not the
                             converged state; the DIIS error is that of the unshifted matrices.
                             0 (default): none */
+  void* workspace;       /* device memory owned by the caller (NULL, the default: the call
+                            allocates its own): at least dfx_scf_plan's bytes, any alignment.
+                            Every device buffer of the call (B, the one-electron matrices,
+                            the DIIS history, J/K work) lives in it; the library allocates
+                            no device memory then, apart from a rocBLAS handle's scratch
+                            that the calling thread keeps for the process.  Read and
+                            written only during the call.  Too small: DFX_ENOMEM before
+                            any device work */
+  size_t ws_bytes;
 } dfx_scf_opts;
 
 #define DFX_MAXHIST 256
@@ -326,9 +359,21 @@ typedef struct {
   int32_t n_purified;    /* occupied-space updates by purification */
   int32_t n_eigh;        /* occupied-space updates by dsyevd (the final C/eps solve excluded) */
   int32_t purify_steps;  /* purification steps (matrix squarings) over all updates */
+  double t_trsm_update;  /* the B transform's block update products alone (inside t_trsm) */
+  double trsm_update_flops;
+  int32_t n_trsm_update; /* their launches */
 } dfx_scf_info;
 
 void dfx_scf_default_opts(dfx_scf_opts* o);
+
+/*
+ * dfx_scf_plan -- bytes of dfx_scf_opts.workspace for dfx_scf, dfx_uhf or
+ * dfx_rohf on these shells (an upper bound; host only).  natom: atoms of the
+ * geometry (the learned guess's inputs scale with the atom pairs); opts may be
+ * NULL (defaults; only diis_size matters).
+ */
+int dfx_scf_plan(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh, int natom,
+                 const dfx_scf_opts* opts, int64_t* bytes);
 
 /*
  * dfx_scf -- DF-RHF: D = C_occ C_occ^T, F = h + 2J - K, E = tr D (h + F) + E_nn,

@@ -4,7 +4,7 @@ Thin Python binding over the C-ABI of ``libdfx.so`` (include/dfx.h).  Every
 step of the computation runs in the library's HIP kernels; this module only
 marshals arguments.  PyTorch supplies device memory and the current stream.
 Importing fails loudly if the library has not been built
-(``python -m paper_1707_03771_amd.build``).
+(``python paper_1707_03771_amd/build.py``).
 """
 from __future__ import annotations
 
@@ -17,7 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdfx.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1707_03771_amd.build`")
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python paper_1707_03771_amd/build.py`")
 
 # torch first: its HIP runtime is then the one libdfx.so binds to (same soname).
 # Loaded the other way round, the process holds two HIP/HSA runtimes and torch's
@@ -62,7 +62,8 @@ class BInfo(ctypes.Structure):
                 ("ncols_tiled", ctypes.c_int64), ("ntriplets", ctypes.c_int64),
                 ("nintegrals", ctypes.c_int64), ("eri_seconds", ctypes.c_double),
                 ("metric_seconds", ctypes.c_double), ("trsm_seconds", ctypes.c_double),
-                ("kappa_lb", ctypes.c_double)]
+                ("kappa_lb", ctypes.c_double), ("trsm_update_seconds", ctypes.c_double),
+                ("trsm_update_flops", ctypes.c_double), ("trsm_update_launches", ctypes.c_int32)]
 
 
 class ScfOpts(ctypes.Structure):
@@ -71,7 +72,7 @@ class ScfOpts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("diis_size", ctypes.c_int32), ("schedule", ctypes.c_int32),
                 ("mixed_prec", ctypes.c_int32), ("guess", ctypes.c_int32), ("verbose", ctypes.c_int32),
                 ("model", ctypes.c_void_p), ("switch_auto", ctypes.c_int32), ("purify", ctypes.c_int32),
-                ("level_shift", ctypes.c_double)]
+                ("level_shift", ctypes.c_double), ("workspace", ctypes.c_void_p), ("ws_bytes", ctypes.c_size_t)]
 
 
 class ScfInfo(ctypes.Structure):
@@ -88,13 +89,16 @@ class ScfInfo(ctypes.Structure):
                 ("E_hist", ctypes.c_double * MAXHIST), ("err_hist", ctypes.c_double * MAXHIST),
                 ("prec_hist", ctypes.c_int8 * MAXHIST), ("t_guess", ctypes.c_double),
                 ("floor_est", ctypes.c_double * 3), ("guess_fallback", ctypes.c_int32),
-                ("n_purified", ctypes.c_int32), ("n_eigh", ctypes.c_int32), ("purify_steps", ctypes.c_int32)]
+                ("n_purified", ctypes.c_int32), ("n_eigh", ctypes.c_int32), ("purify_steps", ctypes.c_int32),
+                ("t_trsm_update", ctypes.c_double), ("trsm_update_flops", ctypes.c_double),
+                ("n_trsm_update", ctypes.c_int32)]
 
 
 class Eri3Sizes(ctypes.Structure):
     _fields_ = [("nbf", ctypes.c_int32), ("naux", ctypes.c_int32), ("ncols_tiled", ctypes.c_int64),
                 ("bytes_B", ctypes.c_int64), ("bytes_raw", ctypes.c_int64), ("bytes_metric", ctypes.c_int64),
-                ("bytes_setup_peak", ctypes.c_int64)]
+                ("bytes_persistent", ctypes.c_int64), ("bytes_jk", ctypes.c_int64),
+                ("bytes_workspace", ctypes.c_int64)]
 
 
 class GuessSpec(ctypes.Structure):
@@ -106,7 +110,7 @@ class GuessSpec(ctypes.Structure):
 
 _vp, _i, _d = ctypes.c_void_p, ctypes.c_int, ctypes.c_double
 _SIGS = {
-    "dfx_eri3": [_vp, _i, _vp, _i, _vp, _vp, _vp],
+    "dfx_eri3": [_vp, _i, _vp, _i, _vp, _vp, ctypes.c_size_t, _vp, _vp],
     "dfx_B_info_get": [_vp, _vp],
     "dfx_B_lists": [_vp, _vp, _vp, _vp, _vp, _vp],
     "dfx_B_export": [_vp, _i, _i, _i, _vp, _vp],
@@ -128,7 +132,8 @@ _SIGS = {
     "dfx_guess_predict": [_vp, _vp, _vp],
     "dfx_guess_info": [_vp, _vp, _vp],
     "dfx_guess_export": [_vp, _i, _vp, _vp, _vp, _vp, _vp],
-    "dfx_eri3_plan": [_vp, _i, _vp, _i, _vp],
+    "dfx_eri3_plan": [_vp, _i, _vp, _i, _vp, _vp],
+    "dfx_scf_plan": [_vp, _i, _vp, _i, _i, _vp, _vp],
     "dfx_B_unpack": [_vp, _i, _i, _vp, _vp],
     "dfx_lowdin": [_vp, _vp, _i, _vp, _vp, _vp],
     "dfx_guess_samples": [_vp, _i, _vp, _vp],
@@ -197,10 +202,13 @@ class _GeomC:
 
 
 class DFTensor:
-    """Owns a dfx_B handle: the fitted three-index tensor resident in HBM."""
+    """Owns a dfx_B handle (the fitted three-index tensor resident in HBM) and
+    the torch tensor that is its workspace: B and dfx_jk's work live in that
+    memory, which is released only after the handle is freed."""
 
-    def __init__(self, handle):
+    def __init__(self, handle, workspace=None):
         self.h = handle
+        self.ws = workspace
         inf = BInfo()
         _check(_lib.dfx_B_info_get(self.h, ctypes.byref(inf)))
         self.info = {k: getattr(inf, k) for k, _ in BInfo._fields_}
@@ -243,6 +251,7 @@ class DFTensor:
         if self.h:
             _check(_lib.dfx_B_free(self.h))
             self.h = None
+        self.ws = None
 
     def __del__(self):
         try:
@@ -251,21 +260,27 @@ class DFTensor:
             pass
 
 
-def eri3_plan(shells, aux):
-    """dfx_eri3_plan: device-memory sizes of dfx_eri3 (host only)."""
+def eri3_plan(shells, aux, flags=0):
+    """dfx_eri3_plan: the workspace dfx_eri3 needs, in bytes (host only)."""
     s, a = _ShellArray(shells), _ShellArray(aux)
     z = Eri3Sizes()
-    _check(_lib.dfx_eri3_plan(s.arr, s.n, a.arr, a.n, ctypes.byref(z)))
+    _check(_lib.dfx_eri3_plan(s.arr, s.n, a.arr, a.n, ctypes.byref(Eri3Opts(1e-12, flags)), ctypes.byref(z)))
     return {k: getattr(z, k) for k, _ in Eri3Sizes._fields_}
 
 
-def eri3(shells, aux, tau=1e-12, flags=0, stream=None):
-    """dfx_eri3: Rys (mu nu|P), metric, Cholesky and B = L^-1 (mu nu|P) in HBM."""
+def eri3(shells, aux, tau=1e-12, flags=0, stream=None, workspace=None):
+    """dfx_eri3: Rys (mu nu|P), metric, Cholesky and B = L^-1 (mu nu|P) in HBM,
+    inside a workspace torch allocates (dfx_eri3_plan's size) unless one is
+    given (a uint8 cuda tensor)."""
+    import torch
     s, a = _ShellArray(shells), _ShellArray(aux)
+    if workspace is None:
+        need = eri3_plan(shells, aux, flags)["bytes_workspace"]
+        workspace = torch.empty(need, dtype=torch.uint8, device="cuda")
     h = ctypes.c_void_p()
-    _check(_lib.dfx_eri3(s.arr, s.n, a.arr, a.n, ctypes.byref(Eri3Opts(tau, flags)), _stream(stream),
-                         ctypes.byref(h)))
-    return DFTensor(h)
+    _check(_lib.dfx_eri3(s.arr, s.n, a.arr, a.n, ctypes.byref(Eri3Opts(tau, flags)), _ptr(workspace),
+                         workspace.numel() * workspace.element_size(), _stream(stream), ctypes.byref(h)))
+    return DFTensor(h, workspace)
 
 
 def jk(B, x, kind=COCC, nocc=None, precision=FP64, want_j=True, want_k=True, stream=None):
@@ -334,6 +349,43 @@ def scf_default_opts():
     return o
 
 
+def scf_plan(shells, aux, natom, diis_size=8):
+    """dfx_scf_plan: bytes of the SCF workspace for these shells (host only)."""
+    s, a = _ShellArray(shells), _ShellArray(aux)
+    o = scf_default_opts()
+    o.diis_size = diis_size
+    b = ctypes.c_int64()
+    _check(_lib.dfx_scf_plan(s.arr, s.n, a.arr, a.n, int(natom), ctypes.byref(o), ctypes.byref(b)))
+    return b.value
+
+
+# One SCF workspace per device, reused by every dfx_scf / dfx_uhf / dfx_rohf
+# call from this module (the calls are synchronous, so one buffer serves them
+# in turn) and grown when a larger system needs more.
+_SCF_WS = {}
+
+
+def _scf_workspace(o, shells, aux, natom):
+    import torch
+    if not torch.cuda.is_available():
+        return None  # the library then reports the missing device itself
+    need = scf_plan(shells, aux, natom, o.diis_size)
+    dev = torch.cuda.current_device()
+    ws = _SCF_WS.get(dev)
+    if ws is None or ws.numel() < need:
+        _SCF_WS.pop(dev, None)
+        ws = torch.empty(need, dtype=torch.uint8, device=f"cuda:{dev}")
+        _SCF_WS[dev] = ws
+    o.workspace = ws.data_ptr()
+    o.ws_bytes = ws.numel()
+    return ws
+
+
+def release_scf_workspace():
+    """Drop the cached SCF workspaces (their memory returns to torch's allocator)."""
+    _SCF_WS.clear()
+
+
 def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, model=None, **opts):
     """dfx_scf: DF-RHF.  Returns (E, C, eps, info dict); C and eps are numpy arrays
     (None with want_c=False).  With a GuessModel, the start is its predicted density (guess = GUESS_LEARNED)."""
@@ -347,6 +399,7 @@ def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, model=None, **opt
         o.guess = GUESS_LEARNED
     s, a = _ShellArray(shells), _ShellArray(aux)
     g = _GeomC(xyz, Z, charge)
+    ws = _scf_workspace(o, shells, aux, len(g.Z)) if not o.workspace else None  # noqa: F841 (kept alive)
     n = sum(2 * int(q["l"]) + 1 for q in shells)
     E = ctypes.c_double()
     C = np.zeros((n, n)) if want_c else None
@@ -379,6 +432,7 @@ def _open_shell(fn, nset, xyz, Z, shells, aux, charge, multiplicity, want_c, opt
         setattr(o, k, v)
     s, a = _ShellArray(shells), _ShellArray(aux)
     g = _GeomC(xyz, Z, charge)
+    ws = _scf_workspace(o, shells, aux, len(g.Z)) if not o.workspace else None  # noqa: F841 (kept alive)
     n = sum(2 * int(q["l"]) + 1 for q in shells)
     E = ctypes.c_double()
     C = np.zeros((nset, n, n)) if want_c else None

@@ -1,6 +1,6 @@
 """Build libdfx.so for gfx950 from csrc/ (HIP kernels + C-ABI host code).
 
-    python -m paper_1707_03771_amd.build [--force] [-j N]
+    python paper_1707_03771_amd/build.py [--force] [-j N]
 
 Objects go to <repo>/_build/, the library to paper_1707_03771_amd/libdfx.so.
 Sources are recompiled when they, or any header in csrc/ or include/, are newer

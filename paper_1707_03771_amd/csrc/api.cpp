@@ -16,9 +16,74 @@ static thread_local std::string g_err;
 void set_last_error(const std::string& m) { g_err = m; }
 
 // ---- device memory ------------------------------------------------------------------
+static constexpr size_t ARENA_ALIGN = 256;
+
+Arena::Arena(void* base, size_t bytes) : base_(static_cast<char*>(base)), size_(0) {
+  // start and length trimmed to the alignment
+  const uintptr_t b = reinterpret_cast<uintptr_t>(base_);
+  const size_t skip = (ARENA_ALIGN - b % ARENA_ALIGN) % ARENA_ALIGN;
+  if (bytes > skip) {
+    base_ += skip;
+    size_ = (bytes - skip) / ARENA_ALIGN * ARENA_ALIGN;
+  }
+  if (size_) free_[0] = size_;
+}
+
+void* Arena::take(size_t bytes) {
+  const size_t need = std::max<size_t>(ARENA_ALIGN, (bytes + ARENA_ALIGN - 1) / ARENA_ALIGN * ARENA_ALIGN);
+  std::lock_guard<std::mutex> g(mu_);
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second < need) continue;
+    const size_t off = it->first, len = it->second;
+    free_.erase(it);
+    if (len > need) free_[off + need] = len - need;
+    used_[off] = need;
+    in_use_ += need;
+    peak_ = std::max(peak_, in_use_);
+    return base_ + off;
+  }
+  throw Error(DFX_ENOMEM, "workspace too small: no free block of " + std::to_string(need) + " bytes (" +
+                              std::to_string(in_use_) + " of " + std::to_string(size_) + " bytes in use)");
+}
+
+void Arena::give(void* p) {
+  std::lock_guard<std::mutex> g(mu_);
+  const size_t off = static_cast<size_t>(static_cast<char*>(p) - base_);
+  auto u = used_.find(off);
+  if (u == used_.end()) return;
+  size_t start = off, len = u->second;
+  in_use_ -= len;
+  used_.erase(u);
+  auto nx = free_.lower_bound(start);
+  if (nx != free_.end() && nx->first == start + len) {  // merge with the next free block
+    len += nx->second;
+    nx = free_.erase(nx);
+  }
+  if (nx != free_.begin()) {  // and with the previous one
+    auto pv = std::prev(nx);
+    if (pv->first + pv->second == start) {
+      start = pv->first;
+      len += pv->second;
+      free_.erase(pv);
+    }
+  }
+  free_[start] = len;
+}
+
+Arena*& current_arena() {
+  static thread_local Arena* a = nullptr;
+  return a;
+}
+
 void DevMem::alloc(size_t bytes) {
   release();
   if (bytes == 0) return;
+  if (Arena* a = current_arena()) {
+    p = a->take(bytes);
+    ar = a;
+    n = bytes;
+    return;
+  }
   const hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) {
     p = nullptr;
@@ -28,9 +93,15 @@ void DevMem::alloc(size_t bytes) {
   n = bytes;
 }
 void DevMem::release() {
-  if (p) (void)hipFree(p);
+  if (p) {
+    if (ar)
+      ar->give(p);
+    else
+      (void)hipFree(p);
+  }
   p = nullptr;
   n = 0;
+  ar = nullptr;
 }
 
 // ---- shells ---------------------------------------------------------------------------
@@ -159,6 +230,74 @@ static void compute_metric(const DevShellSet& daux, const std::vector<std::vecto
 
 using namespace dfx;
 
+// ---- workspace sizes (upper bounds; host arithmetic only) ---------------------------
+static int64_t pad256(int64_t b) { return (b + 255) / 256 * 256; }
+
+static int64_t shells_bytes(const HostShells& h) {
+  return 7 * 256 + pad256(24 * (int64_t)h.nsh) + 4 * pad256(4 * (int64_t)h.nsh) +
+         2 * pad256(8 * (int64_t)h.exps.size());
+}
+
+// columns of raw if no pair were screened: sum over a >= b of n_a n_b
+static int64_t cols_bound(const HostShells& b) {
+  int64_t s = 0, d = 0;
+  for (int a = 0; a < b.nsh; ++a) {
+    const int64_t na = 2 * b.l[a] + 1;
+    s += na;
+    d += na * na;
+  }
+  return (s * s + d) / 2;
+}
+
+// largest dfx_jk work on a B of these sizes: any kind and precision, nocc <= 512
+int64_t dfx::jk_need(int nbf, int naux, int64_t ncols_t) {
+  const int64_t n2 = (int64_t)nbf * nbf;
+  int64_t kmax = 0;
+  for (int p = PREC_FP64; p <= PREC_BF16; ++p) {
+    const JKArgs a{nullptr, nullptr, naux, nbf, ncols_t, p};
+    for (int nocc = 1; nocc <= std::min(nbf, 512); ++nocc) kmax = std::max<int64_t>(kmax, k_work_bytes(a, nocc));
+  }
+  const int64_t jw = pad256(8 * (2 * ncols_t + naux + 8)) + pad256(8 * n2);
+  // the density route adds its eigenvectors, one K and a chunk of 512 columns
+  const int64_t dens = pad256(8 * n2) * 2 + pad256(8 * (int64_t)nbf) + pad256(8 * (int64_t)nbf * 512) +
+                       pad256(512 * 4) + pad256(512 * 8) + pad256(kmax);
+  return pad256(std::max(jw, kmax)) + dens;
+}
+
+dfx::Eri3Need dfx::eri3_need(const HostShells& b, const HostShells& a, int flags) {
+  Eri3Need z{};
+  const int64_t nbf = b.nbf, naux = a.nbf, nsh = b.nsh, nauxsh = a.nsh;
+  const int64_t nct = tiled_cols((int)nbf), ncb = cols_bound(b);
+  const int64_t m2 = pad256(8 * naux * naux), raw = pad256(8 * naux * ncb);
+  const int64_t npall = nsh * (nsh + 1) / 2;
+  z.bytes_B = 2 * pad256(4 * naux * nct);
+  z.bytes_raw = raw;
+  z.bytes_metric = 2 * m2;
+  z.bottom = shells_bytes(b) + shells_bytes(a) + z.bytes_B + m2 + ((flags & DFX_KEEP_METRIC) ? m2 : 0) +
+             ((flags & DFX_KEEP_RAW) ? raw : 0);
+  const int64_t lists = 16 * npall + 25 * npall + 20 * nauxsh + 256 * 256;
+  // raw itself, or its working copy when raw is kept; L when not kept
+  z.setup = lists + raw + ((flags & DFX_KEEP_METRIC) ? 0 : m2) +
+            pad256(8 * (int64_t)cholesky_work_elems((int)naux)) + 256 + 2 * pad256(8 * ncb);
+  z.jk = jk_need((int)nbf, (int)naux, nct);
+  const int64_t top = std::max(z.setup, z.jk + pad256(8 * ncb));
+  z.total = z.bottom + top + top / 64 + ((int64_t)16 << 20);
+  return z;
+}
+
+int64_t dfx::scf_need(const HostShells& b, const HostShells& a, int natom, int diis_size) {
+  const Eri3Need e = eri3_need(b, a, 0);
+  const int64_t n = b.nbf, n2 = pad256(8 * n * n);
+  // the SCF's dense matrices (open shell: both spins, 2 x diis_size entries each
+  // for the Fock matrices and errors), their thin companions and small buffers
+  const int64_t mats = (26 + 4 * (int64_t)diis_size) * n2 + 8 * pad256(8 * n * 512) + 512 * 256;
+  // learned guess: per pair-type inputs, outputs and network work, FP32
+  const int64_t guess = (int64_t)natom * natom * 4 * 9842 + ((int64_t)1 << 20);
+  const int64_t pre = 4 * n2 + 3 * 256;  // split-K partials and small buffers made before B
+  const int64_t top = std::max(e.setup + pre, mats + guess + e.jk);
+  return e.bottom + top + top / 64 + ((int64_t)16 << 20);
+}
+
 void* dfx_B::ensure_work(size_t bytes) {
   if (work.n < bytes) work.alloc(bytes);
   return work.p;
@@ -185,11 +324,21 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     B->daux.upload(B->aux, st);
     const double* rys = rys_table_device();
     const int nbf = B->nbf, naux = B->naux;
+    B->ncols_t = tiled_cols(nbf);
+    // What outlives this call first, at the bottom of a caller's workspace: B's
+    // two words (zeroed: tile elements of screened pairs stay zero), then the
+    // metric and its factor when kept.  Everything allocated after them is
+    // released before returning, into one contiguous free block.
+    B->hi.alloc(sizeof(float) * (size_t)naux * B->ncols_t);
+    B->lo.alloc(sizeof(float) * (size_t)naux * B->ncols_t);
+    DFX_HIP(hipMemsetAsync(B->hi.p, 0, B->hi.n, st));
+    DFX_HIP(hipMemsetAsync(B->lo.p, 0, B->lo.n, st));
+    B->J2.alloc(sizeof(double) * naux * (size_t)naux);
+    if (flags & DFX_KEEP_METRIC) B->L.alloc(sizeof(double) * naux * (size_t)naux);
     GpuTimer tm(st);
 
     // -- metric J_PQ = (P|Q)
     tm.start();
-    B->J2.alloc(sizeof(double) * naux * (size_t)naux);
     std::vector<std::vector<int>> auxby(5);
     for (int c = 0; c < nauxsh; ++c) auxby[B->aux.l[c]].push_back(c);
     std::vector<DevMem> auxby_d(5);
@@ -280,7 +429,6 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
         }
       }
     B->ncols_p = B->col_off.back();
-    B->ncols_t = tiled_cols(nbf);
 
     // -- raw (mu nu|P), aux-major, packed pair columns (screened triplets stay zero)
     B->raw.alloc(sizeof(double) * (size_t)naux * B->ncols_p);
@@ -307,28 +455,39 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     // The (class, l_C) launches write disjoint blocks of raw: they run on NSTR
     // streams forked from and joined back to st, most expensive first, each on
     // the least loaded stream, so that short launches fill the others' tails.
+    // The side streams and events belong to the calling thread on this device,
+    // made on first use and kept until the process ends.
     constexpr int NSTR = 4;
-    struct Fork {
+    struct ForkRes {
       hipStream_t s[NSTR] = {};
       hipEvent_t ev[NSTR + 1] = {};
+    };
+    struct Fork {
+      ForkRes& r;
       hipStream_t main;
-      explicit Fork(hipStream_t m) : main(m) {
-        for (int i = 0; i < NSTR; ++i) DFX_HIP(hipStreamCreateWithFlags(&s[i], hipStreamNonBlocking));
-        for (int i = 0; i <= NSTR; ++i) DFX_HIP(hipEventCreateWithFlags(&ev[i], hipEventDisableTiming));
-        DFX_HIP(hipEventRecord(ev[NSTR], main));
-        for (int i = 0; i < NSTR; ++i) DFX_HIP(hipStreamWaitEvent(s[i], ev[NSTR], 0));
+      hipStream_t* s;
+      static ForkRes& res() {
+        static thread_local std::map<int, ForkRes> all;
+        int dev = 0;
+        DFX_HIP(hipGetDevice(&dev));
+        ForkRes& x = all[dev];
+        if (!x.s[0]) {
+          for (int i = 0; i < NSTR; ++i) DFX_HIP(hipStreamCreateWithFlags(&x.s[i], hipStreamNonBlocking));
+          for (int i = 0; i <= NSTR; ++i) DFX_HIP(hipEventCreateWithFlags(&x.ev[i], hipEventDisableTiming));
+        }
+        return x;
+      }
+      explicit Fork(hipStream_t m) : r(res()), main(m), s(r.s) {
+        DFX_HIP(hipEventRecord(r.ev[NSTR], main));
+        for (int i = 0; i < NSTR; ++i) DFX_HIP(hipStreamWaitEvent(s[i], r.ev[NSTR], 0));
       }
       void join() {
         for (int i = 0; i < NSTR; ++i) {
-          DFX_HIP(hipEventRecord(ev[i], s[i]));
-          DFX_HIP(hipStreamWaitEvent(main, ev[i], 0));
+          DFX_HIP(hipEventRecord(r.ev[i], s[i]));
+          DFX_HIP(hipStreamWaitEvent(main, r.ev[i], 0));
         }
       }
-      ~Fork() {
-        (void)hipStreamSynchronize(main);
-        for (int i = 0; i < NSTR; ++i) (void)hipStreamDestroy(s[i]);
-        for (int i = 0; i <= NSTR; ++i) (void)hipEventDestroy(ev[i]);
-      }
+      ~Fork() { (void)hipStreamSynchronize(main); }
     } fork(st);
     struct Launch {
       double cost;
@@ -378,14 +537,15 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     B->info.eri_seconds = te.seconds();
 
     // -- Cholesky of the metric and L^-1
-    GpuTimer tc(st);
-    tc.start();
-    DevMem Lw(sizeof(double) * (size_t)naux * naux);
-    DFX_HIP(hipMemcpyAsync(Lw.p, B->J2.p, Lw.n, hipMemcpyDeviceToDevice, st));
-    DevMem Linv(sizeof(double) * (size_t)naux * naux);
+    DevMem Lw;  // L, factored in place (in B->L when kept)
+    if (!(flags & DFX_KEEP_METRIC)) Lw.alloc(sizeof(double) * (size_t)naux * naux);
+    double* Lp = (flags & DFX_KEEP_METRIC) ? B->L.as<double>() : Lw.as<double>();
     DevMem cw(sizeof(double) * cholesky_work_elems(naux));
     DevMem info_d(sizeof(int));
-    cholesky_inverse(Lw.as<double>(), naux, Linv.as<double>(), cw.as<double>(), info_d.as<int>(), st);
+    GpuTimer tc(st);
+    tc.start();
+    DFX_HIP(hipMemcpyAsync(Lp, B->J2.p, sizeof(double) * (size_t)naux * naux, hipMemcpyDeviceToDevice, st));
+    cholesky_factor(Lp, naux, cw.as<double>(), info_d.as<int>(), st);
     int info = 0;
     DFX_HIP(hipMemcpyAsync(&info, info_d.p, sizeof(int), hipMemcpyDeviceToHost, st));
     tc.stop();
@@ -394,7 +554,7 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
       throw Error(DFX_ENOTPOSDEF, "fitting metric is not positive definite (pivot " + std::to_string(info - 1) + ")");
     {
       std::vector<double> diag(naux);
-      DFX_HIP(hipMemcpy2DAsync(diag.data(), sizeof(double), Lw.p, sizeof(double) * (naux + 1),
+      DFX_HIP(hipMemcpy2DAsync(diag.data(), sizeof(double), Lp, sizeof(double) * (naux + 1),
                                sizeof(double), naux, hipMemcpyDeviceToHost, st));
       DFX_HIP(hipStreamSynchronize(st));
       const auto mm = std::minmax_element(diag.begin(), diag.end());
@@ -425,22 +585,35 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
         }
     }
     DevMem cmap_d = upload(cmap, st), cmap2_d = upload(cmap2, st);
+    // B = L^-1 raw by blocked forward substitution, in place (on a copy when the
+    // raw integrals are kept), then split into the two FP32 words.  The timed
+    // span holds these launches and nothing else; the update products are also
+    // timed on their own.
+    DevMem rawcopy;
+    double* Bw = B->raw.as<double>();
+    if (flags & DFX_KEEP_RAW) {
+      rawcopy.alloc(B->raw.n);
+      DFX_HIP(hipMemcpyAsync(rawcopy.p, B->raw.p, B->raw.n, hipMemcpyDeviceToDevice, st));
+      Bw = rawcopy.as<double>();
+    }
+    struct UpdTimer : TrsmTimer {
+      EventSpans sp;
+      void begin() override { sp.begin(); }
+      void end() override { sp.end(); }
+    } ut;
+    ut.sp.st = st;
     GpuTimer tt(st);
     tt.start();
-    B->hi.alloc(sizeof(float) * (size_t)naux * B->ncols_t);
-    B->lo.alloc(sizeof(float) * (size_t)naux * B->ncols_t);
-    DFX_HIP(hipMemsetAsync(B->hi.p, 0, B->hi.n, st));
-    DFX_HIP(hipMemsetAsync(B->lo.p, 0, B->lo.n, st));
-    trsm_split(Linv.as<double>(), naux, B->raw.as<double>(), B->ncols_p, B->hi.as<float>(), B->lo.as<float>(),
-               B->ncols_t, cmap_d.as<int64_t>(), cmap2_d.as<int64_t>(), st);
+    const TrsmStats ts = trsm_solve(Lp, naux, Bw, B->ncols_p, st, &ut);
+    split_scatter(Bw, naux, B->ncols_p, B->hi.as<float>(), B->lo.as<float>(), B->ncols_t, cmap_d.as<int64_t>(),
+                  cmap2_d.as<int64_t>(), st);
     DFX_HIP(hipGetLastError());
     tt.stop();
     B->info.trsm_seconds = tt.seconds();
-    if (flags & DFX_KEEP_METRIC) {
-      B->L = std::move(Lw);
-    } else {
-      B->J2.release();
-    }
+    B->info.trsm_update_seconds = ut.sp.seconds();
+    B->info.trsm_update_flops = ts.update_flops;
+    B->info.trsm_update_launches = ts.update_launches;
+    if (!(flags & DFX_KEEP_METRIC)) B->J2.release();
     if (!(flags & DFX_KEEP_RAW)) B->raw.release();
     DFX_HIP(hipStreamSynchronize(st));
 
@@ -459,17 +632,28 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
 
 extern "C" {
 
-int dfx_eri3(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
-             const dfx_eri3_opts* opts, void* stream, dfx_B** out) {
+int dfx_eri3(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh, const dfx_eri3_opts* opts,
+             void* dev_workspace, size_t ws_bytes, void* stream, dfx_B** out) {
   return guard([&] {
     if (!out) throw Error(DFX_EINVAL, "dfx_eri3: out is NULL");
     *out = nullptr;
     if (nsh <= 0 || nauxsh <= 0) throw Error(DFX_EINVAL, "dfx_eri3: empty basis");
     HostShells b = make_shells(shells, nsh, 3, "orbital basis");
     HostShells a = make_shells(aux, nauxsh, 4, "auxiliary basis");
-    *out = build_B(std::move(b), std::move(a), opts ? opts->tau : 1e-12, opts ? opts->flags : 0,
-                   (hipStream_t)stream)
-               .release();
+    if (!dev_workspace) throw Error(DFX_EINVAL, "dfx_eri3: no workspace (size it with dfx_eri3_plan)");
+    const int flags = opts ? opts->flags : 0;
+    const Eri3Need need = eri3_need(b, a, flags);
+    if ((int64_t)ws_bytes < need.total)
+      throw Error(DFX_ENOMEM, "dfx_eri3: workspace of " + std::to_string(ws_bytes) + " bytes, " +
+                                  std::to_string(need.total) + " needed (dfx_eri3_plan)");
+    auto arena = std::make_unique<Arena>(dev_workspace, ws_bytes);
+    std::unique_ptr<dfx_B> B;
+    {
+      ArenaScope scope(arena.get());
+      B = build_B(std::move(b), std::move(a), opts ? opts->tau : 1e-12, flags, (hipStream_t)stream);
+    }
+    B->arena = std::move(arena);
+    *out = B.release();
   });
 }
 
@@ -503,20 +687,24 @@ int dfx_cholesky(double* dev_A, int n, double* dev_Linv, void* stream) {
   });
 }
 
-int dfx_eri3_plan(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh, dfx_eri3_sizes* out) {
+int dfx_eri3_plan(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh, const dfx_eri3_opts* opts,
+                  dfx_eri3_sizes* out) {
   return guard([&] {
     if (!out) throw Error(DFX_EINVAL, "dfx_eri3_plan: out is NULL");
     if (nsh <= 0 || nauxsh <= 0) throw Error(DFX_EINVAL, "dfx_eri3_plan: empty basis");
     const HostShells b = make_shells(shells, nsh, 3, "orbital basis");
     const HostShells a = make_shells(aux, nauxsh, 4, "auxiliary basis");
+    const Eri3Need n = eri3_need(b, a, opts ? opts->flags : 0);
     dfx_eri3_sizes z{};
     z.nbf = b.nbf;
     z.naux = a.nbf;
     z.ncols_tiled = tiled_cols(b.nbf);
-    z.bytes_B = (int64_t)a.nbf * z.ncols_tiled * 8;
-    z.bytes_raw = (int64_t)a.nbf * z.ncols_tiled * 8;
-    z.bytes_metric = (int64_t)a.nbf * a.nbf * 8 * 3;
-    z.bytes_setup_peak = z.bytes_B + z.bytes_raw + z.bytes_metric;
+    z.bytes_B = n.bytes_B;
+    z.bytes_raw = n.bytes_raw;
+    z.bytes_metric = n.bytes_metric;
+    z.bytes_persistent = n.bottom;
+    z.bytes_jk = n.jk;
+    z.bytes_workspace = n.total;
     *out = z;
   });
 }
@@ -566,6 +754,7 @@ int dfx_B_export(const dfx_B* bc, int what, int q0, int q1, double* dev_out, voi
     if (q0 < 0 || q1 > b->naux || q1 < q0) throw Error(DFX_EINVAL, "dfx_B_export: bad row range");
     if (what == DFX_EXPORT_RAW && !b->raw.p) throw Error(DFX_EINVAL, "dfx_B_export: raw not kept");
     hipStream_t st = (hipStream_t)stream;
+    ArenaScope scope(b->arena.get());
     if (!b->toff.p) {
       std::vector<int64_t> toff(b->ncols_p);
       for (size_t k = 0; k < b->pa.size(); ++k) {
@@ -611,6 +800,7 @@ int dfx_jk(const dfx_B* bc, const double* dev_in, int kind, int nocc, int precis
     if (precision < DFX_FP64 || precision > DFX_BF16) throw Error(DFX_EINVAL, "dfx_jk: bad precision");
     if (kind == DFX_COCC && (nocc <= 0 || nocc > b->nbf)) throw Error(DFX_EINVAL, "dfx_jk: bad nocc");
     hipStream_t st = (hipStream_t)stream;
+    ArenaScope scope(b->arena.get());
     JKArgs a{b->hi.as<float>(), b->lo.as<float>(), b->naux, b->nbf, b->ncols_t, precision};
     const int nbf = b->nbf;
     size_t need = 0;

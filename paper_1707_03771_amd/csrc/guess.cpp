@@ -404,6 +404,8 @@ static void init_theta(GuessType& T, uint64_t seed) {
 static void ensure_device(GuessType& T) {
   const size_t n = T.theta_h.size();
   if (T.theta.n == n * sizeof(float)) return;
+  // the model outlives any call's workspace: its weights never come from one
+  ArenaScope own(nullptr);
   T.theta.alloc(n * sizeof(float));
   T.m.alloc(n * sizeof(float));
   T.v.alloc(n * sizeof(float));

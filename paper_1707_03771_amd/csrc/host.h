@@ -1,6 +1,8 @@
 // Host-side runtime of the dfx library: shells, device buffers, screening lists.
 #pragma once
+#include <map>
 #include <memory>
+#include <mutex>
 #include <vector>
 
 #include "../../include/dfx.h"
@@ -9,16 +11,49 @@
 namespace dfx {
 
 // ---- device memory ---------------------------------------------------------
+// Sub-allocator over one range of caller-owned device memory: first fit over
+// the free blocks, 256-byte aligned, neighbouring free blocks merged.  Pure host
+// bookkeeping, no HIP calls.  take() throws DFX_ENOMEM when no free block fits.
+class Arena {
+ public:
+  Arena(void* base, size_t bytes);
+  void* take(size_t bytes);
+  void give(void* p);
+  size_t peak() const { return peak_; }
+  size_t size() const { return size_; }
+  char* base() const { return base_; }
+
+ private:
+  char* base_;
+  size_t size_;
+  std::map<size_t, size_t> free_;  // offset -> length
+  std::map<size_t, size_t> used_;  // offset -> length
+  size_t in_use_ = 0, peak_ = 0;
+  std::mutex mu_;
+};
+
+// The arena that DevMem::alloc draws from on this thread (null: hipMalloc).
+// ArenaScope makes one current for its lifetime and restores the previous.
+Arena*& current_arena();
+struct ArenaScope {
+  Arena* prev;
+  explicit ArenaScope(Arena* a) : prev(current_arena()) { current_arena() = a; }
+  ~ArenaScope() { current_arena() = prev; }
+  ArenaScope(const ArenaScope&) = delete;
+  ArenaScope& operator=(const ArenaScope&) = delete;
+};
+
 struct DevMem {
   void* p = nullptr;
   size_t n = 0;
+  Arena* ar = nullptr;  // the arena p came from, if any
   DevMem() = default;
   explicit DevMem(size_t bytes) { alloc(bytes); }
   DevMem(const DevMem&) = delete;
   DevMem& operator=(const DevMem&) = delete;
-  DevMem(DevMem&& o) noexcept : p(o.p), n(o.n) { o.p = nullptr; o.n = 0; }
+  DevMem(DevMem&& o) noexcept : p(o.p), n(o.n), ar(o.ar) { o.p = nullptr; o.n = 0; o.ar = nullptr; }
   DevMem& operator=(DevMem&& o) noexcept {
-    if (this != &o) { release(); p = o.p; n = o.n; o.p = nullptr; o.n = 0; }
+    if (this != &o) { release(); p = o.p; n = o.n; ar = o.ar; o.p = nullptr; o.n = 0; o.ar = nullptr; }
     return *this;
   }
   ~DevMem() { release(); }
@@ -123,6 +158,8 @@ struct EventSpans {
 
 // ---- the fitted tensor handle -------------------------------------------------------
 struct dfx_B {
+  // declared first, destroyed last: every DevMem below may live in it
+  std::unique_ptr<dfx::Arena> arena;  // over the caller's workspace (dfx_eri3)
   int device = 0;
   dfx::HostShells bas, aux;
   dfx::DevShellSet dbas, daux;
@@ -140,6 +177,19 @@ struct dfx_B {
 };
 
 namespace dfx {
+// device bytes of dfx_eri3 inside a caller's workspace (upper bounds)
+struct Eri3Need {
+  int64_t bytes_B, bytes_raw, bytes_metric;
+  int64_t bottom;  // outlives the call: shells, B (hi, lo), J_PQ slot, kept metric / raw
+  int64_t setup;   // released before the call returns
+  int64_t jk;      // largest dfx_jk work on the result
+  int64_t total;   // bottom + max(setup, jk + export map) + fragmentation slack
+};
+Eri3Need eri3_need(const HostShells& b, const HostShells& a, int flags);
+int64_t jk_need(int nbf, int naux, int64_t ncols_t);
+// device bytes of dfx_scf / dfx_uhf / dfx_rohf inside a caller's workspace
+int64_t scf_need(const HostShells& b, const HostShells& a, int natom, int diis_size);
+
 // internal builders shared by the C-ABI entry points and the SCF driver
 std::unique_ptr<dfx_B> build_B(HostShells bas, HostShells aux, double tau, int flags, hipStream_t st);
 void int1e_build(const HostShells& h, const dfx_geom* geom, double* S, double* T, double* V,

@@ -1,6 +1,7 @@
 // Internal launch interface of the dfx kernels (not part of the C-ABI).
 #pragma once
 #include "common.h"
+#include "dfx.h"  // status codes
 #include "eri_args.h"
 
 namespace dfx {
@@ -45,10 +46,6 @@ struct GemmF64 {
   bool ta, tb;     // op(A) = A^T, op(B) = B^T
   bool lowerA;     // A is lower triangular (skip zero k-blocks)
   bool lowerC;     // only the lower triangle of C is needed (skip blocks above)
-  // scatter epilogue (B transform): column n of the product goes to column
-  // cmap[n] of hi / lo (none if negative), and also to cmap2[n] if that is >= 0
-  const int64_t* cmap;
-  const int64_t* cmap2;
 };
 void dgemm(const GemmF64& g, hipStream_t st);
 // dgemm, with the k-range split over up to 8 partial products (work: ns M N
@@ -56,18 +53,33 @@ void dgemm(const GemmF64& g, hipStream_t st);
 // fill the chip; the partials are summed in a fixed order
 void dgemm_sk(const GemmF64& g, double* work, int64_t work_elems, hipStream_t st);
 
-// B-transform: out = L^-1 * raw with lower-triangular Linv [n x n] and raw
-// [n x ncols] (packed pair columns), written as hi = fl32(out), lo = fl32(out -
-// hi) into rows of length ld_out at the columns cmap (and cmap2, the mirror
-// position inside diagonal tiles).
-void trsm_split(const double* Linv, int n, const double* raw, int64_t ncols, float* hi, float* lo, int64_t ld_out,
-                const int64_t* cmap, const int64_t* cmap2, hipStream_t st);
+
+// B = L^-1 raw in place over raw (n x ncols, FP64, row stride ncols), by
+// blocked forward substitution with the lower-triangular L (n x n): backward
+// stable, unlike a product with an explicit inverse.
+struct TrsmStats {
+  double update_flops = 0.0;  // 2 M K N of every update product
+  int update_launches = 0;
+};
+// optional GPU timer around each update product (events recorded on st)
+struct TrsmTimer {
+  virtual void begin() = 0;
+  virtual void end() = 0;
+  virtual ~TrsmTimer() = default;
+};
+TrsmStats trsm_solve(const double* L, int n, double* raw, int64_t ncols, hipStream_t st, TrsmTimer* timer = nullptr);
+// hi = fl32(B), lo = fl32(B - hi) of B (n x ncols) into rows of length ld_out at
+// the columns cmap (and cmap2 where >= 0)
+void split_scatter(const double* B, int n, int64_t ncols, float* hi, float* lo, int64_t ld_out, const int64_t* cmap,
+                   const int64_t* cmap2, hipStream_t st);
 
 // Blocked Cholesky J = L L^T in place (lower), then Linv = L^-1.  Returns via
 // *info (device int) the first non-positive pivot + 1, or 0; a pivot below
 // 1e-14 of its original diagonal element counts as non-positive.
 // work: cholesky_work_elems(n) doubles.
 void cholesky_inverse(double* J, int n, double* Linv, double* work, int* info, hipStream_t st);
+// the factor alone (no L^-1), same work and error reporting
+void cholesky_factor(double* J, int n, double* work, int* info, hipStream_t st);
 size_t cholesky_work_elems(int n);
 
 // ---- J / K (jk.hip) ----------------------------------------------------------

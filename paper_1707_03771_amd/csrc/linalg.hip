@@ -1,7 +1,7 @@
 // Dense FP64 linear algebra on gfx950 MFMA: a tiled DGEMM (v_mfma_f64_16x16x4),
-// the blocked Cholesky factorisation of the fitting metric J_PQ = L L^T, the
-// inverse L^-1, and the transform B = L^-1 (mu nu|P) of Eq. (1c) with
-// M' = L^-1, whose epilogue splits B into two FP32 words.
+// the blocked Cholesky factorisation of the fitting metric J_PQ = L L^T (and
+// L^-1 where asked), and the transform B = L^-1 (mu nu|P) of Eq. (1c) with
+// M' = L^-1 by blocked forward substitution, then split into two FP32 words.
 #include <algorithm>
 
 #include "kernels.h"
@@ -14,7 +14,7 @@ constexpr int GM = 128, GN = 128, GK = 16, GT = 256;
 // k-major LDS rows of GM + 16 doubles: the four k rows a fragment read touches
 // fall on alternate halves of the 64 banks (2 passes per read, the minimum)
 constexpr int LDS_PAD = 16;
-enum { EPI_F64 = 0, EPI_SPLIT = 1 };
+enum { EPI_F64 = 0, EPI_SUB = 1 };  // EPI_SUB: C -= A B (the B transform's updates)
 
 // Workgroup -> tile map.  Workgroups are dealt round-robin to the 8 XCDs; give
 // each XCD a contiguous range of tiles (M-block fastest) so that the tiles that
@@ -36,11 +36,10 @@ __device__ __forceinline__ void ld8d(const double* __restrict__ p, double* v) {
   }
 }
 
-// C = alpha op(A) op(B) + beta C (EPI_F64) or hi/lo = split(op(A) op(B)) (EPI_SPLIT).
+// C = alpha op(A) op(B) + beta C (EPI_F64), or C -= op(A) op(B) (EPI_SUB).
 // Each k-stage is loaded into registers while the MFMAs of the previous stage run.
 template <bool TA, bool TB, int EPI>
-__global__ void __launch_bounds__(GT, 2) dgemm_kernel(GemmF64 g, float* __restrict__ hi,
-                                                   float* __restrict__ lo) {
+__global__ void __launch_bounds__(GT, 2) dgemm_kernel(GemmF64 g) {
   __shared__ double As[GK][GM + LDS_PAD];
   __shared__ double Bs[GK][GN + LDS_PAD];
   const int MB = (g.M + GM - 1) / GM, NB = (g.N + GN - 1) / GN;
@@ -164,17 +163,7 @@ __global__ void __launch_bounds__(GT, 2) dgemm_kernel(GemmF64 g, float* __restri
             if (g.beta != 0.0) v = fma(g.beta, C[o], v);
             C[o] = v;
           } else {
-            const double v = acc[i][j][r];
-            const float h = (float)v, l = (float)(v - (double)h);
-            const int64_t t = g.cmap[n], t2 = g.cmap2[n];
-            if (t >= 0) {
-              hi[(int64_t)m * g.ldc + t] = h;
-              lo[(int64_t)m * g.ldc + t] = l;
-            }
-            if (t2 >= 0) {
-              hi[(int64_t)m * g.ldc + t2] = h;
-              lo[(int64_t)m * g.ldc + t2] = l;
-            }
+            C[o] = C[o] - acc[i][j][r];
           }
         }
       }
@@ -190,7 +179,7 @@ void dgemm(const GemmF64& g, hipStream_t st) {
     a.K = 0;
   }
 #define L(TA_, TB_) \
-  hipLaunchKernelGGL((dgemm_kernel<TA_, TB_, EPI_F64>), grid, dim3(GT), 0, st, a, nullptr, nullptr)
+  hipLaunchKernelGGL((dgemm_kernel<TA_, TB_, EPI_F64>), grid, dim3(GT), 0, st, a)
   if (!g.ta && !g.tb) L(false, false);
   else if (!g.ta && g.tb) L(false, true);
   else if (g.ta && !g.tb) L(true, false);
@@ -228,7 +217,7 @@ void dgemm_sk(const GemmF64& g, double* work, int64_t work_elems, hipStream_t st
   auto launch = [&](const GemmF64& x, int nz) {
     const dim3 grid(tiles, 1, nz);
 #define L(TA_, TB_) \
-  hipLaunchKernelGGL((dgemm_kernel<TA_, TB_, EPI_F64>), grid, dim3(GT), 0, st, x, nullptr, nullptr)
+  hipLaunchKernelGGL((dgemm_kernel<TA_, TB_, EPI_F64>), grid, dim3(GT), 0, st, x)
     if (!x.ta && !x.tb) L(false, false);
     else if (!x.ta && x.tb) L(false, true);
     else if (x.ta && !x.tb) L(true, false);
@@ -258,23 +247,159 @@ void dgemm_sk(const GemmF64& g, double* work, int64_t work_elems, hipStream_t st
                      g.alpha, g.beta, g.C, g.ldc);
 }
 
-void trsm_split(const double* Linv, int n, const double* raw, int64_t ncols, float* hi, float* lo, int64_t ld_out,
-                const int64_t* cmap, const int64_t* cmap2, hipStream_t st) {
-  // columns in slabs so that the grid stays within one launch's int range
-  const int64_t slab = (int64_t)GN * 65536;
+// ---------------------------------------------------------------------------
+// B = L^-1 raw by blocked forward substitution, in place over raw (n x ncols,
+// row stride ncols).  Left-looking over blocks of TB = 128 rows: the block's
+// rows take R_i -= L_i,0:i B_0:i as one DGEMM (MFMA, the rows before it are
+// already B), then the 128 x 128 diagonal block is solved by substitution, in
+// two halves of 64 rows with the DGEMM R_2 -= L_21 B_1 between them.  Unlike a
+// product with an explicitly formed L^-1, whose rounding errors are amplified
+// by cond(L), this is backward stable: the result is the exact transform with
+// a metric perturbed at the rounding level.
+constexpr int TS_T = 256;   // columns per workgroup of the substitution
+constexpr int TS_R = 64;    // rows solved in registers
+
+// L x = b for the nr <= 64 rows r0.. of every column c of X: one column per
+// thread, its 64 unknowns in registers.  Rows go in groups of 8: the group's
+// right-hand sides take s_r -= L_rk x_k for every earlier unknown k (one step
+// per k reads the 8 entries L_(g..g+7),k, stored k-major in LDS so that they are
+// consecutive), then the 8 x 8 triangle is solved, x_r = s_r / L_rr.  The block
+// of L is staged in LDS and every lane reads the same address.
+constexpr int TS_G = 8;
+template <bool FULL>  // FULL: nr == 64
+__global__ void __launch_bounds__(TS_T) trsv64_cols_kernel(const double* __restrict__ L, int64_t ldl, int nr,
+                                                           double* __restrict__ X, int64_t ldx, int ncols) {
+  __shared__ double Lt[TS_R][TS_R];  // Lt[k][i] = L_ik
+  for (int e = threadIdx.x; e < TS_R * TS_R; e += TS_T) {
+    const int k = e / TS_R, i = e % TS_R;
+    // rows beyond nr: the identity, so their (zero) unknowns stay zero
+    Lt[k][i] = (i < nr && k < nr) ? (k <= i ? L[(int64_t)i * ldl + k] : 0.0) : (i == k ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  const int c = blockIdx.x * TS_T + threadIdx.x;
+  if (c >= ncols) return;
+  double x[TS_R];
+#pragma unroll
+  for (int g = 0; g < TS_R; g += TS_G) {
+    double s[TS_G];
+#pragma unroll
+    for (int r = 0; r < TS_G; ++r) {
+      // the row base is wave-uniform; rows past nr read row nr - 1 and drop it
+      const int row = FULL ? g + r : min(g + r, nr - 1);
+      const double v = X[(int64_t)row * ldx + c];
+      s[r] = (FULL || g + r < nr) ? v : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < g; ++k) {
+      double l[TS_G];
+#pragma unroll
+      for (int r = 0; r < TS_G; ++r) l[r] = Lt[k][g + r];
+#pragma unroll
+      for (int r = 0; r < TS_G; ++r) s[r] = fma(-l[r], x[k], s[r]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int r = 0; r < TS_G; ++r) {
+#pragma unroll
+      for (int k = 0; k < r; ++k) s[r] = fma(-Lt[g + k][g + r], x[g + k], s[r]);
+      x[g + r] = s[r] / Lt[g + r][g + r];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // without branches: rows past nr store to row nr - 1, in descending order so
+  // that the last store there (program order, one thread) is x[nr - 1]
+#pragma unroll
+  for (int i = TS_R - 1; i >= 0; --i) X[(int64_t)(FULL ? i : min(i, nr - 1)) * ldx + c] = x[i];
+}
+
+// hi = fl32(B), lo = fl32(B - hi) scattered to the tile layout: packed column c
+// goes to column cmap[c] of a row of length ld_out (none if negative), and also
+// to cmap2[c] when that is >= 0 (the mirror position inside a diagonal tile)
+__global__ void split_scatter_kernel(const double* __restrict__ B, int64_t ncols, const int64_t* __restrict__ cmap,
+                                     const int64_t* __restrict__ cmap2, float* __restrict__ hi,
+                                     float* __restrict__ lo, int64_t ld_out) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= ncols) return;
+  const int64_t q = blockIdx.y;
+  const double v = B[q * ncols + c];
+  const float h = (float)v, l = (float)(v - (double)h);
+  const int64_t t = cmap[c], t2 = cmap2[c];
+  if (t >= 0) {
+    hi[q * ld_out + t] = h;
+    lo[q * ld_out + t] = l;
+  }
+  if (t2 >= 0) {
+    hi[q * ld_out + t2] = h;
+    lo[q * ld_out + t2] = l;
+  }
+}
+
+static void trsv64_cols(const double* L, int64_t ldl, int nr, double* X, int64_t ldx, int64_t ncols,
+                        hipStream_t st) {
+  // columns in slabs whose indices fit the kernel's 32-bit column offsets
+  const int64_t slab = (int64_t)TS_T * 1048576;
   for (int64_t c0 = 0; c0 < ncols; c0 += slab) {
     const int nc = (int)std::min<int64_t>(slab, ncols - c0);
+    const dim3 g((unsigned)((nc + TS_T - 1) / TS_T));
+    if (nr == TS_R)
+      hipLaunchKernelGGL(trsv64_cols_kernel<true>, g, dim3(TS_T), 0, st, L, ldl, nr, X + c0, ldx, nc);
+    else
+      hipLaunchKernelGGL(trsv64_cols_kernel<false>, g, dim3(TS_T), 0, st, L, ldl, nr, X + c0, ldx, nc);
+  }
+}
+
+// X[rows] -= A X[krows]: R_i -= L_i,0:k B_0:k over all columns, in slabs that
+// keep each launch's grid within range
+static double trsm_update(const double* A, int64_t lda, int M, int K, const double* Bsrc, double* C, int64_t ncols,
+                          hipStream_t st) {
+  const int64_t slab = (int64_t)GN * 65536;
+  for (int64_t c0 = 0; c0 < ncols; c0 += slab) {
     GemmF64 g{};
-    g.M = n; g.N = nc; g.K = n;
-    g.A = Linv; g.lda = n;
-    g.B = raw + c0; g.ldb = ncols;
-    g.C = nullptr; g.ldc = ld_out;
-    g.alpha = 1.0; g.beta = 0.0; g.batch = 1;
-    g.lowerA = true;
-    g.cmap = cmap + c0;
-    g.cmap2 = cmap2 + c0;
-    const dim3 grid(gemm_tiles(g.M, g.N));
-    hipLaunchKernelGGL((dgemm_kernel<false, false, EPI_SPLIT>), grid, dim3(GT), 0, st, g, hi, lo);
+    g.M = M; g.N = (int)std::min<int64_t>(slab, ncols - c0); g.K = K;
+    g.A = A; g.lda = lda;
+    g.B = Bsrc + c0; g.ldb = ncols;
+    g.C = C + c0; g.ldc = ncols;
+    g.alpha = -1.0; g.beta = 1.0; g.batch = 1;
+    hipLaunchKernelGGL((dgemm_kernel<false, false, EPI_SUB>), dim3(gemm_tiles(g.M, g.N)), dim3(GT), 0, st, g);
+  }
+  return 2.0 * M * (double)K * (double)ncols;
+}
+
+TrsmStats trsm_solve(const double* L, int n, double* raw, int64_t ncols, hipStream_t st, TrsmTimer* timer) {
+  TrsmStats z{};
+  if (ncols <= 0) return z;
+  constexpr int TB = 2 * TS_R;
+  for (int r0 = 0; r0 < n; r0 += TB) {
+    const int rb = std::min(TB, n - r0);
+    if (r0 > 0) {
+      if (timer) timer->begin();
+      z.update_flops += trsm_update(L + (int64_t)r0 * n, n, rb, r0, raw, raw + (int64_t)r0 * ncols, ncols, st);
+      if (timer) timer->end();
+      ++z.update_launches;
+    }
+    const int h1 = std::min(TS_R, rb);
+    trsv64_cols(L + (int64_t)r0 * n + r0, n, h1, raw + (int64_t)r0 * ncols, ncols, ncols, st);
+    if (rb > TS_R) {
+      const int r1 = r0 + TS_R;
+      if (timer) timer->begin();
+      z.update_flops += trsm_update(L + (int64_t)r1 * n + r0, n, rb - TS_R, TS_R, raw + (int64_t)r0 * ncols,
+                                    raw + (int64_t)r1 * ncols, ncols, st);
+      if (timer) timer->end();
+      ++z.update_launches;
+      trsv64_cols(L + (int64_t)r1 * n + r1, n, rb - TS_R, raw + (int64_t)r1 * ncols, ncols, ncols, st);
+    }
+  }
+  return z;
+}
+
+void split_scatter(const double* B, int n, int64_t ncols, float* hi, float* lo, int64_t ld_out, const int64_t* cmap,
+                   const int64_t* cmap2, hipStream_t st) {
+  if (ncols <= 0 || n <= 0) return;
+  for (int q0 = 0; q0 < n; q0 += 65535) {
+    const int nq = std::min(65535, n - q0);
+    const dim3 g((unsigned)((ncols + 255) / 256), nq);
+    hipLaunchKernelGGL(split_scatter_kernel, g, dim3(256), 0, st, B + (int64_t)q0 * ncols, ncols, cmap, cmap2,
+                       hi + (int64_t)q0 * ld_out, lo + (int64_t)q0 * ld_out, ld_out);
   }
 }
 
@@ -283,7 +408,7 @@ void trsm_split(const double* Linv, int n, const double* raw, int64_t ncols, flo
 // inverse.  A non-positive pivot records its global index + 1 in *info.
 constexpr int CB = 64;
 __global__ void __launch_bounds__(64) potrf_diag_kernel(double* J, int n, int k0, int kb,
-                                                        double* Linv, int* info,
+                                                        double* Linv, int64_t ldx, int* info,
                                                         const double* __restrict__ diag0) {
   __shared__ double a[CB][CB + 1];
   __shared__ double x[CB][CB + 1];
@@ -326,7 +451,7 @@ __global__ void __launch_bounds__(64) potrf_diag_kernel(double* J, int n, int k0
   for (int i = 0; i < kb; ++i)
     if (t < kb) {
       J[(int64_t)(k0 + i) * n + k0 + t] = (t <= i) ? a[i][t] : 0.0;
-      Linv[(int64_t)(k0 + i) * n + k0 + t] = x[i][t];
+      Linv[(int64_t)i * ldx + t] = x[i][t];
     }
 }
 
@@ -380,23 +505,27 @@ __global__ void diag_kernel(const double* A, int n, double* d) {
 // work: at least n * (CB + 1) doubles.
 // work: the panel (n x CB), the original diagonal (n), and the split-K partial
 // products of the inverse's block rows (8 x CB x n)
-size_t cholesky_work_elems(int n) { return (size_t)n * (CB + 1) + (size_t)8 * CB * n; }
+size_t cholesky_work_elems(int n) { return (size_t)n * (CB + 1) + std::max((size_t)8 * CB * n, (size_t)CB * CB); }
 
-void cholesky_inverse(double* J, int n, double* Linv, double* work, int* info, hipStream_t st) {
-  fill_f64(Linv, (size_t)n * n, 0.0, st);
+// J = L L^T in place; with Linv, the inverses of the diagonal blocks go there
+// (the rest of Linv is then formed by cholesky_inverse), else to work.
+static void cholesky_factor_impl(double* J, int n, double* Linv, double* work, int* info, hipStream_t st) {
   DFX_HIP(hipMemsetAsync(info, 0, sizeof(int), st));
   double* diag0 = work + (size_t)n * CB;
+  double* xblk = work + (size_t)n * (CB + 1);  // CB x CB when there is no Linv
   hipLaunchKernelGGL(diag_kernel, dim3((n + 255) / 256), dim3(256), 0, st, J, n, diag0);
   for (int k0 = 0; k0 < n; k0 += CB) {
     const int kb = std::min(CB, n - k0);
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(64), 0, st, J, n, k0, kb, Linv, info, diag0);
+    double* X = Linv ? Linv + (int64_t)k0 * n + k0 : xblk;
+    const int64_t ldx = Linv ? n : CB;
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(64), 0, st, J, n, k0, kb, X, ldx, info, diag0);
     const int r0 = k0 + kb, rows = n - r0;
     if (rows <= 0) break;
     // panel: L21 = A21 inv(L11)^T
     GemmF64 g{};
     g.M = rows; g.N = kb; g.K = kb;
     g.A = J + (int64_t)r0 * n + k0; g.lda = n;
-    g.B = Linv + (int64_t)k0 * n + k0; g.ldb = n; g.tb = true;
+    g.B = X; g.ldb = ldx; g.tb = true;
     g.C = work; g.ldc = kb;
     g.alpha = 1.0; g.beta = 0.0; g.batch = 1;
     dgemm(g, st);
@@ -414,6 +543,15 @@ void cholesky_inverse(double* J, int n, double* Linv, double* work, int* info, h
     const int64_t t = (int64_t)n * n;
     hipLaunchKernelGGL(zero_upper_kernel, dim3((unsigned)((t + 255) / 256)), dim3(256), 0, st, J, n);
   }
+}
+
+void cholesky_factor(double* J, int n, double* work, int* info, hipStream_t st) {
+  cholesky_factor_impl(J, n, nullptr, work, info, st);
+}
+
+void cholesky_inverse(double* J, int n, double* Linv, double* work, int* info, hipStream_t st) {
+  fill_f64(Linv, (size_t)n * n, 0.0, st);
+  cholesky_factor_impl(J, n, Linv, work, info, st);
   // off-diagonal blocks of L^-1, block row by block row (row-wise substitution,
   // which keeps the inverse accurate for an ill-conditioned metric; a recursive
   // X21 = -X22 L21 X11 lost two to three digits on kappa = 8.6e9):

@@ -22,6 +22,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 
 #include "host.h"
 
@@ -289,6 +290,30 @@ __global__ void negate_kernel(double* __restrict__ A, int64_t n) {
 
 static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
+// The calling thread's SCF stream and rocBLAS handle on the current device,
+// made on first use and kept until the process ends: a call neither creates
+// nor destroys them (the handle also keeps the eigensolver's device scratch
+// between calls).
+struct DevCtx {
+  hipStream_t st = nullptr;
+  rocblas_handle rb = nullptr;
+};
+static DevCtx& thread_ctx() {
+  static thread_local std::map<int, DevCtx> ctx;
+  int dev = 0;
+  DFX_HIP(hipGetDevice(&dev));
+  DevCtx& c = ctx[dev];
+  if (!c.st) DFX_HIP(hipStreamCreate(&c.st));
+  if (!c.rb) {
+    // the handle's own scratch is its for the process: never from a call's workspace
+    if (rocblas_create_handle(&c.rb) != rocblas_status_success) {
+      c.rb = nullptr;
+      throw Error(DFX_EHIP, "rocblas_create_handle failed");
+    }
+  }
+  return c;
+}
+
 // ---- driver ---------------------------------------------------------------------------
 struct Scf {
   hipStream_t st{};
@@ -476,13 +501,7 @@ void k_from_density(const JKArgs& a, const double* D, double* K, hipStream_t st)
   const int64_t n2 = (int64_t)n * n;
   Scf S;
   S.st = st;
-  struct Cleanup {
-    Scf& s;
-    ~Cleanup() {
-      if (s.rb) rocblas_destroy_handle(s.rb);
-    }
-  } cleanup{S};
-  if (rocblas_create_handle(&S.rb) != rocblas_status_success) throw Error(DFX_EHIP, "rocblas_create_handle failed");
+  S.rb = thread_ctx().rb;
   rocblas_set_stream(S.rb, st);
   S.eig_info.alloc(sizeof(int));
   DevMem W(8 * n2), lam(8 * (size_t)n);
@@ -526,11 +545,37 @@ void k_from_density(const JKArgs& a, const double* D, double* K, hipStream_t st)
   }
 }
 
+// The arena over opts.workspace (null without one).  The size is checked
+// against scf_need before any device work.
+static std::unique_ptr<Arena> scf_arena(const dfx_scf_opts& o, const HostShells& hb, const HostShells& ha, int natom,
+                                        const char* fn) {
+  if (!o.workspace) return nullptr;
+  const int64_t need = scf_need(hb, ha, natom, o.diis_size);
+  if ((int64_t)o.ws_bytes < need)
+    throw Error(DFX_ENOMEM, std::string(fn) + ": workspace of " + std::to_string(o.ws_bytes) + " bytes, " +
+                                std::to_string(need) + " needed (dfx_scf_plan)");
+  return std::make_unique<Arena>(o.workspace, o.ws_bytes);
+}
+
 }  // namespace dfx
 
 using namespace dfx;
 
 extern "C" {
+
+int dfx_scf_plan(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh, int natom,
+                 const dfx_scf_opts* opts, int64_t* bytes) {
+  return guard([&] {
+    if (!bytes || natom <= 0) throw Error(DFX_EINVAL, "dfx_scf_plan: bad argument");
+    dfx_scf_opts o;
+    dfx_scf_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.diis_size < 1 || o.diis_size > 16) throw Error(DFX_EINVAL, "dfx_scf_plan: bad options");
+    const HostShells hb = make_shells(shells, nsh, 3, "orbital basis");
+    const HostShells ha = make_shells(aux, nauxsh, 4, "auxiliary basis");
+    *bytes = scf_need(hb, ha, natom, o.diis_size);
+  });
+}
 
 void dfx_scf_default_opts(dfx_scf_opts* o) {
   if (!o) return;
@@ -579,17 +624,16 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     const int n = hb.nbf;
     if (nocc > n) throw Error(DFX_EINVAL, "dfx_scf: more occupied orbitals than basis functions");
 
+    // with a caller's workspace every device buffer of the call lives in it
+    std::unique_ptr<Arena> arena = scf_arena(o, hb, ha, geom->natom, "dfx_scf");
+    ArenaScope scope(arena.get());
     Scf S;
-    DFX_HIP(hipStreamCreate(&S.st));
-    struct Cleanup {
-      Scf& s;
-      ~Cleanup() {
-        if (s.rb) rocblas_destroy_handle(s.rb);
-        if (s.st) (void)hipStreamDestroy(s.st);
-      }
-    } cleanup{S};
-    if (rocblas_create_handle(&S.rb) != rocblas_status_success) throw Error(DFX_EHIP, "rocblas_create_handle failed");
-    rocblas_set_stream(S.rb, S.st);
+    {
+      DevCtx& ctx = thread_ctx();
+      S.st = ctx.st;
+      S.rb = ctx.rb;
+      rocblas_set_stream(S.rb, S.st);
+    }
     hipStream_t st = S.st;
     S.n = n;
     S.nocc = nocc;
@@ -1032,6 +1076,9 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     inf.t_eri = B->info.eri_seconds;
     inf.t_metric = B->info.metric_seconds;
     inf.t_trsm = B->info.trsm_seconds;
+    inf.t_trsm_update = B->info.trsm_update_seconds;
+    inf.trsm_update_flops = B->info.trsm_update_flops;
+    inf.n_trsm_update = B->info.trsm_update_launches;
     inf.t_j = sp_j.seconds();
     inf.t_kx = inf.t_ksyrk = 0.0;
     inf.n_kx_launch = 0;
@@ -1091,17 +1138,15 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
     const int n = hb.nbf;
     if (na > n) throw Error(DFX_EINVAL, fn + ": more occupied orbitals than basis functions");
 
+    std::unique_ptr<Arena> arena = scf_arena(o, hb, ha, geom->natom, fn.c_str());
+    ArenaScope scope(arena.get());
     Scf S;
-    DFX_HIP(hipStreamCreate(&S.st));
-    struct Cleanup {
-      Scf& s;
-      ~Cleanup() {
-        if (s.rb) rocblas_destroy_handle(s.rb);
-        if (s.st) (void)hipStreamDestroy(s.st);
-      }
-    } cleanup{S};
-    if (rocblas_create_handle(&S.rb) != rocblas_status_success) throw Error(DFX_EHIP, "rocblas_create_handle failed");
-    rocblas_set_stream(S.rb, S.st);
+    {
+      DevCtx& ctx = thread_ctx();
+      S.st = ctx.st;
+      S.rb = ctx.rb;
+      rocblas_set_stream(S.rb, S.st);
+    }
     hipStream_t st = S.st;
     S.n = n;
     S.nocc = na;
@@ -1385,6 +1430,9 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
     inf.t_eri = B->info.eri_seconds;
     inf.t_metric = B->info.metric_seconds;
     inf.t_trsm = B->info.trsm_seconds;
+    inf.t_trsm_update = B->info.trsm_update_seconds;
+    inf.trsm_update_flops = B->info.trsm_update_flops;
+    inf.n_trsm_update = B->info.trsm_update_launches;
     inf.nintegrals = B->info.nintegrals;
     inf.ncols = B->info.ncols;
     if (info) *info = inf;
@@ -1414,13 +1462,7 @@ int dfx_lowdin(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dou
     const int64_t n2 = (int64_t)n * n;
     Scf S;
     S.st = (hipStream_t)stream;
-    struct Cleanup {
-      Scf& s;
-      ~Cleanup() {
-        if (s.rb) rocblas_destroy_handle(s.rb);
-      }
-    } cleanup{S};
-    if (rocblas_create_handle(&S.rb) != rocblas_status_success) throw Error(DFX_EHIP, "rocblas_create_handle failed");
+    S.rb = thread_ctx().rb;
     rocblas_set_stream(S.rb, S.st);
     S.eig_info.alloc(sizeof(int));
     hipStream_t st = S.st;

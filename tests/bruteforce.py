@@ -66,3 +66,29 @@ def overlap_cart(A, a, pa, B, b, pb):
         t = P[ax] + x / math.sqrt(p)
         out *= float(np.sum(w * (t - A[ax]) ** pa[ax] * (t - B[ax]) ** pb[ax])) / math.sqrt(p)
     return out
+
+
+def kinetic_cart(A, a, pa, B, b, pb):
+    """<a| -1/2 nabla^2 |b> over unnormalised Cartesian primitives, in the
+    symmetric form 1/2 int grad(phi_a) . grad(phi_b) d^3r (integration by
+    parts).  Each first derivative is written out, d/dx [(x-A)^i e^(-a(x-A)^2)]
+    = [i (x-A)^(i-1) - 2a (x-A)^(i+1)] e^(-a(x-A)^2), and every axis integral is
+    an exact Gauss-Hermite sum, so nothing is shared with a second-derivative
+    recursion on one side."""
+    A, B = np.asarray(A, float), np.asarray(B, float)
+    p = a + b
+    P = (a * A + b * B) / p
+    K = math.exp(-a * b / p * float(np.sum((A - B) ** 2)))
+    x, w = np.polynomial.hermite.hermgauss(16)
+    s_ax, d_ax = [], []
+    for ax in range(3):
+        t = P[ax] + x / math.sqrt(p)
+        u, v = t - A[ax], t - B[ax]
+        i, j = pa[ax], pb[ax]
+        fa, fb = u ** i, v ** j
+        ga = (i * u ** (i - 1) if i > 0 else 0.0) - 2.0 * a * u ** (i + 1)
+        gb = (j * v ** (j - 1) if j > 0 else 0.0) - 2.0 * b * v ** (j + 1)
+        s_ax.append(float(np.sum(w * fa * fb)) / math.sqrt(p))
+        d_ax.append(float(np.sum(w * ga * gb)) / math.sqrt(p))
+    tot = (d_ax[0] * s_ax[1] * s_ax[2] + s_ax[0] * d_ax[1] * s_ax[2] + s_ax[0] * s_ax[1] * d_ax[2])
+    return 0.5 * K * tot

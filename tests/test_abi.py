@@ -36,28 +36,28 @@ def test_argument_errors_are_status_codes():
     lib = dfx._lib
     out = ctypes.c_void_p()
     # empty basis
-    assert lib.dfx_eri3(None, 0, None, 0, None, None, ctypes.byref(out)) == dfx.EINVAL
+    assert lib.dfx_eri3(None, 0, None, 0, None, None, 0, None, ctypes.byref(out)) == dfx.EINVAL
     assert "empty" in dfx.last_error()
     # NULL output handle
-    assert lib.dfx_eri3(None, 1, None, 1, None, None, None) == dfx.EINVAL
+    assert lib.dfx_eri3(None, 1, None, 1, None, None, 0, None, None) == dfx.EINVAL
     # l beyond the compiled classes is reported before any device work
     e = np.array([1.0]); c = np.array([1.0])
     sh = (dfx.Shell * 1)()
     sh[0].l, sh[0].nprim, sh[0].exps, sh[0].coefs = 4, 1, e.ctypes.data, c.ctypes.data
     ax = (dfx.Shell * 1)()
     ax[0].l, ax[0].nprim, ax[0].exps, ax[0].coefs = 0, 1, e.ctypes.data, c.ctypes.data
-    assert lib.dfx_eri3(sh, 1, ax, 1, None, None, ctypes.byref(out)) == dfx.EUNSUPPORTED
+    assert lib.dfx_eri3(sh, 1, ax, 1, None, None, 0, None, ctypes.byref(out)) == dfx.EUNSUPPORTED
     sh[0].l = 1
     ax[0].l = 5
-    assert lib.dfx_eri3(sh, 1, ax, 1, None, None, ctypes.byref(out)) == dfx.EUNSUPPORTED
+    assert lib.dfx_eri3(sh, 1, ax, 1, None, None, 0, None, ctypes.byref(out)) == dfx.EUNSUPPORTED
     # malformed shells
     sh[0].nprim = 0
     ax[0].l = 0
-    assert lib.dfx_eri3(sh, 1, ax, 1, None, None, ctypes.byref(out)) == dfx.EINVAL
+    assert lib.dfx_eri3(sh, 1, ax, 1, None, None, 0, None, ctypes.byref(out)) == dfx.EINVAL
     sh[0].nprim = 1
     neg = np.array([-1.0])
     sh[0].exps = neg.ctypes.data
-    assert lib.dfx_eri3(sh, 1, ax, 1, None, None, ctypes.byref(out)) == dfx.EINVAL
+    assert lib.dfx_eri3(sh, 1, ax, 1, None, None, 0, None, ctypes.byref(out)) == dfx.EINVAL
     # jk / B calls on a NULL handle
     assert lib.dfx_jk(None, None, 1, 1, 0, None, None, None) == dfx.EINVAL
     assert lib.dfx_B_info_get(None, None) == dfx.EINVAL
@@ -71,12 +71,20 @@ def test_eri3_plan_sizes_host_only():
     _, _, sh, ax = W.workload("h4")
     z = dfx.eri3_plan(sh, ax)
     assert (z["nbf"], z["naux"], z["ncols_tiled"]) == (24, 100, 1024)
-    assert z["bytes_B"] == 100 * 1024 * 8 and z["bytes_raw"] == z["bytes_B"]
-    assert z["bytes_setup_peak"] == z["bytes_B"] + z["bytes_raw"] + 3 * 100 * 100 * 8
+    assert z["bytes_B"] == 2 * 100 * 1024 * 4
+    # every pair a >= b of 16 shells (4 x (3s 1p) on H): raw columns (24^2 + 4 (3 + 9)) / 2
+    assert 0 <= z["bytes_raw"] - 100 * ((24 * 24 + 4 * 12) // 2) * 8 < 256
+    assert 0 <= z["bytes_metric"] - 2 * 100 * 100 * 8 < 2 * 256  # J_PQ and L, each 256-byte aligned
+    assert z["bytes_workspace"] >= z["bytes_persistent"] + z["bytes_jk"]
+    assert z["bytes_persistent"] >= z["bytes_B"] + 100 * 100 * 8
+    zk = dfx.eri3_plan(sh, ax, flags=dfx.KEEP_RAW | dfx.KEEP_METRIC)
+    assert zk["bytes_persistent"] >= z["bytes_persistent"] + z["bytes_raw"] + 100 * 100 * 8
     _, _, sh, ax = W.workload("water4")
     z = dfx.eri3_plan(sh, ax)
     nt = 1536 // 32
     assert (z["nbf"], z["naux"], z["ncols_tiled"]) == (1536, 6784, nt * (nt + 1) // 2 * 1024)
+    # B (65 GB) + raw bound (64 GB) + metric, well inside one GPU's 288 GB
+    assert 1.2e11 < z["bytes_workspace"] < 1.6e11
     with pytest.raises(dfx.DfxError) as e:
         dfx.eri3_plan([], ax)
     assert e.value.code == dfx.EINVAL
@@ -112,3 +120,41 @@ def test_open_shell_and_mp2_argument_errors_before_device_work():
     with pytest.raises(dfx.DfxError) as e:
         dfx.scf(xyz, Z, sh, ax, want_c=False, level_shift=0.3)
     assert e.value.code == dfx.EINVAL and "level_shift" in dfx.last_error()
+
+
+@pytest.mark.skipif(not os.path.exists(LIB), reason="libdfx.so not built")
+def test_undersized_workspace_is_enomem_before_device_work():
+    """A caller's workspace smaller than the plan is refused with DFX_ENOMEM
+    before anything touches the device (the pointer here is not device memory
+    and is never dereferenced); a NULL workspace is DFX_EINVAL."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    import systems
+    import paper_1707_03771_amd as dfx
+    lib = dfx._lib
+    xyz, Z, sh, ax, _ = systems.h4()
+    s, a = dfx._ShellArray(sh), dfx._ShellArray(ax)
+    need = dfx.eri3_plan(sh, ax)["bytes_workspace"]
+    fake = ctypes.c_void_p(0x100000)
+    out = ctypes.c_void_p()
+    for short in (0, 1, need // 2, need - 1):
+        assert lib.dfx_eri3(s.arr, s.n, a.arr, a.n, None, fake, short, None, ctypes.byref(out)) == dfx.ENOMEM
+        assert "workspace" in dfx.last_error() and str(need) in dfx.last_error()
+        assert not out.value
+    assert lib.dfx_eri3(s.arr, s.n, a.arr, a.n, None, None, need, None, ctypes.byref(out)) == dfx.EINVAL
+    # kept raw integrals need more
+    keep = dfx.Eri3Opts(1e-12, dfx.KEEP_RAW)
+    assert lib.dfx_eri3(s.arr, s.n, a.arr, a.n, ctypes.byref(keep), fake, need, None, ctypes.byref(out)) == dfx.ENOMEM
+    # the SCF drivers check opts.workspace the same way
+    sneed = dfx.scf_plan(sh, ax, len(Z))
+    assert sneed > need
+    g = dfx._GeomC(xyz, Z)
+    E = ctypes.c_double()
+    o = dfx.scf_default_opts()
+    o.workspace, o.ws_bytes = 0x100000, sneed - 1
+    assert lib.dfx_scf(ctypes.byref(g.g), s.arr, s.n, a.arr, a.n, ctypes.byref(o), None, ctypes.byref(E),
+                       None, None, None) == dfx.ENOMEM
+    assert "dfx_scf_plan" in dfx.last_error()
+    for fn in (lib.dfx_uhf, lib.dfx_rohf):
+        assert fn(ctypes.byref(g.g), s.arr, s.n, a.arr, a.n, ctypes.byref(o), 1, ctypes.byref(E), None, None,
+                  None) == dfx.ENOMEM

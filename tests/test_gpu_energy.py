@@ -1,0 +1,79 @@
+"""DF-RHF energies of the GPU path against the oracle's, at the sizes of the
+water-cluster and alkane workloads.
+
+The stored energies and their floors come from tests/golden/df_rhf_floors.json,
+written by tests/golden/make_energy_floors.py from the oracle alone.  The floor
+is how far the oracle's own energy moves when the fitting metric is perturbed
+element-wise at the rounding level (the metrics here have condition numbers of
+1e9 to 1e12): two correct FP64 fits differ by about that much.  The bound is
+the larger of 1e-8 Eh and four times the floor.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import listcheck
+import oracle as O
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "df_rhf_floors.json")
+
+
+@pytest.fixture(scope="module")
+def dfx():
+    import paper_1707_03771_amd as m
+    return m
+
+
+def _gold(name):
+    if not os.path.exists(GOLD):
+        pytest.skip("no stored oracle energies")
+    g = json.load(open(GOLD))
+    if name not in g:
+        pytest.skip(f"no stored oracle energy for {name}")
+    return g[name]
+
+
+def _workload(name):
+    return W.workload(name, seed=0) if name == "alkane" else W.workload(name)
+
+
+@pytest.mark.parametrize("name", ["water2", "water3", "alkane"])
+def test_energy_against_oracle(dfx, name):
+    gold = _gold(name)
+    elems, xyz, sh, ax = _workload(name)
+    Z = W.charges(elems)
+    bound = max(1e-8, 4.0 * gold["floor"])
+    conv = dict(conv_dE=1e-10, conv_err=1e-8, want_c=False)
+    for kw in ({}, dict(schedule=dfx.SCHED_MIXED, mixed_prec=dfx.FP32)):
+        E, _, _, info = dfx.scf(xyz, Z, sh, ax, **conv, **kw)
+        assert info["converged"] and info["nbf"] == gold["nbf"] and info["nocc"] == gold["nocc"]
+        dE = E - gold["E"]
+        print(f"{name} {kw.get('schedule', 'plain')}: E = {E:.10f}, oracle {gold['E']:.10f}, dE {dE:.2e}, "
+              f"floor {gold['floor']:.1e}, kappa {gold['kappa']:.1e}, bound {bound:.1e}")
+        assert abs(dE) <= bound
+
+
+@pytest.mark.parametrize("name", ["water3", "alkane"])
+def test_screening_lists_bit_exact(dfx, name):
+    """The integer screening lists at these sizes against the oracle's."""
+    elems, xyz, sh, ax = _workload(name)
+    bas, aux = O.Basis(sh), O.Basis(ax)
+    Qab, QC = O.schwarz(bas, aux)
+    scr = O.screen(bas, aux, Qab, QC, 1e-12)
+    B = dfx.eri3(sh, ax)
+    try:
+        pairs, off, keep, _, _ = B.lists(keep=True)
+        res = listcheck.compare_lists(bas, scr, Qab, QC, pairs, off, keep)
+        assert res["tie_pairs_differing"] == 0, res
+        assert B.info["ntriplets"] == int(scr.keep.sum())
+        # the condition number the library reports is a lower bound of the true one
+        assert B.info["kappa_lb"] <= np.linalg.cond(O.eri2(aux)) * (1 + 1e-6)
+    finally:
+        B.free()

@@ -7,6 +7,7 @@ lists and offsets are bit-exact; B, J and K meet 1e-9 absolute.
 import numpy as np
 import pytest
 
+import listcheck
 import oracle as O
 import systems
 
@@ -58,13 +59,32 @@ def test_schwarz_factors_and_lists_bit_exact(case):
     pairs, off, keep, gQab, gQC = B.lists(keep=True)
     assert np.abs(gQab - Qab).max() <= 1e-13 * Qab.max()
     assert np.abs(gQC - QC).max() <= 1e-13 * QC.max()
-    # bit-exact integer contract, unless a product sits on the threshold
-    if scr.margin > 1e-12:
-        assert np.array_equal(pairs, scr.pairs)
-        assert np.array_equal(off, scr.col_off)
-        assert np.array_equal(keep.astype(bool), scr.keep)
+    # bit-exact integer contract; only products within rounding of tau excluded
+    res = listcheck.compare_lists(bas, scr, Qab, QC, pairs, off, keep)
+    assert res["mode"] == "exact", res
     assert B.info["npairs"] == len(scr.pairs) and B.info["ncols"] == scr.col_off[-1]
     assert B.info["ntriplets"] == int(scr.keep.sum())
+
+
+# thresholds at which the oracle drops both pairs and triplets of these systems
+@pytest.mark.parametrize("name,tau", [("mixed", 1e-4), ("mixed_d", 1e-2), ("h4", 1e-4)])
+def test_lists_bit_exact_with_real_screening(dfx, name, tau):
+    """At tau = 1e-12 these small systems keep every pair; a larger threshold
+    makes the screening drop pairs and triplets, and the lists must still be
+    identical to the oracle's."""
+    sh, ax = SYSTEMS[name]()
+    bas, aux = O.Basis(sh), O.Basis(ax)
+    Qab, QC = O.schwarz(bas, aux)
+    scr = O.screen(bas, aux, Qab, QC, tau)
+    B = dfx.eri3(sh, ax, tau=tau)
+    try:
+        pairs, off, keep, _, _ = B.lists(keep=True)
+        res = listcheck.compare_lists(bas, scr, Qab, QC, pairs, off, keep)
+        assert res["mode"] == "exact", res
+        assert res["screened_pairs"] > 0 and res["screened_triplets"] > 0, res
+        assert B.info["ntriplets"] == int(scr.keep.sum())
+    finally:
+        B.free()
 
 
 def test_raw_three_index_integrals(case):

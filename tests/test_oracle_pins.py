@@ -110,6 +110,36 @@ def test_overlap_against_gauss_hermite():
     assert np.abs(S[:5, 5:] - ref).max() < 1e-14
 
 
+@pytest.mark.parametrize("la,lb", [(0, 2), (2, 2), (1, 3), (3, 2), (3, 3)])
+def test_kinetic_against_gauss_hermite(la, lb):
+    """d and f shells on both sides: the ket's j (j - 1) S(i, j - 2) term of
+    the kinetic recursion only appears for Cartesian powers j >= 2."""
+    A, B = np.array([0.2, -0.4, 0.1]), np.array([-0.3, 0.5, 0.6])
+    a, b = 0.9, 1.4
+    bas = O.Basis([_shell(A, la, [a]), _shell(B, lb, [b])])
+    _, T, _ = O.int1e(bas, np.zeros((1, 3)), [0])
+    na = 2 * la + 1
+    ca, cb = bas.coef[0], bas.coef[1]
+    pa, pb = O.cart_powers(la), O.cart_powers(lb)
+    cart = np.array([[bf.kinetic_cart(A, a, p, B, b, q) for q in pb] for p in pa]) * ca * cb
+    ref = O.solid_harmonics(la) @ cart @ O.solid_harmonics(lb).T
+    assert np.abs(T[:na, na:] - ref).max() < 1e-13 * max(1.0, np.abs(ref).max())
+    # the diagonal block of one shell: <phi| T |phi> against the same quadrature
+    cart_aa = np.array([[bf.kinetic_cart(A, a, p, A, a, q) for q in pa] for p in pa]) * ca * ca
+    ref_aa = O.solid_harmonics(la) @ cart_aa @ O.solid_harmonics(la).T
+    assert np.abs(T[:na, :na] - ref_aa).max() < 1e-13 * max(1.0, np.abs(ref_aa).max())
+
+
+def test_kinetic_pin_catches_a_dropped_term():
+    """The quadrature is sensitive to the term a dropped j (j - 1) S(i, j - 2)
+    would lose: for x^2 e^(-b x^2) against itself that term is 2 S(2, 0), which
+    is not small next to the total."""
+    A = np.zeros(3)
+    full = bf.kinetic_cart(A, 1.1, (2, 0, 0), A, 1.1, (2, 0, 0))
+    dropped = full - (-0.5) * 2 * bf.overlap_cart(A, 1.1, (2, 0, 0), A, 1.1, (0, 0, 0))
+    assert abs(full - dropped) > 1e-2 * abs(full)
+
+
 def test_h2_sto3g_textbook():
     g = json.load(open(os.path.join(GOLD, "h2_sto3g.json")))
     xyz = np.array([[0, 0, 0], [0, 0, g["R_bohr"]]], float)
