@@ -219,6 +219,29 @@ int dfx_jk(const dfx_B* b, const double* dev_in, int kind, int nocc, int precisi
            double* dev_K, void* stream);
 
 /*
+ * dfx_jk_noalloc -- dfx_jk for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it): the
+ * same J and K, from C_occ only, with the builds' scratch in a device array
+ * that the library holds on every GPU it runs on, DFX_NOALLOC_SCRATCH_MIB
+ * mebibytes per GPU, until the process ends.  It calls no hipMalloc / hipFree
+ * and no allocating library routine, and does not touch B's workspace.
+ *   dev_C      C_occ [nbf][nocc] device, 1 <= nocc <= min(nbf, 512)
+ *   precision  as dfx_jk; dev_J, dev_K outputs as dfx_jk (either may be NULL)
+ * The exchange build cuts the auxiliary index into as many chunks as the array
+ * takes (more launches than dfx_jk for large systems; the sums run in another
+ * order, so K agrees with dfx_jk to rounding, J bit for bit).  Sizes beyond
+ * the array (about nbf > 2000) are rejected with DFX_ENOMEM before any work.
+ * Every call on one GPU shares the array and it keeps the last call's
+ * contents (nothing in it needs to start at zero): calls that overlap on one
+ * GPU, on different streams or host threads, race and must be serialised by
+ * the caller.  Enqueued on stream.
+ * Errors: DFX_EINVAL, DFX_EUNSUPPORTED (nocc > 512), DFX_ENOMEM, DFX_EHIP.
+ */
+#define DFX_NOALLOC_SCRATCH_MIB 256
+int dfx_jk_noalloc(const dfx_B* b, const double* dev_C, int nocc, int precision, double* dev_J, double* dev_K,
+                   void* stream);
+
+/*
  * dfx_mp2 -- DF-MP2 correlation energy of a closed-shell RHF reference (section
  * "Standard algorithms": MP2 as a post-HF method, on the density-fitting
  * operations of Eqs. (1) and (2)):

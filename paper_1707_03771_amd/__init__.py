@@ -117,6 +117,7 @@ _SIGS = {
     "dfx_B_metric": [_vp, _i, _vp, _vp],
     "dfx_B_free": [_vp],
     "dfx_jk": [_vp, _vp, _i, _i, _i, _vp, _vp, _vp],
+    "dfx_jk_noalloc": [_vp, _vp, _i, _i, _vp, _vp, _vp],
     "dfx_mp2": [_vp, _vp, _i, _vp, _i, _i, _vp, _vp],
     "dfx_int1e": [_vp, _i, _vp, _vp, _vp, _vp, _vp],
     "dfx_scf": [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _vp, _vp, _vp],
@@ -297,6 +298,23 @@ def jk(B, x, kind=COCC, nocc=None, precision=FP64, want_j=True, want_k=True, str
     _check(_lib.dfx_jk(B.h, _ptr(x), kind, nocc, precision, _ptr(J) if want_j else None,
                        _ptr(K) if want_k else None, _stream(stream)))
     return J, K
+
+
+def jk_noalloc(B, C, precision=FP64, want_j=True, want_k=True, J=None, K=None, stream=None):
+    """dfx_jk_noalloc: J and K from C_occ with the library's fixed device scratch
+    (no device allocation in the library).  J, K: (nbf, nbf) float64 cuda
+    outputs, allocated here unless given."""
+    import torch
+    if C.dtype != torch.float64 or not C.is_cuda or not C.is_contiguous():
+        raise ValueError("jk_noalloc: C must be a contiguous float64 cuda tensor")
+    n = B.nbf
+    if want_j and J is None:
+        J = torch.empty((n, n), dtype=torch.float64, device=C.device)
+    if want_k and K is None:
+        K = torch.empty((n, n), dtype=torch.float64, device=C.device)
+    _check(_lib.dfx_jk_noalloc(B.h, _ptr(C), C.shape[1], precision, _ptr(J) if want_j else None,
+                               _ptr(K) if want_k else None, _stream(stream)))
+    return (J if want_j else None), (K if want_k else None)
 
 
 def mp2(B, C, eps, nocc, nfrozen=0, stream=None):

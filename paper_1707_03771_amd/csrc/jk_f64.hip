@@ -8,6 +8,8 @@
 // global loads of the next k-stage before the MFMAs of the current one.
 #include <algorithm>
 
+#include <string>
+
 #include "kernels.h"
 
 namespace dfx {
@@ -269,12 +271,29 @@ struct F64Plan {
   size_t x_bytes, p_bytes, c_bytes;
 };
 
+static size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
+
 // X chunks of at most 8 GiB, balanced over the chunks; enough SYRK slices (a
-// multiple of 8) to give the chip ~2048 workgroups, partial sums within 2 GiB
+// multiple of 8) to give the chip ~2048 workgroups, partial sums within 2 GiB.
+// Under a work cap: eight slices and X in what the cap leaves.
 static F64Plan f64_plan(const JKArgs& a, int nocc) {
   F64Plan p{};
   const size_t per_q = (size_t)a.nbf * nocc * sizeof(double);
-  size_t cap = ((size_t)8 << 30) / per_q;
+  p.np = 64 * ((nocc + 63) / 64);
+  p.nbfp = ntiles_for(a.nbf) * TILE;
+  p.c_bytes = (size_t)p.nbfp * p.np * sizeof(double);
+  size_t xbytes = (size_t)8 << 30;
+  int64_t by_mem = ((int64_t)2 << 30) / ((int64_t)a.nbf * a.nbf * 8);
+  if (a.ws_cap) {
+    // eight slices, C, the row padding of X (7 doubles per row) and alignment
+    const size_t fixed = a256((size_t)8 * a.nbf * a.nbf * 8) + p.c_bytes + (size_t)a.nbf * 56 + 1024;
+    if (a.ws_cap < fixed + per_q)
+      throw Error(DFX_ENOMEM, "K work: " + std::to_string(a.ws_cap) + " bytes hold no chunk (" +
+                                  std::to_string(fixed + per_q) + " needed)");
+    xbytes = a.ws_cap - fixed;
+    by_mem = 8;
+  }
+  size_t cap = xbytes / per_q;
   if (cap < 1) cap = 1;
   const int nchunks = (int)((a.naux + cap - 1) / cap);
   p.qc = (a.naux + nchunks - 1) / nchunks;
@@ -283,19 +302,13 @@ static F64Plan f64_plan(const JKArgs& a, int nocc) {
   const int mt = (a.nbf + 127) / 128;
   p.ntl = mt * (mt + 1) / 2;
   int64_t ns = (2048 + p.ntl - 1) / p.ntl;
-  const int64_t by_mem = ((int64_t)2 << 30) / ((int64_t)a.nbf * a.nbf * 8);
   const int64_t by_len = (kdim + S64 - 1) / S64;  // at least one stage per slice
   ns = std::min(ns, std::max<int64_t>(1, std::min(by_mem, by_len)));
   p.ns = (int)(((ns + 7) / 8) * 8);
   p.x_bytes = (size_t)a.nbf * p.ldx * sizeof(double);
   p.p_bytes = (size_t)p.ns * a.nbf * a.nbf * sizeof(double);
-  p.np = 64 * ((nocc + 63) / 64);
-  p.nbfp = ntiles_for(a.nbf) * TILE;
-  p.c_bytes = (size_t)p.nbfp * p.np * sizeof(double);
   return p;
 }
-
-static size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 size_t half_transform_f64_work(const JKArgs& a, int nocc) {
   const F64Plan p = f64_plan(a, nocc);

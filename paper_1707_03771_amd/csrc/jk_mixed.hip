@@ -7,6 +7,8 @@
 // X is written in the compute precision.  Phase 2 is a split-K SYRK over the
 // (Q, i) index: FP32 MFMA sums of KT products, added up in FP64, reduced over
 // the slices in FP64 in a fixed order.
+#include <string>
+
 #include "kernels.h"
 
 namespace dfx {
@@ -304,7 +306,17 @@ static MixedPlan mixed_plan(const JKArgs& a, int nocc, size_t esize) {
   p.npad = 64 * p.ncb;
   p.nbfp = ntiles_for(a.nbf) * TILE;
   const size_t per_q = (size_t)a.nbf * nocc * esize;
-  size_t cap = ((size_t)2 << 30) / per_q;
+  size_t xbytes = (size_t)2 << 30;
+  if (a.ws_cap) {
+    // C, eight partial-sum slices, the row padding of X and alignment
+    const size_t fixed = (size_t)p.npad * p.nbfp * esize + (size_t)8 * a.nbf * a.nbf * 8 + (size_t)a.nbf * 8 * esize +
+                         1024 + 512;
+    if (a.ws_cap < fixed + per_q)
+      throw Error(DFX_ENOMEM, "K work: " + std::to_string(a.ws_cap) + " bytes hold no chunk (" +
+                                  std::to_string(fixed + per_q) + " needed)");
+    xbytes = a.ws_cap - fixed;
+  }
+  size_t cap = xbytes / per_q;
   if (cap < 1) cap = 1;
   p.qc = (int)std::min<size_t>(cap, (size_t)a.naux);
   p.kdim = (int64_t)p.qc * nocc;
@@ -316,7 +328,7 @@ static MixedPlan mixed_plan(const JKArgs& a, int nocc, size_t esize) {
   ns = ((ns + 7) / 8) * 8;
   const int64_t maxs = (p.kdim + KT - 1) / KT;
   if (ns > maxs) ns = (int)(((maxs + 7) / 8) * 8);
-  if (ns < 8) ns = 8;
+  if (ns < 8 || a.ws_cap) ns = 8;
   p.ns = ns;
   p.kslice = ((p.kdim + ns - 1) / ns + KT - 1) / KT * KT;
   p.ct_bytes = (size_t)p.npad * p.nbfp * esize;

@@ -90,6 +90,11 @@ struct JKArgs {
   int naux, nbf;
   int64_t ncols;   // tiled columns
   int prec;
+  // K work cap in bytes (0: the default chunk sizes).  With a cap the
+  // auxiliary index is cut into as many chunks as it takes for k_work_bytes to
+  // stay within it, and the SYRK keeps eight partial-sum slices; DFX_ENOMEM if
+  // even one auxiliary function per chunk does not fit.
+  size_t ws_cap = 0;
 };
 void j_build(const JKArgs& a, const double* D, double* J, double* work, hipStream_t st);
 // K from the occupied block C [nbf][nocc] (row-major); work >= k_work_bytes
