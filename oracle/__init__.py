@@ -17,7 +17,9 @@ algorithms" for DF-based RHF):
 * J = sum_Q B_Q gamma_Q with gamma_Q = sum_{mu nu} B_Q,mu nu D_mu nu -- Eq. (3a)
   then (3b);
 * K = sum_Q (B_Q C)(B_Q C)^T -- Eq. (1a) then (2a);
-* a DIIS-accelerated restricted SCF built on these.
+* a DIIS-accelerated restricted SCF built on these;
+* the analytic nuclear gradient of that SCF energy (``grad.py``, with the
+  McMurchie-Davidson derivative integrals of ``md_ints.c``).
 
 Textbook parts the paper does not spell out (Boys function, Hermite
 recursions, Pulay DIIS, canonical orthogonalisation) follow Helgaker,

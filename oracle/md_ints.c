@@ -477,3 +477,336 @@ void oracle_int1e(const obasis *bs, int nbf, int natom, const double *xyz, const
     }
   }
 }
+
+/* ======================================================================
+ * Nuclear-coordinate derivatives (the analytic gradient of DF-RHF).
+ *
+ * Moving the centre A of a Cartesian Gaussian x_A^i exp(-alpha x_A^2)
+ * differentiates it into
+ *     d/dA_x = 2 alpha x_A^{i+1} e^{..} - i x_A^{i-1} e^{..},
+ * so every derivative integral is a combination of ordinary integrals with
+ * one power raised or lowered on the moved centre, primitive by primitive.
+ * The contractions below weight the derivative blocks of all shell pairs and
+ * triplets with dense spherical weight arrays and sum into per-atom
+ * gradients.  Each centre is differentiated directly (no translational
+ * shortcut), so the translational sum rule is a test of the code.
+ * ====================================================================== */
+
+/* primitive Cartesian (ab|cd) without the 2 pi^{5/2}/(p q sqrt(p+q)) prefactor,
+   for arbitrary power triples, from the Hermite expansions and R */
+static double prim_eri(const hprod *hb, const hprod *hk, const double *R, const int *a, const int *b,
+                       const int *c, const int *d) {
+  double s = 0.0;
+  for (int t = 0; t <= a[0] + b[0]; ++t)
+    for (int u = 0; u <= a[1] + b[1]; ++u)
+      for (int v = 0; v <= a[2] + b[2]; ++v) {
+        const double eb = hb->Ex[a[0]][b[0]][t] * hb->Ey[a[1]][b[1]][u] * hb->Ez[a[2]][b[2]][v];
+        if (eb == 0.0) continue;
+        double sk = 0.0;
+        for (int tt = 0; tt <= c[0] + d[0]; ++tt)
+          for (int uu = 0; uu <= c[1] + d[1]; ++uu)
+            for (int vv = 0; vv <= c[2] + d[2]; ++vv) {
+              const double ek = hk->Ex[c[0]][d[0]][tt] * hk->Ey[c[1]][d[1]][uu] * hk->Ez[c[2]][d[2]][vv];
+              const double sg = ((tt + uu + vv) & 1) ? -1.0 : 1.0;
+              sk += sg * ek * R[RIX(t + tt, u + uu, v + vv)];
+            }
+        s += eb * sk;
+      }
+  return s;
+}
+
+/* d(ab|cd)/d(centre `which`)_k, k = x, y, z, spherical: out [3][sa][sb][sc][sd].
+   which: 0 = A, 1 = B, 2 = C, 3 = D.  A unit shell (the constant 1) has no
+   derivative and is never the moved shell here. */
+static void eri_generic_deriv(const oshell *A, const oshell *B, const oshell *C, const oshell *D, int which,
+                              double *out) {
+  const oshell *S[4] = {A, B, C, D};
+  int l[4], n[4];
+  for (int s = 0; s < 4; ++s) { l[s] = S[s]->l; n[s] = ncart(l[s]); }
+  int pw[4][28][3];
+  for (int s = 0; s < 4; ++s) cart_powers(l[s], pw[s]);
+  const int ntot = n[0] * n[1] * n[2] * n[3];
+  double *cart = (double *)calloc(3 * ntot, sizeof(double));
+  double *R = (double *)malloc(sizeof(double) * RD * RD * RD);
+  hprod *hb = (hprod *)malloc(sizeof(hprod));
+  hprod *hk = (hprod *)malloc(sizeof(hprod));
+  const int L = l[0] + l[1] + l[2] + l[3] + 1;
+  const int up0 = which == 0, up1 = which == 1, up2 = which == 2, up3 = which == 3;
+  for (int ia = 0; ia < A->nprim; ++ia)
+    for (int ib = 0; ib < B->nprim; ++ib) {
+      make_prod(hb, l[0] + up0, l[1] + up1, A->exps[ia], A->ctr, B->exps[ib], B->ctr);
+      const double cab = A->coef[ia] * B->coef[ib];
+      for (int ic = 0; ic < C->nprim; ++ic)
+        for (int id = 0; id < D->nprim; ++id) {
+          make_prod(hk, l[2] + up2, l[3] + up3, C->exps[ic], C->ctr, D->exps[id], D->ctr);
+          const double p = hb->p, q = hk->p, alpha = p * q / (p + q);
+          hermite_R(L, alpha, hb->P[0] - hk->P[0], hb->P[1] - hk->P[1], hb->P[2] - hk->P[2], R);
+          const double pref = cab * C->coef[ic] * D->coef[id] * 2.0 * pow(PI, 2.5) / (p * q * sqrt(p + q));
+          const double ex = which == 0 ? A->exps[ia] : which == 1 ? B->exps[ib] : which == 2 ? C->exps[ic]
+                                                                                              : D->exps[id];
+          int idx = 0;
+          for (int a = 0; a < n[0]; ++a)
+            for (int b = 0; b < n[1]; ++b)
+              for (int c = 0; c < n[2]; ++c)
+                for (int d = 0; d < n[3]; ++d, ++idx) {
+                  int q4[4][3];
+                  memcpy(q4[0], pw[0][a], sizeof q4[0]);
+                  memcpy(q4[1], pw[1][b], sizeof q4[1]);
+                  memcpy(q4[2], pw[2][c], sizeof q4[2]);
+                  memcpy(q4[3], pw[3][d], sizeof q4[3]);
+                  for (int k = 0; k < 3; ++k) {
+                    int *w = q4[which];
+                    const int i0 = w[k];
+                    w[k] = i0 + 1;
+                    double v = 2.0 * ex * prim_eri(hb, hk, R, q4[0], q4[1], q4[2], q4[3]);
+                    if (i0 > 0) {
+                      w[k] = i0 - 1;
+                      v -= i0 * prim_eri(hb, hk, R, q4[0], q4[1], q4[2], q4[3]);
+                    }
+                    w[k] = i0;
+                    cart[k * ntot + idx] += pref * v;
+                  }
+                }
+        }
+    }
+  const int sa = 2 * l[0] + 1, sb = B->unit ? 1 : 2 * l[1] + 1, sc = 2 * l[2] + 1, sd = D->unit ? 1 : 2 * l[3] + 1;
+  const int nsph = sa * sb * sc * sd;
+  double *t1 = (double *)malloc(sizeof(double) * ntot);
+  double *t2 = (double *)malloc(sizeof(double) * ntot);
+  for (int k = 0; k < 3; ++k) {
+    sph_index(cart + k * ntot, t1, 1, l[0], n[1] * n[2] * n[3]);
+    if (B->unit) memcpy(t2, t1, sizeof(double) * sa * n[2] * n[3]);
+    else sph_index(t1, t2, sa, l[1], n[2] * n[3]);
+    sph_index(t2, t1, sa * sb, l[2], n[3]);
+    if (D->unit) memcpy(out + k * nsph, t1, sizeof(double) * nsph);
+    else sph_index(t1, out + k * nsph, sa * sb * sc, l[3], 1);
+  }
+  free(t1); free(t2); free(cart); free(R); free(hb); free(hk);
+}
+
+/* d(ab|P)/dR of one triplet: out [3 centres A, B, P][3 axes][na][nb][nP] */
+void oracle_eri3_deriv_block(const obasis *bs, int a, int b, const obasis *ax, int c, double *out) {
+  oshell A = get_shell(bs, a), B = get_shell(bs, b), C = get_shell(ax, c);
+  oshell D = unit_shell(C.ctr);
+  const int blk = 3 * nsph_of(bs, a) * nsph_of(bs, b) * nsph_of(ax, c);
+  eri_generic_deriv(&A, &B, &C, &D, 0, out);
+  eri_generic_deriv(&A, &B, &C, &D, 1, out + blk);
+  eri_generic_deriv(&A, &B, &C, &D, 2, out + 2 * blk);
+}
+
+/* d(P|Q)/dR: out [2 centres P, Q][3 axes][nP][nQ] */
+void oracle_eri2_deriv_block(const obasis *ax, int p, int q, double *out) {
+  oshell A = get_shell(ax, p), C = get_shell(ax, q);
+  oshell B = unit_shell(A.ctr), D = unit_shell(C.ctr);
+  const int blk = 3 * nsph_of(ax, p) * nsph_of(ax, q);
+  eri_generic_deriv(&A, &B, &C, &D, 0, out);
+  eri_generic_deriv(&A, &B, &C, &D, 2, out + blk);
+}
+
+/* grad[atom][k] += sum_{mu nu P} Gam[P][mu][nu] d(mu nu|P)/dR_atom,k over all
+   shells a, b (both orders) and auxiliary shells C; Gam dense [naux][nbf][nbf]. */
+void oracle_eri3_grad(const obasis *bs, int nbf, const obasis *ax, int naux, const int *atom_bs,
+                      const int *atom_ax, int natom, const double *Gam, double *grad) {
+  for (int i = 0; i < 3 * natom; ++i) grad[i] = 0.0;
+#pragma omp parallel
+  {
+    double *g = (double *)calloc(3 * natom, sizeof(double));
+    double *blk = (double *)malloc(sizeof(double) * 9 * 13 * 13 * 9);
+#pragma omp for schedule(dynamic) collapse(2)
+    for (int a = 0; a < bs->nsh; ++a)
+      for (int b = 0; b < bs->nsh; ++b) {
+        const int na = nsph_of(bs, a), nb = nsph_of(bs, b);
+        for (int C = 0; C < ax->nsh; ++C) {
+          const int nc = nsph_of(ax, C), bl = na * nb * nc;
+          oracle_eri3_deriv_block(bs, a, b, ax, C, blk);
+          const int at[3] = {atom_bs[a], atom_bs[b], atom_ax[C]};
+          for (int w = 0; w < 3; ++w)
+            for (int k = 0; k < 3; ++k) {
+              double s = 0.0;
+              for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j)
+                  for (int m = 0; m < nc; ++m)
+                    s += Gam[((size_t)(ax->foff[C] + m) * nbf + bs->foff[a] + i) * nbf + bs->foff[b] + j] *
+                         blk[(w * 3 + k) * bl + (i * nb + j) * nc + m];
+              g[3 * at[w] + k] += s;
+            }
+        }
+      }
+#pragma omp critical
+    for (int i = 0; i < 3 * natom; ++i) grad[i] += g[i];
+    free(g); free(blk);
+  }
+}
+
+/* grad[atom][k] += sum_{PQ} Gam2[P][Q] d(P|Q)/dR_atom,k; Gam2 dense [naux][naux] */
+void oracle_eri2_grad(const obasis *ax, int naux, const int *atom_ax, int natom, const double *Gam2,
+                      double *grad) {
+  for (int i = 0; i < 3 * natom; ++i) grad[i] = 0.0;
+#pragma omp parallel
+  {
+    double *g = (double *)calloc(3 * natom, sizeof(double));
+    double blk[2 * 3 * 81];
+#pragma omp for schedule(dynamic) collapse(2)
+    for (int p = 0; p < ax->nsh; ++p)
+      for (int q = 0; q < ax->nsh; ++q) {
+        const int np = nsph_of(ax, p), nq = nsph_of(ax, q), bl = np * nq;
+        oracle_eri2_deriv_block(ax, p, q, blk);
+        const int at[2] = {atom_ax[p], atom_ax[q]};
+        for (int w = 0; w < 2; ++w)
+          for (int k = 0; k < 3; ++k) {
+            double s = 0.0;
+            for (int i = 0; i < np; ++i)
+              for (int j = 0; j < nq; ++j)
+                s += Gam2[(size_t)(ax->foff[p] + i) * naux + ax->foff[q] + j] * blk[(w * 3 + k) * bl + i * nq + j];
+            g[3 * at[w] + k] += s;
+          }
+      }
+#pragma omp critical
+    for (int i = 0; i < 3 * natom; ++i) grad[i] += g[i];
+    free(g);
+  }
+}
+
+/* ---- one-electron derivatives ----
+ * Primitive Cartesian S, T and V_C for arbitrary powers i (on A) and j (on B),
+ * from the Hermite expansion of the product (E up to i + 1 and j + 3). */
+static double prim_S(const hprod *h, const int *i, const int *j) {
+  const double s1 = sqrt(PI / h->p);
+  return h->Ex[i[0]][j[0]][0] * h->Ey[i[1]][j[1]][0] * h->Ez[i[2]][j[2]][0] * s1 * s1 * s1;
+}
+
+static double prim_T(const hprod *h, const int *i, const int *j, double b) {
+  /* <i| -1/2 d^2/dx^2 |j> per axis: 4b^2 S(i,j+2) - 2b(2j+1) S(i,j) + j(j-1) S(i,j-2) */
+  const double s1 = sqrt(PI / h->p);
+  double S1[3], D1[3];
+  for (int k = 0; k < 3; ++k) {
+    double (*E)[ED][2 * ED] = (double (*)[ED][2 * ED])(k == 0 ? h->Ex : (k == 1 ? h->Ey : h->Ez));
+    const int ii = i[k], jj = j[k];
+    S1[k] = E[ii][jj][0] * s1;
+    double d = 4.0 * b * b * E[ii][jj + 2][0] * s1 - 2.0 * b * (2 * jj + 1) * S1[k];
+    if (jj >= 2) d += jj * (jj - 1) * E[ii][jj - 2][0] * s1;
+    D1[k] = d;
+  }
+  return -0.5 * (D1[0] * S1[1] * S1[2] + S1[0] * D1[1] * S1[2] + S1[0] * S1[1] * D1[2]);
+}
+
+static double prim_V(const hprod *h, const double *R, const int *i, const int *j) {
+  /* <i| 1/|r - C| |j> without the charge: 2 pi / p sum E E E R */
+  double s = 0.0;
+  for (int t = 0; t <= i[0] + j[0]; ++t)
+    for (int u = 0; u <= i[1] + j[1]; ++u)
+      for (int v = 0; v <= i[2] + j[2]; ++v)
+        s += h->Ex[i[0]][j[0]][t] * h->Ey[i[1]][j[1]][u] * h->Ez[i[2]][j[2]][v] * R[RIX(t, u, v)];
+  return 2.0 * PI / h->p * s;
+}
+
+/* d/dC_k of <i| 1/|r - C| |j>: R_tuv depends on P - C, and d R_tuv / dC_x = -R_t+1,u,v */
+static double prim_V_dC(const hprod *h, const double *R, const int *i, const int *j, int k) {
+  double s = 0.0;
+  for (int t = 0; t <= i[0] + j[0]; ++t)
+    for (int u = 0; u <= i[1] + j[1]; ++u)
+      for (int v = 0; v <= i[2] + j[2]; ++v)
+        s += h->Ex[i[0]][j[0]][t] * h->Ey[i[1]][j[1]][u] * h->Ez[i[2]][j[2]][v] *
+             R[RIX(t + (k == 0), u + (k == 1), v + (k == 2))];
+  return -2.0 * PI / h->p * s;
+}
+
+/* Gradient of 2 tr(D h) - 2 tr(W S) over all shell pairs (both orders), h = T + V,
+   V = -sum_C Z_C / |r - C|: the derivatives of the basis functions on both
+   centres, and of the operator on every nucleus C (moving C by itself).
+   Dw, Ww dense [nbf][nbf], already carrying their factors (2 D, 2 W). */
+void oracle_int1e_grad(const obasis *bs, int nbf, const int *atom_bs, int natom, const double *xyz,
+                       const double *Z, const double *Dw, const double *Ww, double *grad) {
+  for (int i = 0; i < 3 * natom; ++i) grad[i] = 0.0;
+#pragma omp parallel
+  {
+    double *g = (double *)calloc(3 * natom, sizeof(double));
+    double *R = (double *)malloc(sizeof(double) * RD * RD * RD);
+    hprod *h = (hprod *)malloc(sizeof(hprod));
+#pragma omp for schedule(dynamic) collapse(2)
+    for (int sa = 0; sa < bs->nsh; ++sa)
+      for (int sb = 0; sb < bs->nsh; ++sb) {
+        const oshell A = get_shell(bs, sa), B = get_shell(bs, sb);
+        const int la = A.l, lb = B.l, na = ncart(la), nb = ncart(lb), ma = 2 * la + 1, mb = 2 * lb + 1;
+        int pa[28][3], pb[28][3];
+        cart_powers(la, pa); cart_powers(lb, pb);
+        /* Cartesian weights: Wd = T_a^T Dw_block T_b, likewise Ws */
+        double cd[28 * 28], cs[28 * 28];
+        for (int i = 0; i < na; ++i)
+          for (int j = 0; j < nb; ++j) {
+            double sd = 0.0, ss = 0.0;
+            for (int m = 0; m < ma; ++m)
+              for (int nn = 0; nn < mb; ++nn) {
+                const double t = g_sph[la][m * na + i] * g_sph[lb][nn * nb + j];
+                const size_t o = (size_t)(bs->foff[sa] + m) * nbf + bs->foff[sb] + nn;
+                sd += t * Dw[o];
+                ss += t * Ww[o];
+              }
+            cd[i * nb + j] = sd;
+            cs[i * nb + j] = ss;
+          }
+        for (int ia = 0; ia < A.nprim; ++ia)
+          for (int ib = 0; ib < B.nprim; ++ib) {
+            const double a = A.exps[ia], b = B.exps[ib], w = A.coef[ia] * B.coef[ib];
+            make_prod(h, la + 1, lb + 3, a, A.ctr, b, B.ctr);
+            /* basis-function derivatives on A and on B: S, T, and V of every nucleus */
+            for (int i = 0; i < na; ++i)
+              for (int j = 0; j < nb; ++j) {
+                const double wd = cd[i * nb + j], ws = cs[i * nb + j];
+                for (int mv = 0; mv < 2; ++mv) {          /* 0: centre A moves, 1: centre B */
+                  const double ex = mv == 0 ? a : b;
+                  const int at = mv == 0 ? atom_bs[sa] : atom_bs[sb];
+                  for (int k = 0; k < 3; ++k) {
+                    int ii[3] = {pa[i][0], pa[i][1], pa[i][2]}, jj[3] = {pb[j][0], pb[j][1], pb[j][2]};
+                    int *q = mv == 0 ? ii : jj;
+                    const int i0 = q[k];
+                    q[k] = i0 + 1;
+                    double dS = 2.0 * ex * prim_S(h, ii, jj), dT = 2.0 * ex * prim_T(h, ii, jj, b);
+                    if (i0 > 0) {
+                      q[k] = i0 - 1;
+                      dS -= i0 * prim_S(h, ii, jj);
+                      dT -= i0 * prim_T(h, ii, jj, b);
+                    }
+                    g[3 * at + k] += w * (wd * dT - ws * dS);
+                  }
+                }
+              }
+            for (int C = 0; C < natom; ++C) {
+              const double *Cc = xyz + 3 * C;
+              hermite_R(la + lb + 1, h->p, h->P[0] - Cc[0], h->P[1] - Cc[1], h->P[2] - Cc[2], R);
+              for (int i = 0; i < na; ++i)
+                for (int j = 0; j < nb; ++j) {
+                  const double wd = cd[i * nb + j];
+                  if (wd == 0.0) continue;
+                  double dv[2][3];
+                  for (int mv = 0; mv < 2; ++mv) {
+                    const double ex = mv == 0 ? a : b;
+                    for (int k = 0; k < 3; ++k) {
+                      int ii[3] = {pa[i][0], pa[i][1], pa[i][2]}, jj[3] = {pb[j][0], pb[j][1], pb[j][2]};
+                      int *q = mv == 0 ? ii : jj;
+                      const int i0 = q[k];
+                      q[k] = i0 + 1;
+                      double v = 2.0 * ex * prim_V(h, R, ii, jj);
+                      if (i0 > 0) {
+                        q[k] = i0 - 1;
+                        v -= i0 * prim_V(h, R, ii, jj);
+                      }
+                      dv[mv][k] = -Z[C] * v;
+                    }
+                  }
+                  const int ii[3] = {pa[i][0], pa[i][1], pa[i][2]}, jj[3] = {pb[j][0], pb[j][1], pb[j][2]};
+                  for (int k = 0; k < 3; ++k) {
+                    g[3 * atom_bs[sa] + k] += w * wd * dv[0][k];
+                    g[3 * atom_bs[sb] + k] += w * wd * dv[1][k];
+                    /* the operator's own derivative: nucleus C moving alone */
+                    g[3 * C + k] += w * wd * -Z[C] * prim_V_dC(h, R, ii, jj, k);
+                  }
+                }
+            }
+          }
+      }
+#pragma omp critical
+    for (int i = 0; i < 3 * natom; ++i) grad[i] += g[i];
+    free(g); free(R); free(h);
+  }
+}
