@@ -410,6 +410,44 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
             dfx_scf_info* info);
 
 /*
+ * dfx_rhf_grad -- analytic nuclear gradient of the DF-RHF energy (section
+ * "Standard algorithms" lists analytic gradients of the SCF methods; section
+ * "Molecular integrals" the integral derivatives) at converged orbitals:
+ *   dE/dR = 2 tr(D h^x) - 2 tr(W S^x) + dE_nn/dx
+ *         + sum Gam_P,mu nu (mu nu|P)^x + sum Gam2_PQ (P|Q)^x,
+ *   D = C_occ C_occ^T, W = C_occ diag(eps_occ) C_occ^T,
+ *   Gam = L^-T (4 gamma_Q D - 2 C_occ b_Q C_occ^T), b_Q = C_occ^T B_Q C_occ, gamma = B d,
+ *   Gam2 = L^-T (-2 gamma gamma^T + sum_ij b_ij b_ij^T) L^-1,
+ * for the fitted tensor of dfx_eri3 with opts->tau (the integrals of screened
+ * triplets are dropped from the derivative as from the energy).  Every shell
+ * moves with the atom of geom whose coordinates equal its centre exactly.
+ *   opts        tau and workspace as for dfx_scf (workspace sized by dfx_grad_plan)
+ *   C_occ       host [nbf][nocc]: the occupied orbitals of a converged dfx_scf
+ *               (its C's first nocc columns), eps_occ host [nocc] their levels
+ *   grad        host [natom][3] out, Eh/bohr
+ *   info        may be NULL: GPU times of the weights, the three-index and metric
+ *               derivatives and the one-electron terms, and the wall time
+ * FP64 throughout.  Synchronous.  Errors: DFX_EINVAL (NULL, bad nocc, a shell
+ * off every atom), DFX_EUNSUPPORTED (nocc > 512, l beyond the compiled
+ * classes), DFX_ENOMEM, DFX_EHIP, DFX_ENOTPOSDEF.
+ */
+typedef struct {
+  int32_t natom;
+  double t_setup;        /* B (integrals, metric, fit) */
+  double t_weights;      /* D, W, gamma, Gam and Gam2 */
+  double t_deriv3;       /* three-index derivative integrals with their contraction */
+  double t_deriv2;       /* metric derivative integrals */
+  double t_onee;         /* one-electron derivative terms */
+  double t_total;        /* wall time of the call */
+} dfx_grad_info;
+int dfx_rhf_grad(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh,
+                 const dfx_scf_opts* opts, const double* C_occ, const double* eps_occ, int nocc, double* grad,
+                 dfx_grad_info* info);
+/* bytes of dfx_scf_opts.workspace for dfx_rhf_grad (an upper bound; host only) */
+int dfx_grad_plan(const dfx_shell* shells, int nsh, const dfx_shell* aux, int nauxsh, int natom, int nocc,
+                  int64_t* bytes);
+
+/*
  * dfx_uhf -- DF-UHF (section "Standard algorithms" lists unrestricted Hartree-Fock
  * among the SCF methods): the Pople-Nesbet equations on the same fitted tensor as
  * dfx_scf.  With n_alpha = (nelec + multiplicity - 1) / 2 and n_beta = nelec - n_alpha,

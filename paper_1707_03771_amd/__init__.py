@@ -101,6 +101,12 @@ class Eri3Sizes(ctypes.Structure):
                 ("bytes_workspace", ctypes.c_int64)]
 
 
+class GradInfo(ctypes.Structure):
+    _fields_ = [("natom", ctypes.c_int32), ("t_setup", ctypes.c_double), ("t_weights", ctypes.c_double),
+                ("t_deriv3", ctypes.c_double), ("t_deriv2", ctypes.c_double), ("t_onee", ctypes.c_double),
+                ("t_total", ctypes.c_double)]
+
+
 class GuessSpec(ctypes.Structure):
     _fields_ = [("nelem", ctypes.c_int32), ("Z", ctypes.c_void_p), ("nshell", ctypes.c_void_p),
                 ("shell_l", ctypes.c_void_p), ("rc", ctypes.c_double), ("rc_env", ctypes.c_double),
@@ -135,6 +141,8 @@ _SIGS = {
     "dfx_guess_export": [_vp, _i, _vp, _vp, _vp, _vp, _vp],
     "dfx_eri3_plan": [_vp, _i, _vp, _i, _vp, _vp],
     "dfx_scf_plan": [_vp, _i, _vp, _i, _i, _vp, _vp],
+    "dfx_grad_plan": [_vp, _i, _vp, _i, _i, _i, _vp],
+    "dfx_rhf_grad": [_vp, _vp, _i, _vp, _i, _vp, _vp, _vp, _i, _vp, _vp],
     "dfx_B_unpack": [_vp, _i, _i, _vp, _vp],
     "dfx_lowdin": [_vp, _vp, _i, _vp, _vp, _vp],
     "dfx_guess_samples": [_vp, _i, _vp, _vp],
@@ -383,11 +391,12 @@ def scf_plan(shells, aux, natom, diis_size=8):
 _SCF_WS = {}
 
 
-def _scf_workspace(o, shells, aux, natom):
+def _scf_workspace(o, shells, aux, natom, need=None):
     import torch
     if not torch.cuda.is_available():
         return None  # the library then reports the missing device itself
-    need = scf_plan(shells, aux, natom, o.diis_size)
+    if need is None:
+        need = scf_plan(shells, aux, natom, o.diis_size)
     dev = torch.cuda.current_device()
     ws = _SCF_WS.get(dev)
     if ws is None or ws.numel() < need:
@@ -440,6 +449,36 @@ def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, model=None, **opt
     info["prec_hist"] = list(inf.prec_hist)[: inf.niter]
     info["status"] = code
     return E.value, C, eps, info
+
+
+def grad_plan(shells, aux, natom, nocc):
+    """dfx_grad_plan: bytes of the gradient's workspace (host only)."""
+    s, a = _ShellArray(shells), _ShellArray(aux)
+    b = ctypes.c_int64()
+    _check(_lib.dfx_grad_plan(s.arr, s.n, a.arr, a.n, int(natom), int(nocc), ctypes.byref(b)))
+    return b.value
+
+
+def rhf_grad(xyz, Z, shells, aux, C_occ, eps_occ, tau=1e-12, charge=0):
+    """dfx_rhf_grad: the DF-RHF nuclear gradient [natom][3] (Eh/bohr) at the
+    converged occupied orbitals C_occ (nbf x nocc) with levels eps_occ, and the
+    timing info.  The workspace is the module's cached SCF workspace, grown to
+    the gradient's size when needed."""
+    C = np.ascontiguousarray(C_occ, dtype=np.float64)
+    e = np.ascontiguousarray(eps_occ, dtype=np.float64)
+    nocc = C.shape[1]
+    if e.shape[0] != nocc:
+        raise ValueError("rhf_grad: eps_occ must have one level per column of C_occ")
+    o = scf_default_opts()
+    o.tau = tau
+    s, a = _ShellArray(shells), _ShellArray(aux)
+    g = _GeomC(xyz, Z, charge)
+    ws = _scf_workspace(o, shells, aux, len(g.Z), need=grad_plan(shells, aux, len(g.Z), nocc))  # noqa: F841
+    out = np.zeros((len(g.Z), 3))
+    inf = GradInfo()
+    _check(_lib.dfx_rhf_grad(ctypes.byref(g.g), s.arr, s.n, a.arr, a.n, ctypes.byref(o), C.ctypes.data,
+                             e.ctypes.data, nocc, out.ctypes.data, ctypes.byref(inf)))
+    return out, {k: getattr(inf, k) for k, _ in GradInfo._fields_}
 
 
 def _open_shell(fn, nset, xyz, Z, shells, aux, charge, multiplicity, want_c, opts):

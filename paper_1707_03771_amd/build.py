@@ -29,8 +29,46 @@ FLAGS = ["--offload-arch=" + ARCH, "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-
 LIBS = ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"]
 
 
+# Sources compiled once per combination of defines: the derivative integral
+# classes (one orbital class (LA, LB) >= and one moved centre and axis per
+# object, so that the heavy instantiations build in parallel) and the metric
+# derivatives (one axis per object).
+VARIANTS = {
+    "grad3_class.hip": [dict(GRAD_LA=la, GRAD_LB=lb, GRAD_W=w, GRAD_AX=ax)
+                        for la in range(4) for lb in range(la + 1) for w in range(2) for ax in range(3)],
+    "grad2_class.hip": [dict(GRAD_AX=ax) for ax in range(3)],
+}
+
+
+class Unit:
+    """One object file: a source and the defines it is compiled with."""
+
+    def __init__(self, src, defs=None):
+        self.src, self.defs = src, defs or {}
+        tag = "".join(f"_{k.split('_')[-1].lower()}{v}" for k, v in self.defs.items())
+        self.obj = os.path.join(BUILD, os.path.basename(src) + tag + ".o")
+
+    def cost(self):
+        # the heaviest translation units first
+        big = ("eri3_l3" in self.src or "eri3_l2" in self.src or
+               (self.defs.get("GRAD_LA", 0) >= 2 and "grad3" in self.src))
+        return -os.path.getsize(self.src) - (10 ** 6 if big else 0) - 1000 * self.defs.get("GRAD_LA", 0) \
+            - 100 * self.defs.get("GRAD_LB", 0)
+
+
 def sources():
     return sorted(glob.glob(os.path.join(CSRC, "*.hip")) + glob.glob(os.path.join(CSRC, "*.cpp")))
+
+
+def units():
+    out = []
+    for s in sources():
+        name = os.path.basename(s)
+        if name in VARIANTS:
+            out += [Unit(s, d) for d in VARIANTS[name]]
+        else:
+            out.append(Unit(s))
+    return out
 
 
 def _includes(path, seen):
@@ -51,15 +89,12 @@ def deps_mtime(src):
     return max([os.path.getmtime(src)] + [os.path.getmtime(h) for h in _includes(src, set())])
 
 
-def obj_of(src):
-    return os.path.join(BUILD, os.path.basename(src) + ".o")
-
-
-def compile_one(src, verbose):
-    out = obj_of(src)
-    cmd = [HIPCC] + FLAGS + ["-c", src, "-o", out + ".tmp"]
+def compile_one(u, verbose):
+    src, out = u.src, u.obj
+    defs = [f"-D{k}={v}" for k, v in u.defs.items()]
+    cmd = [HIPCC] + FLAGS + defs + ["-c", src, "-o", out + ".tmp"]
     if src.endswith(".cpp"):
-        cmd = [HIPCC] + FLAGS + ["-x", "hip", "-c", src, "-o", out + ".tmp"]
+        cmd = [HIPCC] + FLAGS + defs + ["-x", "hip", "-c", src, "-o", out + ".tmp"]
     t = time.time()
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
@@ -67,24 +102,22 @@ def compile_one(src, verbose):
         raise RuntimeError(f"compile failed: {os.path.basename(src)}\n{msg}")
     os.replace(out + ".tmp", out)
     if verbose:
-        print(f"  {os.path.basename(src)}: {time.time() - t:.1f} s", flush=True)
+        print(f"  {os.path.basename(out)}: {time.time() - t:.1f} s", flush=True)
     return out
 
 
 def build(force=False, jobs=None, verbose=True):
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sources()
-    todo = [s for s in srcs if force or not os.path.exists(obj_of(s))
-            or os.path.getmtime(obj_of(s)) < deps_mtime(s)]
+    us = units()
+    todo = [u for u in us if force or not os.path.exists(u.obj) or os.path.getmtime(u.obj) < deps_mtime(u.src)]
     jobs = jobs or min(16, os.cpu_count() or 4)
-    # the heaviest translation units first
-    todo.sort(key=lambda s: -os.path.getsize(s) - (10 ** 6 if "eri3_l3" in s or "eri3_l2" in s else 0))
+    todo.sort(key=lambda u: u.cost())
     if todo:
         if verbose:
-            print(f"compiling {len(todo)} of {len(srcs)} sources with {jobs} jobs", flush=True)
+            print(f"compiling {len(todo)} of {len(us)} objects with {jobs} jobs", flush=True)
         with cf.ThreadPoolExecutor(jobs) as ex:
-            list(ex.map(lambda s: compile_one(s, verbose), todo))
-    objs = [obj_of(s) for s in srcs]
+            list(ex.map(lambda u: compile_one(u, verbose), todo))
+    objs = [u.obj for u in us]
     if todo or not os.path.exists(LIB) or os.path.getmtime(LIB) < max(os.path.getmtime(o) for o in objs):
         cmd = [HIPCC, "--offload-arch=" + ARCH, "-shared", "-o", LIB + ".tmp"] + objs + LIBS
         subprocess.check_call(cmd)

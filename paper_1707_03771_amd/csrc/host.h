@@ -90,6 +90,14 @@ struct DevShellSet {
 
 const double* rys_table_device();  // per current device, built on first use
 
+// The calling thread's stream and rocBLAS handle on the current device (scf.hip),
+// made on first use and kept until the process ends.
+struct DevCtx {
+  hipStream_t st = nullptr;
+  void* rb = nullptr;  // rocblas_handle
+};
+DevCtx& thread_ctx();
+
 // K from a symmetric density by signed eigen-factorisation (scf.hip); synchronous
 void k_from_density(const JKArgs& a, const double* D, double* K, hipStream_t st);
 

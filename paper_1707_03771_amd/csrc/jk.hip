@@ -110,17 +110,21 @@ __global__ void unpack_sym_kernel(const double* __restrict__ v, int nbf, double*
   M[idx] = v[tile_base(r >> 5, c >> 5) + ((r & 31) << 5) + (c & 31)];
 }
 
-void j_build(const JKArgs& a, const double* D, double* J, double* work, hipStream_t st) {
+void j_gamma(const JKArgs& a, const double* D, double* gam, double* dvec, hipStream_t st) {
   const int nt = ntiles_for(a.nbf);
-  double* dvec = work;                       // ncols
-  double* gam = work + a.ncols;              // naux
-  double* jv = gam + ((a.naux + 3) & ~3);    // ncols
   hipLaunchKernelGGL(pack_density_kernel, dim3(nt * (nt + 1) / 2), dim3(256), 0, st, D, a.nbf, dvec);
   // both words of B in every precision: J is bandwidth-bound, and with the hi
   // word alone its error (amplified by the conditioning of the metric) exceeds
   // that of a reduced-precision K
   hipLaunchKernelGGL(j_gamma_kernel, dim3((a.naux + JG_Q - 1) / JG_Q), dim3(256), 0, st, a.hi, a.lo, a.ncols, a.naux,
                      dvec, gam);
+}
+
+void j_build(const JKArgs& a, const double* D, double* J, double* work, hipStream_t st) {
+  double* dvec = work;                       // ncols
+  double* gam = work + a.ncols;              // naux
+  double* jv = gam + ((a.naux + 3) & ~3);    // ncols
+  j_gamma(a, D, gam, dvec, st);
   const unsigned gb = (unsigned)(((a.ncols >> 2) + 255) / 256);
   hipLaunchKernelGGL(j_back_kernel, dim3(gb), dim3(256), 0, st, a.hi, a.lo, a.ncols, a.naux, gam, jv);
   const int64_t n2 = (int64_t)a.nbf * a.nbf;

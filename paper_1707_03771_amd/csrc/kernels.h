@@ -68,6 +68,9 @@ struct TrsmTimer {
   virtual ~TrsmTimer() = default;
 };
 TrsmStats trsm_solve(const double* L, int n, double* raw, int64_t ncols, hipStream_t st, TrsmTimer* timer = nullptr);
+// X = L^-T X in place (n x ncols, row stride ncols) by blocked back
+// substitution with the lower-triangular L: the transpose of trsm_solve.
+void trsm_solve_t(const double* L, int n, double* X, int64_t ncols, hipStream_t st);
 // hi = fl32(B), lo = fl32(B - hi) of B (n x ncols) into rows of length ld_out at
 // the columns cmap (and cmap2 where >= 0)
 void split_scatter(const double* B, int n, int64_t ncols, float* hi, float* lo, int64_t ld_out, const int64_t* cmap,
@@ -97,6 +100,8 @@ struct JKArgs {
   size_t ws_cap = 0;
 };
 void j_build(const JKArgs& a, const double* D, double* J, double* work, hipStream_t st);
+// gamma_Q = sum B_Q,mu nu D_mu nu alone (Eq. 3a); dvec: ncols doubles of work
+void j_gamma(const JKArgs& a, const double* D, double* gam, double* dvec, hipStream_t st);
 // K from the occupied block C [nbf][nocc] (row-major); work >= k_work_bytes
 size_t k_work_bytes(const JKArgs& a, int nocc);
 // optional GPU timers around the two K phases (events are recorded on st)

@@ -312,6 +312,52 @@ __global__ void __launch_bounds__(TS_T) trsv64_cols_kernel(const double* __restr
   for (int i = TS_R - 1; i >= 0; --i) X[(int64_t)(FULL ? i : min(i, nr - 1)) * ldx + c] = x[i];
 }
 
+// L^T x = b for the nr <= 64 rows of every column of X (the diagonal block L of
+// the back substitution B = L^-T R): x_i = (b_i - sum_k>i L_ki x_k) / L_ii,
+// rows from the last, in groups of 8 as in trsv64_cols_kernel.  Rows beyond nr
+// are the identity with zero right-hand sides.
+template <bool FULL>
+__global__ void __launch_bounds__(TS_T) trsv64t_cols_kernel(const double* __restrict__ L, int64_t ldl, int nr,
+                                                            double* __restrict__ X, int64_t ldx, int ncols) {
+  __shared__ double Lr[TS_R][TS_R];  // Lr[k][i] = L_ki
+  for (int e = threadIdx.x; e < TS_R * TS_R; e += TS_T) {
+    const int k = e / TS_R, i = e % TS_R;
+    Lr[k][i] = (i < nr && k < nr) ? (i <= k ? L[(int64_t)k * ldl + i] : 0.0) : (i == k ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  const int c = blockIdx.x * TS_T + threadIdx.x;
+  if (c >= ncols) return;
+  double x[TS_R];
+#pragma unroll
+  for (int g = TS_R - TS_G; g >= 0; g -= TS_G) {
+    double s[TS_G];
+#pragma unroll
+    for (int r = 0; r < TS_G; ++r) {
+      const int row = FULL ? g + r : min(g + r, nr - 1);
+      const double v = X[(int64_t)row * ldx + c];
+      s[r] = (FULL || g + r < nr) ? v : 0.0;
+    }
+#pragma unroll
+    for (int k = TS_R - 1; k >= g + TS_G; --k) {
+      double l[TS_G];
+#pragma unroll
+      for (int r = 0; r < TS_G; ++r) l[r] = Lr[k][g + r];
+#pragma unroll
+      for (int r = 0; r < TS_G; ++r) s[r] = fma(-l[r], x[k], s[r]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int r = TS_G - 1; r >= 0; --r) {
+#pragma unroll
+      for (int k = r + 1; k < TS_G; ++k) s[r] = fma(-Lr[g + k][g + r], x[g + k], s[r]);
+      x[g + r] = s[r] / Lr[g + r][g + r];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+#pragma unroll
+  for (int i = TS_R - 1; i >= 0; --i) X[(int64_t)(FULL ? i : min(i, nr - 1)) * ldx + c] = x[i];
+}
+
 // hi = fl32(B), lo = fl32(B - hi) scattered to the tile layout: packed column c
 // goes to column cmap[c] of a row of length ld_out (none if negative), and also
 // to cmap2[c] when that is >= 0 (the mirror position inside a diagonal tile)
@@ -350,6 +396,54 @@ static void trsv64_cols(const double* L, int64_t ldl, int nr, double* X, int64_t
 
 // X[rows] -= A X[krows]: R_i -= L_i,0:k B_0:k over all columns, in slabs that
 // keep each launch's grid within range
+static void trsv64t_cols(const double* L, int64_t ldl, int nr, double* X, int64_t ldx, int64_t ncols,
+                         hipStream_t st) {
+  const int64_t slab = (int64_t)TS_T * 1048576;
+  for (int64_t c0 = 0; c0 < ncols; c0 += slab) {
+    const int nc = (int)std::min<int64_t>(slab, ncols - c0);
+    const dim3 g((unsigned)((nc + TS_T - 1) / TS_T));
+    if (nr == TS_R)
+      hipLaunchKernelGGL(trsv64t_cols_kernel<true>, g, dim3(TS_T), 0, st, L, ldl, nr, X + c0, ldx, nc);
+    else
+      hipLaunchKernelGGL(trsv64t_cols_kernel<false>, g, dim3(TS_T), 0, st, L, ldl, nr, X + c0, ldx, nc);
+  }
+}
+
+// C -= A^T X over all columns: A stored K x M (lda), the transposed blocks of L
+static void trsm_update_t(const double* A, int64_t lda, int M, int K, const double* Bsrc, double* C, int64_t ncols,
+                          hipStream_t st) {
+  const int64_t slab = (int64_t)GN * 65536;
+  for (int64_t c0 = 0; c0 < ncols; c0 += slab) {
+    GemmF64 g{};
+    g.M = M; g.N = (int)std::min<int64_t>(slab, ncols - c0); g.K = K;
+    g.A = A; g.lda = lda; g.ta = true;
+    g.B = Bsrc + c0; g.ldb = ncols;
+    g.C = C + c0; g.ldc = ncols;
+    g.alpha = -1.0; g.beta = 1.0; g.batch = 1;
+    hipLaunchKernelGGL((dgemm_kernel<true, false, EPI_SUB>), dim3(gemm_tiles(g.M, g.N)), dim3(GT), 0, st, g);
+  }
+}
+
+void trsm_solve_t(const double* L, int n, double* X, int64_t ncols, hipStream_t st) {
+  if (ncols <= 0 || n <= 0) return;
+  constexpr int TB = 2 * TS_R;
+  const int nb = (n + TB - 1) / TB;
+  for (int bi = nb - 1; bi >= 0; --bi) {
+    const int r0 = bi * TB, rb = std::min(TB, n - r0), r1 = r0 + rb;
+    // rows r0.. of the block: R -= (L_k,block)^T X_k over the solved rows k >= r1
+    if (r1 < n) trsm_update_t(L + (int64_t)r1 * n + r0, n, rb, n - r1, X + (int64_t)r1 * ncols,
+                              X + (int64_t)r0 * ncols, ncols, st);
+    const int h1 = std::min(TS_R, rb);
+    if (rb > TS_R) {  // lower half of the block first, then the upper one
+      const int rm = r0 + TS_R;
+      trsv64t_cols(L + (int64_t)rm * n + rm, n, rb - TS_R, X + (int64_t)rm * ncols, ncols, ncols, st);
+      trsm_update_t(L + (int64_t)rm * n + r0, n, TS_R, rb - TS_R, X + (int64_t)rm * ncols, X + (int64_t)r0 * ncols,
+                    ncols, st);
+    }
+    trsv64t_cols(L + (int64_t)r0 * n + r0, n, h1, X + (int64_t)r0 * ncols, ncols, ncols, st);
+  }
+}
+
 static double trsm_update(const double* A, int64_t lda, int M, int K, const double* Bsrc, double* C, int64_t ncols,
                           hipStream_t st) {
   const int64_t slab = (int64_t)GN * 65536;

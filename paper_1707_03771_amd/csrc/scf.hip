@@ -294,11 +294,7 @@ static unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 // made on first use and kept until the process ends: a call neither creates
 // nor destroys them (the handle also keeps the eigensolver's device scratch
 // between calls).
-struct DevCtx {
-  hipStream_t st = nullptr;
-  rocblas_handle rb = nullptr;
-};
-static DevCtx& thread_ctx() {
+DevCtx& thread_ctx() {
   static thread_local std::map<int, DevCtx> ctx;
   int dev = 0;
   DFX_HIP(hipGetDevice(&dev));
@@ -306,10 +302,9 @@ static DevCtx& thread_ctx() {
   if (!c.st) DFX_HIP(hipStreamCreate(&c.st));
   if (!c.rb) {
     // the handle's own scratch is its for the process: never from a call's workspace
-    if (rocblas_create_handle(&c.rb) != rocblas_status_success) {
-      c.rb = nullptr;
-      throw Error(DFX_EHIP, "rocblas_create_handle failed");
-    }
+    rocblas_handle h = nullptr;
+    if (rocblas_create_handle(&h) != rocblas_status_success) throw Error(DFX_EHIP, "rocblas_create_handle failed");
+    c.rb = h;
   }
   return c;
 }
@@ -501,7 +496,7 @@ void k_from_density(const JKArgs& a, const double* D, double* K, hipStream_t st)
   const int64_t n2 = (int64_t)n * n;
   Scf S;
   S.st = st;
-  S.rb = thread_ctx().rb;
+  S.rb = (rocblas_handle)thread_ctx().rb;
   rocblas_set_stream(S.rb, st);
   S.eig_info.alloc(sizeof(int));
   DevMem W(8 * n2), lam(8 * (size_t)n);
@@ -631,7 +626,7 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     {
       DevCtx& ctx = thread_ctx();
       S.st = ctx.st;
-      S.rb = ctx.rb;
+      S.rb = (rocblas_handle)ctx.rb;
       rocblas_set_stream(S.rb, S.st);
     }
     hipStream_t st = S.st;
@@ -1144,7 +1139,7 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
     {
       DevCtx& ctx = thread_ctx();
       S.st = ctx.st;
-      S.rb = ctx.rb;
+      S.rb = (rocblas_handle)ctx.rb;
       rocblas_set_stream(S.rb, S.st);
     }
     hipStream_t st = S.st;
@@ -1462,7 +1457,7 @@ int dfx_lowdin(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dou
     const int64_t n2 = (int64_t)n * n;
     Scf S;
     S.st = (hipStream_t)stream;
-    S.rb = thread_ctx().rb;
+    S.rb = (rocblas_handle)thread_ctx().rb;
     rocblas_set_stream(S.rb, S.st);
     S.eig_info.alloc(sizeof(int));
     hipStream_t st = S.st;
