@@ -381,6 +381,31 @@ def eval_open_shell(dfx, runs=(("alkane", 0, 1, 150, 0.0), ("alkane", 0, 3, 150,
     print(json.dumps({"metric": "DF-UHF and DF-ROHF (FP64 J and K, core guess, DIIS)", "runs": rows}))
 
 
+def eval_grad(dfx, workloads=("alkane", "water4")):
+    """DF-RHF analytic nuclear gradient (FP64) after a converged plain FP64 SCF
+    at full size: wall and GPU times of its phases, the translational and
+    torque sum rules, and the largest component."""
+    rows = []
+    for wl in workloads:
+        elems, xyz, sh, ax = W.workload(wl, seed=0) if wl == "alkane" else W.workload(wl)
+        Z = W.charges(elems)
+        E, C, eps, info = dfx.scf(xyz, Z, sh, ax, conv_dE=1e-9, conv_err=1e-7)
+        nocc = info["nocc"]
+        dfx.rhf_grad(xyz, Z, sh, ax, C[:, :nocc], eps[:nocc])                     # warm-up
+        t0 = time.perf_counter()
+        g, gi = dfx.rhf_grad(xyz, Z, sh, ax, C[:, :nocc], eps[:nocc])
+        dt = time.perf_counter() - t0
+        ctr = np.asarray(xyz).mean(axis=0)
+        torque = sum(np.cross(xyz[i] - ctr, g[i]) for i in range(len(Z)))  # about the centroid
+        row = {"workload": wl, "natom": len(Z), "nbf": info["nbf"], "naux": info["naux"], "nocc": nocc,
+               "E": E, "grad_s": round(dt, 4), "phases_s": {k: round(v, 4) for k, v in gi.items() if k != "natom"},
+               "max_abs_g": float(np.abs(g).max()), "sum_rule": float(np.abs(g.sum(axis=0)).max()),
+               "torque": float(np.abs(torque).max()), "scf_s": round(info["t_total"], 3)}
+        log(json.dumps(row))
+        rows.append(row)
+    print(json.dumps({"metric": "DF-RHF analytic nuclear gradient, FP64", "runs": rows}))
+
+
 def eval_trajectory(dfx, nframes):
     """(H2O)64 over a seeded trajectory: per frame, mixed + learned (timed) and
     plain FP64 from the core guess; as context, mixed from the previous frame's
@@ -430,7 +455,8 @@ def main():
                     help="step k runs frame k of a seeded trajectory (per-atom sigma 0.02 bohr)")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 reference run")
     ap.add_argument("--no-context", action="store_true", help="skip the core-guess context run")
-    ap.add_argument("--eval", default=None, choices=["ring-guess", "alkane", "trajectory", "mp2", "open-shell"],
+    ap.add_argument("--eval", default=None,
+                    choices=["ring-guess", "alkane", "trajectory", "mp2", "open-shell", "grad"],
                     help="evaluation runs beside the benchmark line (each prints its own JSON line)")
     ap.add_argument("--ntrain", type=int, default=1600)
     ap.add_argument("--ntest", type=int, default=400)
@@ -440,6 +466,7 @@ def main():
                     help="counter-run driver: build B, one J/K build in this precision with the SCF's "
                          "launch configuration, and a 1 GiB elementwise copy as the HBM calibration")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--run-log", default=None, help="append one JSON line per SCF / gradient call to this file")
     a = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if a.gpus != 1 or world != 1:
@@ -449,6 +476,8 @@ def main():
 
     import torch
     import paper_1707_03771_amd as dfx
+    if a.run_log:
+        dfx.set_run_log(a.run_log)
 
     elems, xyz, sh, ax = W.workload(a.workload)
     Z = W.charges(elems)
@@ -464,6 +493,9 @@ def main():
         return
     if a.eval == "open-shell":
         eval_open_shell(dfx)
+        return
+    if a.eval == "grad":
+        eval_grad(dfx)
         return
     if a.eval == "trajectory":
         eval_trajectory(dfx, a.frames)

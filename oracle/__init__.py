@@ -43,7 +43,8 @@ _LIB = None
 def lib():
     global _LIB
     if _LIB is None:
-        path = os.path.join(HERE, "liboracle.so")
+        # DFX_ORACLE_LIB: another build of md_ints.c (the sanitizer test's)
+        path = os.environ.get("DFX_ORACLE_LIB") or os.path.join(HERE, "liboracle.so")
         if not os.path.exists(path):
             from . import build as _b  # noqa: WPS433 (oracle-local build step)
             _b.build()

@@ -610,7 +610,7 @@ void oracle_eri3_grad(const obasis *bs, int nbf, const obasis *ax, int naux, con
   for (int i = 0; i < 3 * natom; ++i) grad[i] = 0.0;
 #pragma omp parallel
   {
-    double *g = (double *)calloc(3 * natom, sizeof(double));
+    double *g = (double *)calloc((size_t)3 * (size_t)(natom > 0 ? natom : 0), sizeof(double));
     double *blk = (double *)malloc(sizeof(double) * 9 * 13 * 13 * 9);
 #pragma omp for schedule(dynamic) collapse(2)
     for (int a = 0; a < bs->nsh; ++a)
@@ -644,7 +644,7 @@ void oracle_eri2_grad(const obasis *ax, int naux, const int *atom_ax, int natom,
   for (int i = 0; i < 3 * natom; ++i) grad[i] = 0.0;
 #pragma omp parallel
   {
-    double *g = (double *)calloc(3 * natom, sizeof(double));
+    double *g = (double *)calloc((size_t)3 * (size_t)(natom > 0 ? natom : 0), sizeof(double));
     double blk[2 * 3 * 81];
 #pragma omp for schedule(dynamic) collapse(2)
     for (int p = 0; p < ax->nsh; ++p)
@@ -720,7 +720,7 @@ void oracle_int1e_grad(const obasis *bs, int nbf, const int *atom_bs, int natom,
   for (int i = 0; i < 3 * natom; ++i) grad[i] = 0.0;
 #pragma omp parallel
   {
-    double *g = (double *)calloc(3 * natom, sizeof(double));
+    double *g = (double *)calloc((size_t)3 * (size_t)(natom > 0 ? natom : 0), sizeof(double));
     double *R = (double *)malloc(sizeof(double) * RD * RD * RD);
     hprod *h = (hprod *)malloc(sizeof(hprod));
 #pragma omp for schedule(dynamic) collapse(2)

@@ -9,7 +9,9 @@ Importing fails loudly if the library has not been built
 from __future__ import annotations
 
 import ctypes
+import json
 import os
+import time
 
 import numpy as np
 
@@ -369,6 +371,41 @@ def cholesky(A, stream=None):
     return L, Linv
 
 
+# ---- run log -------------------------------------------------------------------
+# With a path set (set_run_log, or the DFX_RUN_LOG environment variable), every
+# dfx_scf / dfx_uhf / dfx_rohf / dfx_rhf_grad call appends one JSON line: the
+# entry point, the system's size, the status, the energy and the info record
+# (per-iteration energies, error norms and precisions, phase times).
+_RUN_LOG = os.environ.get("DFX_RUN_LOG") or None
+
+
+def set_run_log(path):
+    """Append a JSON line per SCF / gradient call to `path` (None: stop)."""
+    global _RUN_LOG
+    _RUN_LOG = os.fspath(path) if path is not None else None
+
+
+def _plain(v):
+    if isinstance(v, (list, tuple)):
+        return [_plain(x) for x in v]
+    if isinstance(v, (np.integer,)):
+        return int(v)
+    if isinstance(v, (np.floating,)):
+        return float(v)
+    if isinstance(v, np.ndarray):
+        return v.tolist()
+    return v
+
+
+def _log_run(entry, natom, nbf, record):
+    if not _RUN_LOG:
+        return
+    line = {"entry": entry, "unix_time": round(time.time(), 3), "natom": int(natom), "nbf": int(nbf)}
+    line.update({k: _plain(v) for k, v in record.items()})
+    with open(_RUN_LOG, "a") as f:
+        f.write(json.dumps(line) + "\n")
+
+
 def scf_default_opts():
     o = ScfOpts()
     _lib.dfx_scf_default_opts(ctypes.byref(o))
@@ -448,6 +485,7 @@ def scf(xyz, Z, shells, aux, charge=0, init=None, want_c=True, model=None, **opt
     info["err_hist"] = list(inf.err_hist)[: inf.niter]
     info["prec_hist"] = list(inf.prec_hist)[: inf.niter]
     info["status"] = code
+    _log_run("dfx_scf", len(g.Z), n, dict(E=E.value, **info))
     return E.value, C, eps, info
 
 
@@ -478,7 +516,9 @@ def rhf_grad(xyz, Z, shells, aux, C_occ, eps_occ, tau=1e-12, charge=0):
     inf = GradInfo()
     _check(_lib.dfx_rhf_grad(ctypes.byref(g.g), s.arr, s.n, a.arr, a.n, ctypes.byref(o), C.ctypes.data,
                              e.ctypes.data, nocc, out.ctypes.data, ctypes.byref(inf)))
-    return out, {k: getattr(inf, k) for k, _ in GradInfo._fields_}
+    info = {k: getattr(inf, k) for k, _ in GradInfo._fields_}
+    _log_run("dfx_rhf_grad", len(g.Z), C.shape[0], dict(nocc=nocc, max_abs_grad=float(np.abs(out).max()), **info))
+    return out, info
 
 
 def _open_shell(fn, nset, xyz, Z, shells, aux, charge, multiplicity, want_c, opts):
@@ -503,6 +543,8 @@ def _open_shell(fn, nset, xyz, Z, shells, aux, charge, multiplicity, want_c, opt
     info["E_hist"] = list(inf.E_hist)[: inf.niter]
     info["err_hist"] = list(inf.err_hist)[: inf.niter]
     info["status"] = code
+    _log_run("dfx_uhf" if nset == 2 else "dfx_rohf", len(g.Z), n, dict(E=E.value, multiplicity=int(multiplicity),
+                                                                       **info))
     if want_c and nset == 1:
         C, eps = C[0], eps[0]
     return E.value, C, eps, info

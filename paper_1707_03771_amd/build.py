@@ -49,11 +49,18 @@ class Unit:
         self.obj = os.path.join(BUILD, os.path.basename(src) + tag + ".o")
 
     def cost(self):
-        # the heaviest translation units first
-        big = ("eri3_l3" in self.src or "eri3_l2" in self.src or
-               (self.defs.get("GRAD_LA", 0) >= 2 and "grad3" in self.src))
-        return -os.path.getsize(self.src) - (10 ** 6 if big else 0) - 1000 * self.defs.get("GRAD_LA", 0) \
-            - 100 * self.defs.get("GRAD_LB", 0)
+        """Sort key, heaviest first: the integral classes' compile time grows
+        like the square of their Cartesian block (measured: f f ERIs ~280 s,
+        their derivatives ~400 s per centre and axis)."""
+        import re
+        nc = lambda l: (l + 1) * (l + 2) // 2  # noqa: E731
+        m = re.search(r"eri3_l(\d)(\d)\.hip$", self.src)
+        if m:
+            return -2.8 * (nc(int(m.group(1))) * nc(int(m.group(2)))) ** 2 / 100.0
+        if "grad3" in self.src:
+            la, lb = self.defs["GRAD_LA"], self.defs["GRAD_LB"]
+            return -4.0 * (nc(la) * nc(lb)) ** 2 / 100.0
+        return -os.path.getsize(self.src) / 1000.0
 
 
 def sources():
@@ -127,13 +134,52 @@ def build(force=False, jobs=None, verbose=True):
     return LIB
 
 
+ASAN_DIR = os.path.join(BUILD, "asan")
+ASAN_LIB = os.path.join(BUILD, "libdfx_asan.so")
+# host code only: -Xarch_host before each sanitizer flag keeps device code as it is
+ASAN_FLAGS = ["-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def build_host_asan(jobs=None, verbose=True):
+    """A second library for the sanitizer test: the host C++ sources (*.cpp:
+    the C-ABI, argument checks, plans, arenas, the gradient driver, the guess's
+    geometry code) built with AddressSanitizer, linked with the regular objects
+    of the HIP sources into _build/libdfx_asan.so.  The package never loads
+    it; a process that does must preload the compiler's ASan runtime, which
+    resolves the instrumentation's symbols."""
+    build(jobs=jobs, verbose=verbose)
+    os.makedirs(ASAN_DIR, exist_ok=True)
+    objs = []
+    for u in units():
+        if not u.src.endswith(".cpp"):
+            objs.append(u.obj)
+            continue
+        out = os.path.join(ASAN_DIR, os.path.basename(u.obj))
+        if not os.path.exists(out) or os.path.getmtime(out) < deps_mtime(u.src):
+            cmd = [HIPCC] + FLAGS + ASAN_FLAGS + ["-x", "hip", "-c", u.src, "-o", out + ".tmp"]
+            r = subprocess.run(cmd, capture_output=True, text=True)
+            if r.returncode != 0:
+                raise RuntimeError(f"compile failed: {os.path.basename(u.src)} (asan)\n{r.stderr}")
+            os.replace(out + ".tmp", out)
+            if verbose:
+                print(f"  asan/{os.path.basename(out)}", flush=True)
+        objs.append(out)
+    if not os.path.exists(ASAN_LIB) or os.path.getmtime(ASAN_LIB) < max(os.path.getmtime(o) for o in objs):
+        subprocess.check_call([HIPCC, "--offload-arch=" + ARCH, "-shared", "-o", ASAN_LIB + ".tmp"] + objs + LIBS)
+        os.replace(ASAN_LIB + ".tmp", ASAN_LIB)
+    return ASAN_LIB
+
+
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
     ap.add_argument("--force", action="store_true")
     ap.add_argument("-j", type=int, default=None)
+    ap.add_argument("--host-asan", action="store_true", help="also build _build/libdfx_asan.so")
     a = ap.parse_args()
     try:
         build(force=a.force, jobs=a.j)
+        if a.host_asan:
+            build_host_asan(jobs=a.j)
     except RuntimeError as e:
         print(e, file=sys.stderr)
         sys.exit(1)

@@ -137,3 +137,23 @@ def test_h2_sto3g_textbook_through_the_gpu_path(dfx):
     jkf = lambda D, Cc: (np.einsum("mnls,ls->mn", G, D), np.einsum("mlns,ls->mn", G, D))  # noqa: E731
     r = O.rhf(S, T + V, 1.0 / g["R_bohr"], 1, jkf)
     assert r.converged and abs(E - r.E) < 1e-8
+
+
+def test_run_log_records_every_call(dfx, h4_ref, tmp_path):
+    """The JSONL run log: one line per SCF call with the energy and the
+    per-iteration record the library returned."""
+    import json
+    xyz, Z, sh, ax, nocc, ref = h4_ref
+    path = tmp_path / "runs.jsonl"
+    dfx.set_run_log(path)
+    try:
+        E, _, _, info = dfx.scf(xyz, Z, sh, ax, conv_dE=1e-10, conv_err=1e-8)
+        E2, _, _, _ = dfx.scf(xyz, Z, sh, ax, want_c=False, schedule=dfx.SCHED_MIXED)
+    finally:
+        dfx.set_run_log(None)
+    lines = [json.loads(t) for t in path.read_text().splitlines()]
+    assert [r["entry"] for r in lines] == ["dfx_scf", "dfx_scf"]
+    assert lines[0]["E"] == E and lines[1]["E"] == E2
+    assert lines[0]["E_hist"] == info["E_hist"] and len(lines[0]["err_hist"]) == info["niter"]
+    assert lines[0]["natom"] == len(Z) and lines[0]["nbf"] == info["nbf"]
+    assert lines[1]["n_mixed"] >= 1 and set(lines[1]["prec_hist"]) <= {0, 1, 2}
