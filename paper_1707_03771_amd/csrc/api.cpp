@@ -400,10 +400,12 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     std::vector<std::vector<double>> qc_by_l(5);
     for (int c = 0; c < nauxsh; ++c) qc_by_l[B->aux.l[c]].push_back(B->QC[c]);
     for (auto& v : qc_by_l) std::sort(v.begin(), v.end());
-    std::vector<std::vector<int>> cf(16), cs(16);
-    std::vector<std::vector<unsigned char>> crow(16);
+    std::vector<std::vector<int>>& cf = B->cls_f;
+    std::vector<std::vector<int>>& cs = B->cls_s;
+    cf.assign(16, {});
+    cs.assign(16, {});
     std::vector<std::vector<double>> cq(16);
-    std::vector<std::vector<int64_t>> cpc(16);
+    std::vector<int> kcls, kidx;  // class and position in it of every kept pair
     int64_t ntrip = 0, nint = 0;
     for (int a = 0; a < nsh; ++a)
       for (int b = 0; b <= a; ++b) {
@@ -416,11 +418,11 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
         B->col_off.push_back(first_col + (int64_t)na * nb);
         const int la = B->bas.l[a], lb = B->bas.l[b];
         const int cls = std::max(la, lb) * 4 + std::min(la, lb);
+        kcls.push_back(cls);
+        kidx.push_back((int)cf[cls].size());
         cf[cls].push_back(la >= lb ? a : b);
         cs[cls].push_back(la >= lb ? b : a);
-        crow[cls].push_back(la >= lb ? 1 : 0);
         cq[cls].push_back(q);
-        cpc[cls].push_back(first_col);
         const int64_t uniq = (a == b) ? (int64_t)na * (na + 1) / 2 : (int64_t)na * nb;
         for (int lc = 0; lc <= 4; ++lc) {
           const int64_t k = count_kept(q, qc_by_l[lc], tau);
@@ -429,6 +431,24 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
         }
       }
     B->ncols_p = B->col_off.back();
+    // raw's columns class by class, pair by pair, each pair's block row-major in
+    // (first shell, second shell) (the ERI stores of a wave fill one contiguous
+    // block); canonical column -> raw column for export
+    B->cls_base.assign(17, 0);
+    for (int cls = 0; cls < 16; ++cls)
+      B->cls_base[cls + 1] = B->cls_base[cls] + (int64_t)cf[cls].size() * (2 * (cls / 4) + 1) * (2 * (cls % 4) + 1);
+    B->rawcol.resize(B->ncols_p);
+    for (size_t k = 0; k < B->pa.size(); ++k) {
+      const int a = B->pa[k], b = B->pb[k], cls = kcls[k], pos = kidx[k];
+      const int na = 2 * B->bas.l[a] + 1, nb = 2 * B->bas.l[b] + 1;
+      const bool afirst = B->bas.l[a] >= B->bas.l[b];
+      const int SB = 2 * (cls % 4) + 1, SASB = (2 * (cls / 4) + 1) * SB;
+      for (int i = 0; i < na; ++i)
+        for (int j = 0; j < nb; ++j) {
+          const int ma = afirst ? i : j, mb = afirst ? j : i;
+          B->rawcol[B->col_off[k] + (int64_t)i * nb + j] = B->cls_base[cls] + (int64_t)pos * SASB + (ma * SB + mb);
+        }
+    }
 
     // -- raw (mu nu|P), aux-major, packed pair columns (screened triplets stay zero)
     B->raw.alloc(sizeof(double) * (size_t)naux * B->ncols_p);
@@ -439,14 +459,12 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
       for (int c : auxby[l]) q.push_back(B->QC[c]);
       qcl_d[l] = upload(q, st);
     }
-    std::vector<DevMem> cf_d(16), cs_d(16), cr_d(16), cq_d(16), cpc_d(16);
+    std::vector<DevMem> cf_d(16), cs_d(16), cq_d(16);
     for (int cls = 0; cls < 16; ++cls) {
       if (cf[cls].empty()) continue;
       cf_d[cls] = upload(cf[cls], st);
       cs_d[cls] = upload(cs[cls], st);
-      cr_d[cls] = upload(crow[cls], st);
       cq_d[cls] = upload(cq[cls], st);
-      cpc_d[cls] = upload(cpc[cls], st);
     }
     tm.stop();
     const double t_metric0 = tm.seconds();
@@ -517,9 +535,8 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
         a.K = B->daux.view();
         a.pf = cf_d[cls].as<int>();
         a.ps = cs_d[cls].as<int>();
-        a.rowfirst = cr_d[cls].as<unsigned char>();
         a.pq = cq_d[cls].as<double>();
-        a.pcol = cpc_d[cls].as<int64_t>();
+        a.cbase = B->cls_base[cls];
         a.npairs = (int)cf[cls].size();
         a.kl = auxby_d[lc].as<int>();
         a.kq = qcl_d[lc].as<double>();
@@ -528,7 +545,7 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
         a.out = B->raw.as<double>();
         a.ld = B->ncols_p;
         a.rys = rys;
-        eri3_dispatch(cls / 4, cls % 4, lc, false, STORE_PACKED, a, fork.s[k]);
+        eri3_dispatch(cls / 4, cls % 4, lc, false, STORE_CLASS, a, fork.s[k]);
       }
     }
     DFX_HIP(hipGetLastError());
@@ -562,27 +579,31 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     }
     cw.release();
 
-    // -- B = L^-1 raw over the packed columns, split into FP32 hi / lo and
-    // scattered to the tiled layout: packed column -> its tile position (r >= c),
-    // plus the mirror position inside a diagonal tile; of the duplicate columns
-    // (i, j) and (j, i) of a diagonal shell pair only i >= j is stored.  Tile
-    // elements of screened pairs stay zero.
+    // -- B = L^-1 raw over raw's columns, split into FP32 hi / lo and scattered
+    // to the tiled layout: raw column -> its tile position (r >= c), plus the
+    // mirror position inside a diagonal tile; of the duplicate columns (i, j)
+    // and (j, i) of a diagonal shell pair only i >= j is stored.  Tile elements
+    // of screened pairs stay zero.
     std::vector<int64_t> cmap(B->ncols_p), cmap2(B->ncols_p);
-    for (size_t k = 0; k < B->pa.size(); ++k) {
-      const int a = B->pa[k], b = B->pb[k];
-      const int na = 2 * B->bas.l[a] + 1, nb = 2 * B->bas.l[b] + 1;
-      for (int i = 0; i < na; ++i)
-        for (int j = 0; j < nb; ++j) {
-          const int64_t col = B->col_off[k] + (int64_t)i * nb + j;
-          const int r = B->bas.foff[a] + i, c = B->bas.foff[b] + j;
-          if (r < c) {
-            cmap[col] = cmap2[col] = -1;
-            continue;
+    for (int cls = 0; cls < 16; ++cls) {
+      const int SA = 2 * (cls / 4) + 1, SB = 2 * (cls % 4) + 1;
+      const int64_t npc = (int64_t)cf[cls].size();
+      for (int64_t p = 0; p < npc; ++p) {
+        const int f = cf[cls][p], sh = cs[cls][p];
+        for (int ma = 0; ma < SA; ++ma)
+          for (int mb = 0; mb < SB; ++mb) {
+            const int64_t col = B->cls_base[cls] + p * (SA * SB) + (ma * SB + mb);
+            const int mu = B->bas.foff[f] + ma, nu = B->bas.foff[sh] + mb;
+            if (f == sh && mu < nu) {  // the other triangle of a diagonal block: a duplicate
+              cmap[col] = cmap2[col] = -1;
+              continue;
+            }
+            const int r = std::max(mu, nu), c = std::min(mu, nu);
+            const int I = r >> 5, J = c >> 5;
+            cmap[col] = tile_base(I, J) + ((r & 31) << 5) + (c & 31);
+            cmap2[col] = (I == J && r != c) ? tile_base(I, J) + ((c & 31) << 5) + (r & 31) : -1;
           }
-          const int I = r >> 5, J = c >> 5;
-          cmap[col] = tile_base(I, J) + ((r & 31) << 5) + (c & 31);
-          cmap2[col] = (I == J && r != c) ? tile_base(I, J) + ((c & 31) << 5) + (r & 31) : -1;
-        }
+      }
     }
     DevMem cmap_d = upload(cmap, st), cmap2_d = upload(cmap2, st);
     // B = L^-1 raw by blocked forward substitution, in place (on a copy when the
@@ -769,10 +790,11 @@ int dfx_B_export(const dfx_B* bc, int what, int q0, int q1, double* dev_out, voi
       }
       b->toff = upload(toff, st);
     }
+    if (what == DFX_EXPORT_RAW && !b->rawcol_d.p) b->rawcol_d = upload(b->rawcol, st);
     export_rows(what == DFX_EXPORT_RAW ? nullptr : b->hi.as<float>(),
                 what == DFX_EXPORT_B ? b->lo.as<float>() : nullptr,
                 what == DFX_EXPORT_RAW ? b->raw.as<double>() : nullptr, b->ncols_t, q0, q1,
-                b->toff.as<int64_t>(), b->ncols_p, dev_out, st);
+                what == DFX_EXPORT_RAW ? b->rawcol_d.as<int64_t>() : b->toff.as<int64_t>(), b->ncols_p, dev_out, st);
     DFX_HIP(hipGetLastError());
   });
 }

@@ -5,7 +5,7 @@
 namespace dfx {
 
 void eri3_dispatch(int LA, int LB, int LC, bool unitb, int mode, Eri3Args a, hipStream_t st) {
-  if (unitb || mode != STORE_PACKED) throw Error(-6, "eri3: unsupported mode");
+  if (unitb || mode != STORE_CLASS) throw Error(-6, "eri3: unsupported mode");
   switch (LA * 8 + LB) {
     case 0: eri3_dispatch_pair<0, 0>(LC, a, st); break;
     case 8: eri3_dispatch_pair<1, 0>(LC, a, st); break;

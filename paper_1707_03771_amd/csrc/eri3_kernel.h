@@ -3,7 +3,9 @@
 // One kernel instantiation per shell-triplet class (LA, LB | LC), LA >= LB,
 // and per group of solid-harmonic components of the ket shell.  Each lane owns
 // one orbital shell pair; a workgroup walks a chunk of ket (auxiliary) shells
-// of angular momentum LC, so the whole wave shares one ket shell.  Per root of
+// of angular momentum LC, so the whole wave shares one ket shell.  The raw
+// integrals are stored class by class (STORE_CLASS, see eri_args.h): the
+// lanes of a wave fill one contiguous block of columns.  Per root of
 // the Rys quadrature the lane builds the 2D integrals by the vertical
 // recurrence on (a+b, c) and the horizontal transfer to (a, b), then
 // accumulates the Cartesian products straight into the real solid harmonics of
@@ -85,40 +87,17 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_kernel(const Eri3Args a) {
   constexpr int SA = 2 * LA + 1, SB = UNITB ? 1 : 2 * LB + 1;
   __shared__ double tab[rys_dev_size(NR)];
   rys_stage<NR>(tab, a.rys);
-  // Small bra blocks (3..16 components) are stored through LDS: per ket function
-  // the workgroup writes its pairs' blocks as runs of consecutive columns, one
-  // pair after another, instead of each lane scattering its own block.  Every
-  // lane then passes the same barriers: lanes past the last pair keep a valid
-  // pair's data and store nothing; screened triplets stage zeros (raw starts at
-  // zero, so the result is unchanged).
-  constexpr int NSAB = SA * SB;
-  constexpr bool STAGED = MODE == STORE_PACKED && !UNITB && NSAB > 1 && NSAB <= 16;
-  constexpr int SP = NSAB + 1;
-  __shared__ double stage[STAGED ? ERI_THREADS * SP : 1];
-  __shared__ int64_t pcol_s[STAGED ? ERI_THREADS : 1];
-
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  const bool live = p < a.npairs;
-  if constexpr (!STAGED) {
-    if (!live) return;
-  }
-  const int pp = live ? p : a.npairs - 1;
-  const int f = a.pf[pp];
-  const int s = UNITB ? f : a.ps[pp];
+  if (p >= a.npairs) return;
+  const int f = a.pf[p];
+  const int s = UNITB ? f : a.ps[p];
   const double A0 = a.F.ctr[3 * f], A1 = a.F.ctr[3 * f + 1], A2 = a.F.ctr[3 * f + 2];
   const double B0 = UNITB ? A0 : a.S.ctr[3 * s], B1 = UNITB ? A1 : a.S.ctr[3 * s + 1],
                B2 = UNITB ? A2 : a.S.ctr[3 * s + 2];
   const int nfp = a.F.nprim[f], fpo = a.F.poff[f];
   const int nsp = UNITB ? 1 : a.S.nprim[s], spo = UNITB ? 0 : a.S.poff[s];
-  const int foffF = a.F.foff[f], foffS = UNITB ? 0 : a.S.foff[s];
-  const bool rowF = UNITB ? true : (a.rowfirst[pp] != 0);
-  const double qab = a.pq ? a.pq[pp] : 1.0;
-  const int64_t pcol = MODE == STORE_PACKED ? a.pcol[pp] : 0;
-  const int nvalid = min(ERI_THREADS, a.npairs - (int)(blockIdx.x * blockDim.x));
-  if constexpr (STAGED) {
-    pcol_s[threadIdx.x] = pcol;
-    __syncthreads();
-  }
+  const int foffF = a.F.foff[f];
+  const double qab = a.pq ? a.pq[p] : 1.0;
   const double AB0 = A0 - B0, AB1 = A1 - B1, AB2 = A2 - B2;
   const double rAB2 = AB0 * AB0 + AB1 * AB1 + AB2 * AB2;
   constexpr double TWO_PI_52 = 34.98683665524972;  // 2 pi^(5/2)
@@ -126,10 +105,7 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_kernel(const Eri3Args a) {
   const int c0 = blockIdx.y * a.kchunk;
   const int c1 = min(c0 + a.kchunk, a.nk);
   for (int ci = c0; ci < c1; ++ci) {
-    const bool eval = live && !(MODE == STORE_PACKED && !(qab * a.kq[ci] >= a.tau));
-    if constexpr (!STAGED) {
-      if (!eval) continue;
-    }
+    if (MODE == STORE_CLASS && !(qab * a.kq[ci] >= a.tau)) continue;  // screened: stays zero
     const int kc = a.kl[ci];
     const double C0 = a.K.ctr[3 * kc], C1 = a.K.ctr[3 * kc + 1], C2 = a.K.ctr[3 * kc + 2];
     const int nkp = a.K.nprim[kc], kpo = a.K.poff[kc];
@@ -137,7 +113,7 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_kernel(const Eri3Args a) {
     double acc[NA][NB][GN];
     sfor<NA>([&](auto i) { sfor<NB>([&](auto j) { sfor<GN>([&](auto g) { acc[i][j][g] = 0.0; }); }); });
 
-    for (int ip = 0; ip < (eval ? nfp : 0); ++ip) {
+    for (int ip = 0; ip < nfp; ++ip) {
       const double al = a.F.exps[fpo + ip], ca = a.F.coef[fpo + ip];
       for (int jp = 0; jp < nsp; ++jp) {
         const double be = UNITB ? 0.0 : a.S.exps[spo + jp];
@@ -211,44 +187,23 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_kernel(const Eri3Args a) {
       });
       return v;
     };
-    if constexpr (STAGED) {
-      sfor<GN>([&](auto ig) {
-        constexpr int g = decltype(ig)::value;
-        sfor<SA>([&](auto mai) {
-          constexpr int ma = decltype(mai)::value;
-          sfor<SB>([&](auto mbi) {
-            constexpr int mb = decltype(mbi)::value;
-            // rowF: the lane's first shell is the pair's first (higher-index) shell
-            stage[threadIdx.x * SP + (rowF ? ma * SB + mb : mb * SA + ma)] = bra(mai, mbi, ig);
-          });
-        });
-        __syncthreads();
-        double* const row = out + (int64_t)(kfo + M0 + g) * a.ld;
-        for (int e = threadIdx.x; e < nvalid * NSAB; e += ERI_THREADS) {
-          const int pl = e / NSAB, cm = e - pl * NSAB;
-          row[pcol_s[pl] + cm] = stage[pl * SP + cm];
-        }
-        __syncthreads();
-      });
-    } else {
-      sfor<SA>([&](auto mai) {
-        constexpr int ma = decltype(mai)::value;
-        sfor<SB>([&](auto mbi) {
-          constexpr int mb = decltype(mbi)::value;
-          sfor<GN>([&](auto ig) {
-            constexpr int g = decltype(ig)::value;
-            const double v = bra(mai, mbi, ig);
-            if constexpr (MODE == STORE_PACKED) {
-              // rowF: the lane's first shell is the pair's first (higher-index) shell
-              const int64_t col = pcol + (rowF ? ma * SB + mb : mb * SA + ma);
-              out[(int64_t)(kfo + M0 + g) * a.ld + col] = v;
-            } else {
-              out[(int64_t)(foffF + ma) * a.ld + kfo + M0 + g] = v;
-            }
-          });
+    // STORE_CLASS: the lanes of a wave hold consecutive pairs of the class, so
+    // the SA SB stores of one ket function fill one contiguous block of columns
+    sfor<SA>([&](auto mai) {
+      constexpr int ma = decltype(mai)::value;
+      sfor<SB>([&](auto mbi) {
+        constexpr int mb = decltype(mbi)::value;
+        sfor<GN>([&](auto ig) {
+          constexpr int g = decltype(ig)::value;
+          const double v = bra(mai, mbi, ig);
+          if constexpr (MODE == STORE_CLASS) {
+            out[(int64_t)(kfo + M0 + g) * a.ld + a.cbase + (int64_t)p * (SA * SB) + (ma * SB + mb)] = v;
+          } else {
+            out[(int64_t)(foffF + ma) * a.ld + kfo + M0 + g] = v;
+          }
         });
       });
-    }
+    });
   }
 }
 

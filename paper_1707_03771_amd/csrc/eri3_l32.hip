@@ -7,11 +7,11 @@ template <>
 void eri3_dispatch_pair<3, 2>(int LC, Eri3Args a, hipStream_t st) {
   const dim3 g = eri3_grid(a);
   switch (LC) {
-    case 0: eri3_launch_groups<3, 2, 0, false, STORE_PACKED>(a, g, st); break;
-    case 1: eri3_launch_groups<3, 2, 1, false, STORE_PACKED>(a, g, st); break;
-    case 2: eri3_launch_groups<3, 2, 2, false, STORE_PACKED>(a, g, st); break;
-    case 3: eri3_launch_groups<3, 2, 3, false, STORE_PACKED>(a, g, st); break;
-    case 4: eri3_launch_groups<3, 2, 4, false, STORE_PACKED>(a, g, st); break;
+    case 0: eri3_launch_groups<3, 2, 0, false, STORE_CLASS>(a, g, st); break;
+    case 1: eri3_launch_groups<3, 2, 1, false, STORE_CLASS>(a, g, st); break;
+    case 2: eri3_launch_groups<3, 2, 2, false, STORE_CLASS>(a, g, st); break;
+    case 3: eri3_launch_groups<3, 2, 3, false, STORE_CLASS>(a, g, st); break;
+    case 4: eri3_launch_groups<3, 2, 4, false, STORE_CLASS>(a, g, st); break;
     default: throw Error(-6, "eri3: unsupported auxiliary angular momentum");
   }
 }

@@ -4,17 +4,18 @@
 
 namespace dfx {
 
-// STORE_PACKED: out[P][pcol[pair] + i nb + j], i over the functions of the pair's
-// first (higher-index) shell, j over the nb of its second; STORE_DENSE: out[mu][P]
-enum { STORE_PACKED = 0, STORE_DENSE = 1 };
+// STORE_CLASS: out[P][cbase + p na nb + ma nb + mb] for pair p of the class
+// list, ma over the na functions of its first shell (pf, the larger l), mb over
+// the nb of its second: the raw columns of a class, pair by pair, each pair's
+// block row-major.  STORE_DENSE: out[mu][P].
+enum { STORE_CLASS = 0, STORE_DENSE = 1 };
 
 struct Eri3Args {
   DevShells F, S, K;         // shells of the first and second bra index and of the ket
   const int* pf;             // [npairs] first bra shell (angular momentum LA)
   const int* ps;             // [npairs] second bra shell (LB); unused with UNITB
-  const unsigned char* rowfirst;  // [npairs] 1: first shell indexes rows of B
   const double* pq;          // [npairs] Schwarz factor of the pair, or null
-  const int64_t* pcol;       // [npairs] first packed column of the pair (STORE_PACKED)
+  int64_t cbase;             // first raw column of the class (STORE_CLASS)
   int npairs;
   const int* kl;             // [nk] ket shells of angular momentum LC
   const double* kq;          // [nk] their Schwarz factors

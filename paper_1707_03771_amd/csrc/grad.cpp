@@ -191,15 +191,18 @@ int dfx_rhf_grad(const dfx_geom* geom, const dfx_shell* shells, int nsh, const d
     dvec.release();
 
     // ---- Gam~ in raw's packed columns, b_Q = C^T X_Q, chunk by chunk of Q
+    // (mu, nu) of every raw column (class by class, pair by pair, as the ERIs store it)
     std::vector<int> cmu(ncols), cnu(ncols);
-    for (size_t k = 0; k < B->pa.size(); ++k) {
-      const int a = B->pa[k], b = B->pb[k];
-      const int na = 2 * bas.l[a] + 1, nb = 2 * bas.l[b] + 1;
-      for (int i = 0; i < na; ++i)
-        for (int j = 0; j < nb; ++j) {
-          cmu[B->col_off[k] + i * nb + j] = bas.foff[a] + i;
-          cnu[B->col_off[k] + i * nb + j] = bas.foff[b] + j;
-        }
+    for (int cls = 0; cls < 16; ++cls) {
+      const int SA = 2 * (cls / 4) + 1, SB = 2 * (cls % 4) + 1;
+      const int64_t npc = (int64_t)B->cls_f[cls].size();
+      for (int64_t p = 0; p < npc; ++p)
+        for (int ma = 0; ma < SA; ++ma)
+          for (int mb = 0; mb < SB; ++mb) {
+            const int64_t col = B->cls_base[cls] + p * (SA * SB) + (ma * SB + mb);
+            cmu[col] = bas.foff[B->cls_f[cls][p]] + ma;
+            cnu[col] = bas.foff[B->cls_s[cls][p]] + mb;
+          }
     }
     DevMem cmu_d = upload(cmu, st), cnu_d = upload(cnu, st);
     DevMem Gam(8 * (size_t)naux * std::max<int64_t>(ncols, 1));
@@ -251,25 +254,15 @@ int dfx_rhf_grad(const dfx_geom* geom, const dfx_shell* shells, int nsh, const d
         for (int c : auxby[l]) q.push_back(B->QC[c]);
         qcl_d[l] = upload(q, st);
       }
-      std::vector<std::vector<int>> cf(16), cs(16);
-      std::vector<std::vector<unsigned char>> crow(16);
+      const std::vector<std::vector<int>>& cf = B->cls_f;
+      const std::vector<std::vector<int>>& cs = B->cls_s;
       std::vector<std::vector<double>> cq(16);
-      std::vector<std::vector<int64_t>> cpc(16);
-      for (size_t k = 0; k < B->pa.size(); ++k) {
-        const int a = B->pa[k], b = B->pb[k];
-        const int la = bas.l[a], lb = bas.l[b];
-        const int cls = std::max(la, lb) * 4 + std::min(la, lb);
-        cf[cls].push_back(la >= lb ? a : b);
-        cs[cls].push_back(la >= lb ? b : a);
-        crow[cls].push_back(la >= lb ? 1 : 0);
-        cq[cls].push_back(B->Qab[(size_t)a * bas.nsh + b]);
-        cpc[cls].push_back(B->col_off[k]);
-      }
+      for (int cls = 0; cls < 16; ++cls)
+        for (size_t p = 0; p < cf[cls].size(); ++p) cq[cls].push_back(B->Qab[(size_t)cf[cls][p] * bas.nsh + cs[cls][p]]);
       sp_3.begin();
       for (int cls = 0; cls < 16; ++cls) {
         if (cf[cls].empty()) continue;
-        DevMem f_d = upload(cf[cls], st), s_d = upload(cs[cls], st), r_d = upload(crow[cls], st),
-               q_d = upload(cq[cls], st), c_d = upload(cpc[cls], st);
+        DevMem f_d = upload(cf[cls], st), s_d = upload(cs[cls], st), q_d = upload(cq[cls], st);
         const int LA = cls / 4, LB = cls % 4;
         for (int lc = 0; lc <= 4; ++lc) {
           if (auxby[lc].empty()) continue;
@@ -280,9 +273,8 @@ int dfx_rhf_grad(const dfx_geom* geom, const dfx_shell* shells, int nsh, const d
           e.K = B->daux.view();
           e.pf = f_d.as<int>();
           e.ps = s_d.as<int>();
-          e.rowfirst = r_d.as<unsigned char>();
           e.pq = q_d.as<double>();
-          e.pcol = c_d.as<int64_t>();
+          e.cbase = B->cls_base[cls];
           e.npairs = (int)cf[cls].size();
           e.kl = auxby_d[lc].as<int>();
           e.kq = qcl_d[lc].as<double>();

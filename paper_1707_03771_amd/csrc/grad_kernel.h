@@ -25,7 +25,7 @@ namespace dfx {
 
 struct GradArgs {
   Eri3Args e;              // lists, shells, Rys table; out/ld unused
-  const double* gam;       // Gam [P][ld] (packed columns) or Gam2 [P][Q] (UNITB)
+  const double* gam;       // Gam [P][ldg] (raw's columns, class by class) or Gam2 [P][Q] (UNITB)
   int64_t ldg;
   double* pbuf;            // [gridDim.y][npairs]: per lane and ket chunk
   double* kbuf;            // [nk][gridDim.x]: per ket shell and workgroup
@@ -69,9 +69,7 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_grad_kernel(const GradArgs g
   const int nfp = a.F.nprim[f], fpo = a.F.poff[f];
   const int nsp = UNITB ? 1 : a.S.nprim[s], spo = UNITB ? 0 : a.S.poff[s];
   const int foffF = a.F.foff[f];
-  const bool rowF = UNITB ? true : (a.rowfirst[pp] != 0);
   const double qab = a.pq ? a.pq[pp] : 1.0;
-  const int64_t pcol = UNITB ? 0 : a.pcol[pp];
   // a pair of two different shells stands for both orders of its block
   const double wpair = (!UNITB && f != s) ? ga.scale_off : 1.0;
   const double AB0 = A0 - B0, AB1 = A1 - B1, AB2 = A2 - B2;
@@ -176,7 +174,7 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_grad_kernel(const GradArgs g
             });
             const int P = kfo + M0 + g;
             const double wgt = UNITB ? ga.gam[(int64_t)(foffF + ma) * ga.ldg + P]
-                                     : ga.gam[(int64_t)P * ga.ldg + pcol + (rowF ? ma * SB + mb : mb * SA + ma)];
+                                     : ga.gam[(int64_t)P * ga.ldg + a.cbase + (int64_t)p * (SA * SB) + (ma * SB + mb)];
             s_ket = fma(v, wgt, s_ket);
           });
         });

@@ -180,6 +180,13 @@ struct dfx_B {
   dfx::DevMem hi, lo, raw, J2, L;   // device tensors
   dfx::DevMem work;                 // grow-only scratch for dfx_jk
   dfx::DevMem toff;                 // packed column -> tile offset (built on demand)
+  // raw's column layout: class cls = 4 max(la, lb) + min(la, lb) holds its pairs
+  // (first shell cls_f, the larger l; second cls_s) from column cls_base[cls],
+  // component-major: column cls_base + (ma nb + mb) npairs_cls + p
+  std::vector<std::vector<int>> cls_f, cls_s;
+  std::vector<int64_t> cls_base;    // [17]
+  std::vector<int64_t> rawcol;      // canonical packed column -> raw column
+  dfx::DevMem rawcol_d;             // (built on demand, for the raw export)
   dfx_B_info info{};
   void* ensure_work(size_t bytes);
 };

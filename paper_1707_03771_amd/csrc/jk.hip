@@ -146,7 +146,7 @@ void k_build(const JKArgs& a, const double* C, int nocc, double* K, void* work, 
 }
 
 // ---------------------------------------------------------------------------
-// canonical packed export: out[q - q0][c] = B[q][tileoff[c]] (hi + lo), or raw[q][c]
+// canonical packed export: out[q - q0][c] = B[q][toff[c]] (hi + lo), or raw[q][toff[c]]
 __global__ void export_kernel(const float* __restrict__ hi, const float* __restrict__ lo,
                               const double* __restrict__ raw, int64_t ncols_t,
                               const int64_t* __restrict__ toff, int64_t ncols_p, int q0,
@@ -154,9 +154,10 @@ __global__ void export_kernel(const float* __restrict__ hi, const float* __restr
   const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= ncols_p) return;
   const int q = q0 + blockIdx.y;
-  const int64_t o = (int64_t)q * ncols_t + toff[c];
+  // toff[c]: the tile offset of canonical column c in B's rows, or its raw column
   out[(int64_t)blockIdx.y * ncols_p + c] =
-      raw ? raw[(int64_t)q * ncols_p + c] : (double)hi[o] + (lo ? (double)lo[o] : 0.0);
+      raw ? raw[(int64_t)q * ncols_p + toff[c]]
+          : (double)hi[(int64_t)q * ncols_t + toff[c]] + (lo ? (double)lo[(int64_t)q * ncols_t + toff[c]] : 0.0);
 }
 
 // out[q - q0][mu][nu] = B_q (mu, nu) = hi + lo at the packed tile position

@@ -13,7 +13,7 @@ parity bound (1e-13 of the largest element plus 1e-15).
 """
 import numpy as np
 import pytest
-from hypothesis import HealthCheck, given, settings
+from hypothesis import HealthCheck, assume, given, settings
 from hypothesis import strategies as st
 
 import oracle as O
@@ -91,7 +91,7 @@ def test_rotation_keeps_block_norm(t3, seed):
     assert abs(n1 - n0) <= 1e-12 * max(1.0, n0)
     # the rotation acts on the block, reshaped to [n_a n_b][n_C], by orthogonal
     # matrices on both sides, so its singular values are invariant as well
-    s0 =np.linalg.svd(ref.reshape(-1, ref.shape[2]), compute_uv=False)
+    s0 = np.linalg.svd(ref.reshape(-1, ref.shape[2]), compute_uv=False)
     s1 = np.linalg.svd(rot.reshape(-1, rot.shape[2]), compute_uv=False)
     assert np.abs(s1 - s0).max() <= 1e-12 * max(1.0, s0.max())
 
@@ -115,11 +115,12 @@ def test_schwarz_inequality(t3):
 
 @st.composite
 def shell_set(draw):
-    """2 or 3 centres; 1-3 orbital shells each (l <= 3, 1-3 primitives); at most
-    one auxiliary shell per (centre, l), l <= 4, so the metric stays positive
-    definite."""
+    """2 or 3 centres at least 1 bohr apart; 1-3 orbital shells each (l <= 3,
+    1-3 primitives); at most one auxiliary shell per (centre, l), l <= 4, so
+    the metric stays positive definite."""
     n = draw(st.integers(2, 3))
     ctrs = [np.array(draw(centre)) * 1.5 for _ in range(n)]
+    assume(min(np.linalg.norm(ctrs[i] - ctrs[j]) for i in range(n) for j in range(i)) >= 1.0)
     sh, ax = [], []
     for r in ctrs:
         for _ in range(draw(st.integers(1, 3))):
