@@ -36,7 +36,7 @@
  *               them.  dfx_scf / dfx_uhf / dfx_rohf do the same with
  *               dfx_scf_opts.workspace (sized by dfx_scf_plan); without one
  *               they allocate per call.  The remaining entry points
- *               (dfx_mp2, dfx_lowdin, dfx_int1e, dfx_metric, dfx_cholesky, the
+ *               (dfx_mp2, dfx_lowdin, dfx_int1e, dfx_metric, dfx_cholesky, dfx_eigh, the
  *               learned guess) allocate their own scratch and free it before
  *               returning, except a guess model's weights, which it holds
  *               until dfx_guess_free.
@@ -281,6 +281,20 @@ int dfx_metric(const dfx_shell* aux, int nauxsh, double* dev_J, void* stream);
  * original diagonal element.  Synchronises the stream.
  */
 int dfx_cholesky(double* dev_A, int n, double* dev_Linv, void* stream);
+
+/*
+ * dfx_eigh -- all eigenpairs of a symmetric n x n matrix (device, row-major;
+ * its symmetric part (A + A^T) / 2 is used), the eigen-decomposition behind
+ * the SCF's orthogonaliser and orbitals (section "Standard algorithms").  On
+ * return the rows of dev_A are orthonormal eigenvectors and dev_w (device, n)
+ * holds the eigenvalues in ascending order, row k belonging to dev_w[k].
+ * Two-sided block Jacobi (32 x 32 blocks, cyclic parallel ordering) until a
+ * sweep finds every off-diagonal element below 1e-15 sqrt(|a_ii a_jj|).
+ * Allocates its scratch (two padded copies of the matrix) and frees it
+ * before returning; synchronises the stream.  *sweeps (may be NULL) gets the
+ * number of Jacobi sweeps.  DFX_EHIP if 40 sweeps do not converge.
+ */
+int dfx_eigh(double* dev_A, int n, double* dev_w, int* sweeps, void* stream);
 
 /* ---- SCF ---------------------------------------------------------------------- */
 #define DFX_GUESS_CORE 0

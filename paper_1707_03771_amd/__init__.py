@@ -134,6 +134,7 @@ _SIGS = {
     "dfx_scf_default_opts": [_vp],
     "dfx_metric": [_vp, _i, _vp, _vp],
     "dfx_cholesky": [_vp, _i, _vp, _vp],
+    "dfx_eigh": [_vp, _i, _vp, _vp, _vp],
     "dfx_guess_create": [_vp, _vp],
     "dfx_guess_free": [_vp],
     "dfx_guess_add": [_vp, _vp, _vp],
@@ -369,6 +370,17 @@ def cholesky(A, stream=None):
     Linv = torch.empty_like(L)
     _check(_lib.dfx_cholesky(_ptr(L), L.shape[0], _ptr(Linv), _stream(stream)))
     return L, Linv
+
+
+def eigh(A, stream=None):
+    """dfx_eigh: (w, V, sweeps) of a symmetric cuda tensor, w ascending and the
+    columns of V the eigenvectors (V[:, k] belongs to w[k])."""
+    import torch
+    W = A.detach().to(torch.float64).clone().contiguous()
+    w = torch.empty(W.shape[0], dtype=torch.float64, device=W.device)
+    sw = ctypes.c_int(0)
+    _check(_lib.dfx_eigh(_ptr(W), W.shape[0], _ptr(w), ctypes.byref(sw), _stream(stream)))
+    return w, W.T, sw.value
 
 
 # ---- run log -------------------------------------------------------------------

@@ -258,9 +258,10 @@ int64_t dfx::jk_need(int nbf, int naux, int64_t ncols_t) {
     for (int nocc = 1; nocc <= std::min(nbf, 512); ++nocc) kmax = std::max<int64_t>(kmax, k_work_bytes(a, nocc));
   }
   const int64_t jw = pad256(8 * (2 * ncols_t + naux + 8)) + pad256(8 * n2);
-  // the density route adds its eigenvectors, one K and a chunk of 512 columns
+  // the density route adds its eigen-decomposition (and eigenvectors), one K
+  // and a chunk of 512 columns
   const int64_t dens = pad256(8 * n2) * 2 + pad256(8 * (int64_t)nbf) + pad256(8 * (int64_t)nbf * 512) +
-                       pad256(512 * 4) + pad256(512 * 8) + pad256(kmax);
+                       pad256(512 * 4) + pad256(512 * 8) + pad256(kmax) + pad256(sym_eig_work_bytes(nbf));
   return pad256(std::max(jw, kmax)) + dens;
 }
 
@@ -290,7 +291,8 @@ int64_t dfx::scf_need(const HostShells& b, const HostShells& a, int natom, int d
   const int64_t n = b.nbf, n2 = pad256(8 * n * n);
   // the SCF's dense matrices (open shell: both spins, 2 x diis_size entries each
   // for the Fock matrices and errors), their thin companions and small buffers
-  const int64_t mats = (26 + 4 * (int64_t)diis_size) * n2 + 8 * pad256(8 * n * 512) + 512 * 256;
+  const int64_t mats = (26 + 4 * (int64_t)diis_size) * n2 + 8 * pad256(8 * n * 512) + 512 * 256 +
+                       pad256(sym_eig_work_bytes((int)n));  // eigen-decompositions (eig.hip)
   // learned guess: per pair-type inputs, outputs and network work, FP32
   const int64_t guess = (int64_t)natom * natom * 4 * 9842 + ((int64_t)1 << 20);
   const int64_t pre = 4 * n2 + 3 * 256;  // split-K partials and small buffers made before B
@@ -705,6 +707,14 @@ int dfx_cholesky(double* dev_A, int n, double* dev_Linv, void* stream) {
     DFX_HIP(hipMemcpyAsync(&info, info_d.p, sizeof(int), hipMemcpyDeviceToHost, st));
     DFX_HIP(hipStreamSynchronize(st));
     if (info != 0) throw Error(DFX_ENOTPOSDEF, "matrix is not positive definite (pivot " + std::to_string(info - 1) + ")");
+  });
+}
+
+int dfx_eigh(double* dev_A, int n, double* dev_w, int* sweeps, void* stream) {
+  return guard([&] {
+    if (!dev_A || !dev_w || n <= 0) throw Error(DFX_EINVAL, "dfx_eigh: bad argument");
+    const int s = sym_eig(dev_A, n, dev_w, (hipStream_t)stream);
+    if (sweeps) *sweeps = s;
   });
 }
 

@@ -94,7 +94,6 @@ const double* rys_table_device();  // per current device, built on first use
 // made on first use and kept until the process ends.
 struct DevCtx {
   hipStream_t st = nullptr;
-  void* rb = nullptr;  // rocblas_handle
 };
 DevCtx& thread_ctx();
 

@@ -85,6 +85,15 @@ void cholesky_inverse(double* J, int n, double* Linv, double* work, int* info, h
 void cholesky_factor(double* J, int n, double* work, int* info, hipStream_t st);
 size_t cholesky_work_elems(int n);
 
+// Symmetric eigen-decomposition by the two-sided block Jacobi method (eig.hip):
+// A (n x n, row-major; the symmetric part is used) is overwritten with the
+// orthonormal eigenvectors as rows, w (device, n) gets the eigenvalues in
+// ascending order.  Every off-diagonal element of the final rotated matrix is
+// below 1e-15 sqrt(|a_ii a_jj|).  Synchronous; returns the number of sweeps;
+// throws after 40 sweeps.  Device memory: sym_eig_work_bytes(n).
+int sym_eig(double* A, int n, double* w, hipStream_t st);
+size_t sym_eig_work_bytes(int n);
+
 // ---- J / K (jk.hip) ----------------------------------------------------------
 enum Prec { PREC_FP64 = 0, PREC_FP32 = 1, PREC_BF16 = 2 };
 struct JKArgs {

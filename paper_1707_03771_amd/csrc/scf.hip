@@ -14,8 +14,6 @@
 // followed by a Cholesky QR (applied twice) of the projector times the previous
 // occupied orbitals; rocSOLVER's dsyevd serves the starting guess, the final
 // orbitals and energies, and any purification that does not converge.
-#include <rocblas/rocblas.h>
-#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <chrono>
@@ -300,21 +298,14 @@ DevCtx& thread_ctx() {
   DFX_HIP(hipGetDevice(&dev));
   DevCtx& c = ctx[dev];
   if (!c.st) DFX_HIP(hipStreamCreate(&c.st));
-  if (!c.rb) {
-    // the handle's own scratch is its for the process: never from a call's workspace
-    rocblas_handle h = nullptr;
-    if (rocblas_create_handle(&h) != rocblas_status_success) throw Error(DFX_EHIP, "rocblas_create_handle failed");
-    c.rb = h;
-  }
   return c;
 }
 
 // ---- driver ---------------------------------------------------------------------------
 struct Scf {
   hipStream_t st{};
-  rocblas_handle rb{};
   int n = 0, m = 0, nocc = 0;
-  DevMem part, eig_e, eig_info, gw;  // gw: split-K partial products
+  DevMem part, gw;  // gw: split-K partial products
   DevMem qr_linv, qr_work, qr_z, qr_info;  // Cholesky QR of the purified occupied space
   std::vector<double> hpart;
   EventSpans* eig_spans = nullptr;
@@ -422,17 +413,11 @@ struct Scf {
     return true;
   }
   // symmetric eigen-decomposition in place: A (k x k) -> rows are eigenvectors, w ascending
+  // (the library's block Jacobi, eig.hip)
   void syevd(double* A, int k, double* w) {
-    if (eig_e.n < sizeof(double) * k) eig_e.alloc(sizeof(double) * k);
     if (eig_spans) eig_spans->begin();
-    if (rocsolver_dsyevd(rb, rocblas_evect_original, rocblas_fill_upper, k, A, k, w, eig_e.as<double>(),
-                         eig_info.as<rocblas_int>()) != rocblas_status_success)
-      throw Error(DFX_EHIP, "rocsolver_dsyevd failed");
+    sym_eig(A, k, w, st);
     if (eig_spans) eig_spans->end();
-    int info = 0;
-    DFX_HIP(hipMemcpyAsync(&info, eig_info.p, sizeof(int), hipMemcpyDeviceToHost, st));
-    DFX_HIP(hipStreamSynchronize(st));
-    if (info != 0) throw Error(DFX_EHIP, "rocsolver_dsyevd did not converge");
   }
 };
 
@@ -496,9 +481,6 @@ void k_from_density(const JKArgs& a, const double* D, double* K, hipStream_t st)
   const int64_t n2 = (int64_t)n * n;
   Scf S;
   S.st = st;
-  S.rb = (rocblas_handle)thread_ctx().rb;
-  rocblas_set_stream(S.rb, st);
-  S.eig_info.alloc(sizeof(int));
   DevMem W(8 * n2), lam(8 * (size_t)n);
   DFX_HIP(hipMemcpyAsync(W.p, D, 8 * n2, hipMemcpyDeviceToDevice, st));
   S.syevd(W.as<double>(), n, lam.as<double>());
@@ -626,8 +608,6 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     {
       DevCtx& ctx = thread_ctx();
       S.st = ctx.st;
-      S.rb = (rocblas_handle)ctx.rb;
-      rocblas_set_stream(S.rb, S.st);
     }
     hipStream_t st = S.st;
     S.n = n;
@@ -638,7 +618,6 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     EventSpans sp_eig_all;
     sp_eig_all.st = S.st;
     S.eig_spans = &sp_eig_all;
-    S.eig_info.alloc(sizeof(int));
     const int64_t n2 = (int64_t)n * n;
 
     // ---- setup: fitted integrals, one-electron matrices, E_nn, orthogonaliser
@@ -1139,15 +1118,12 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
     {
       DevCtx& ctx = thread_ctx();
       S.st = ctx.st;
-      S.rb = (rocblas_handle)ctx.rb;
-      rocblas_set_stream(S.rb, S.st);
     }
     hipStream_t st = S.st;
     S.n = n;
     S.nocc = na;
     S.part.alloc(sizeof(double) * 512);
     S.gw.alloc(sizeof(double) * 4 * (size_t)n * n);
-    S.eig_info.alloc(sizeof(int));
     const int64_t n2 = (int64_t)n * n;
 
     // setup: fitted integrals, one-electron matrices, E_nn, canonical orthogonaliser
@@ -1457,9 +1433,6 @@ int dfx_lowdin(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dou
     const int64_t n2 = (int64_t)n * n;
     Scf S;
     S.st = (hipStream_t)stream;
-    S.rb = (rocblas_handle)thread_ctx().rb;
-    rocblas_set_stream(S.rb, S.st);
-    S.eig_info.alloc(sizeof(int));
     hipStream_t st = S.st;
     DevMem W(8 * n2), Tm(8 * n2), Vm(8 * n2), sv(8 * (size_t)n);
     int1e_build(hb, geom, W.as<double>(), Tm.as<double>(), Vm.as<double>(), st);

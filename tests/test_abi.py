@@ -61,6 +61,9 @@ def test_argument_errors_are_status_codes():
     # jk / B calls on a NULL handle
     assert lib.dfx_jk(None, None, 1, 1, 0, None, None, None) == dfx.EINVAL
     assert lib.dfx_B_info_get(None, None) == dfx.EINVAL
+    # eigen-decomposition: NULL matrix, NULL eigenvalues, empty size
+    assert lib.dfx_eigh(None, 4, None, None, None) == dfx.EINVAL
+    assert lib.dfx_eigh(ctypes.c_void_p(16), 0, ctypes.c_void_p(16), None, None) == dfx.EINVAL
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libdfx.so not built")
