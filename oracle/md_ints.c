@@ -155,18 +155,36 @@ static void hermite_R(int L, double alpha, double X, double Y, double Z, double 
 #define RIX(t, u, v) (((t) * RD + (u)) * RD + (v))
 
 /* Hermite expansion of one (bra) product in all three directions */
+/* The product centre P = (a A + b B) / p is kept as A and P - A = b (B - A) / p:
+   differences of product centres are then formed from centre differences, so
+   they vanish exactly for concentric functions and do not depend on where the
+   origin lies (P itself, rounded, carries an error of the size of the
+   coordinates' last digit). */
 typedef struct {
   double Ex[ED][ED][2 * ED], Ey[ED][ED][2 * ED], Ez[ED][ED][2 * ED];
-  double p, P[3];
+  double p, A[3], PA[3];
 } hprod;
 
 static void make_prod(hprod *h, int la, int lb, double a, const double *A, double b,
                       const double *B) {
   h->p = a + b;
-  for (int k = 0; k < 3; ++k) h->P[k] = (a * A[k] + b * B[k]) / h->p;
+  for (int k = 0; k < 3; ++k) {
+    h->A[k] = A[k];
+    h->PA[k] = b / h->p * (B[k] - A[k]);
+  }
   hermite_E(la, lb, a, b, A[0] - B[0], h->Ex);
   hermite_E(la, lb, a, b, A[1] - B[1], h->Ey);
   hermite_E(la, lb, a, b, A[2] - B[2], h->Ez);
+}
+
+/* P - Q of a bra and a ket product */
+static void pq_diff(const hprod *b, const hprod *k, double d[3]) {
+  for (int i = 0; i < 3; ++i) d[i] = (b->A[i] - k->A[i]) + (b->PA[i] - k->PA[i]);
+}
+
+/* P - C for a point C */
+static void pc_diff(const hprod *h, const double *C, double d[3]) {
+  for (int i = 0; i < 3; ++i) d[i] = (h->A[i] - C[i]) + h->PA[i];
 }
 
 /* ---- spherical transform of one index of a contracted Cartesian block ----
@@ -229,7 +247,9 @@ static void eri_generic(const oshell *A, const oshell *B, const oshell *C, const
         for (int id = 0; id < D->nprim; ++id) {
           make_prod(hk, lc, ld, C->exps[ic], C->ctr, D->exps[id], D->ctr);
           const double p = hb->p, q = hk->p, alpha = p * q / (p + q);
-          hermite_R(L, alpha, hb->P[0] - hk->P[0], hb->P[1] - hk->P[1], hb->P[2] - hk->P[2], R);
+          double d[3];
+          pq_diff(hb, hk, d);
+          hermite_R(L, alpha, d[0], d[1], d[2], R);
           const double pref = cab * C->coef[ic] * D->coef[id] * 2.0 * pow(PI, 2.5) /
                               (p * q * sqrt(p + q));
           int idx = 0;
@@ -433,8 +453,9 @@ static void onee_block(const oshell *A, const oshell *B, int natom, const double
                             (D1[0] * S1[1] * S1[2] + S1[0] * D1[1] * S1[2] + S1[0] * S1[1] * D1[2]);
         }
       for (int C = 0; C < natom; ++C) {
-        hermite_R(la + lb, p, h->P[0] - xyz[3 * C], h->P[1] - xyz[3 * C + 1],
-                  h->P[2] - xyz[3 * C + 2], R);
+        double d[3];
+        pc_diff(h, xyz + 3 * C, d);
+        hermite_R(la + lb, p, d[0], d[1], d[2], R);
         const double pref = -Z[C] * 2.0 * PI / p * w;
         for (int i = 0; i < na; ++i)
           for (int j = 0; j < nb; ++j) {
@@ -540,7 +561,9 @@ static void eri_generic_deriv(const oshell *A, const oshell *B, const oshell *C,
         for (int id = 0; id < D->nprim; ++id) {
           make_prod(hk, l[2] + up2, l[3] + up3, C->exps[ic], C->ctr, D->exps[id], D->ctr);
           const double p = hb->p, q = hk->p, alpha = p * q / (p + q);
-          hermite_R(L, alpha, hb->P[0] - hk->P[0], hb->P[1] - hk->P[1], hb->P[2] - hk->P[2], R);
+          double d[3];
+          pq_diff(hb, hk, d);
+          hermite_R(L, alpha, d[0], d[1], d[2], R);
           const double pref = cab * C->coef[ic] * D->coef[id] * 2.0 * pow(PI, 2.5) / (p * q * sqrt(p + q));
           const double ex = which == 0 ? A->exps[ia] : which == 1 ? B->exps[ib] : which == 2 ? C->exps[ic]
                                                                                               : D->exps[id];
@@ -773,7 +796,9 @@ void oracle_int1e_grad(const obasis *bs, int nbf, const int *atom_bs, int natom,
               }
             for (int C = 0; C < natom; ++C) {
               const double *Cc = xyz + 3 * C;
-              hermite_R(la + lb + 1, h->p, h->P[0] - Cc[0], h->P[1] - Cc[1], h->P[2] - Cc[2], R);
+              double d[3];
+              pc_diff(h, Cc, d);
+              hermite_R(la + lb + 1, h->p, d[0], d[1], d[2], R);
               for (int i = 0; i < na; ++i)
                 for (int j = 0; j < nb; ++j) {
                   const double wd = cd[i * nb + j];

