@@ -119,14 +119,15 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_kernel(const Eri3Args a) {
         const double be = UNITB ? 0.0 : a.S.exps[spo + jp];
         const double cb = UNITB ? 1.0 : a.S.coef[spo + jp];
         const double pp = al + be, ip_ = 1.0 / pp;
-        const double P0 = (al * A0 + be * B0) * ip_, P1 = (al * A1 + be * B1) * ip_,
-                     P2 = (al * A2 + be * B2) * ip_;
+        // P - A = b (B - A) / p from the centre difference: exactly zero for
+        // concentric functions and independent of the origin
+        const double bp = be * ip_;
         const double Kab = UNITB ? 1.0 : exp(-al * be * ip_ * rAB2);
-        const double PA0 = P0 - A0, PA1 = P1 - A1, PA2 = P2 - A2;
+        const double PA0 = -bp * AB0, PA1 = -bp * AB1, PA2 = -bp * AB2;
         for (int kp = 0; kp < nkp; ++kp) {
           const double q = a.K.exps[kpo + kp], cc = a.K.coef[kpo + kp];
           const double pq = pp + q, ipq = 1.0 / pq;
-          const double PC0 = P0 - C0, PC1 = P1 - C1, PC2 = P2 - C2;
+          const double PC0 = PA0 + (A0 - C0), PC1 = PA1 + (A1 - C1), PC2 = PA2 + (A2 - C2);
           const double rho = pp * q * ipq;
           const double T = rho * (PC0 * PC0 + PC1 * PC1 + PC2 * PC2);
           const double pref = TWO_PI_52 / (pp * q * sqrt(pq)) * Kab * ca * cb * cc;

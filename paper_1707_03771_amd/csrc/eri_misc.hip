@@ -64,18 +64,17 @@ __global__ void __launch_bounds__(64) schwarz_kernel(SchwarzArgs a) {
     for (int j1 = 0; j1 < n2; ++j1) {
       const double al = a.sh.exps[o1 + i1], be = a.sh.exps[o2 + j1];
       const double p1 = al + be;
-      const double P[3] = {(al * A[0] + be * B[0]) / p1, (al * A[1] + be * B[1]) / p1,
-                           (al * A[2] + be * B[2]) / p1};
+      // P - A = b (B - A) / p from the centre difference (exact for concentric pairs)
+      const double PA[3] = {be / p1 * (B[0] - A[0]), be / p1 * (B[1] - A[1]), be / p1 * (B[2] - A[2])};
       const double K1 = exp(-al * be / p1 * rAB2) * a.sh.coef[o1 + i1] * a.sh.coef[o2 + j1];
       for (int i2 = 0; i2 < n1; ++i2)
         for (int j2 = 0; j2 < n2; ++j2) {
           const double ga = a.sh.exps[o1 + i2], de = a.sh.exps[o2 + j2];
           const double q = ga + de;
-          const double Q[3] = {(ga * A[0] + de * B[0]) / q, (ga * A[1] + de * B[1]) / q,
-                               (ga * A[2] + de * B[2]) / q};
+          const double QA[3] = {de / q * (B[0] - A[0]), de / q * (B[1] - A[1]), de / q * (B[2] - A[2])};
           const double K2 = exp(-ga * de / q * rAB2) * a.sh.coef[o1 + i2] * a.sh.coef[o2 + j2];
           const double pq = p1 + q;
-          const double PQ[3] = {P[0] - Q[0], P[1] - Q[1], P[2] - Q[2]};
+          const double PQ[3] = {PA[0] - QA[0], PA[1] - QA[1], PA[2] - QA[2]};
           const double T = p1 * q / pq * (PQ[0] * PQ[0] + PQ[1] * PQ[1] + PQ[2] * PQ[2]);
           const double pref = TWO_PI_52 / (p1 * q * sqrt(pq)) * K1 * K2;
           const RysPoint<NR> rp(tab, T);
@@ -84,8 +83,8 @@ __global__ void __launch_bounds__(64) schwarz_kernel(SchwarzArgs a) {
             rp.get(r, u, w);
             if (lane < 3) {
               const int x = lane;
-              const double C00 = (P[x] - A[x]) - q / pq * PQ[x] * u;
-              const double D00 = (Q[x] - A[x]) + p1 / pq * PQ[x] * u;
+              const double C00 = PA[x] - q / pq * PQ[x] * u;
+              const double D00 = QA[x] + p1 / pq * PQ[x] * u;
               const double B00 = 0.5 * u / pq;
               const double B10 = 0.5 / p1 * (1.0 - q / pq * u);
               const double B01 = 0.5 / q * (1.0 - p1 / pq * u);
@@ -201,9 +200,9 @@ __global__ void __launch_bounds__(64) onee_st_kernel(OneEArgs a) {
       double S[3][LA + 1][LB + 3], K[3][LA + 1][LB + 1];
 #pragma unroll
       for (int x = 0; x < 3; ++x) {
-        const double P = (al * A[x] + be * B[x]) / pp;
         const double XAB = A[x] - B[x];
-        const double PA = P - A[x], PB = P - B[x];
+        // P - A and P - B from the centre difference (exact for concentric pairs)
+        const double PA = -be / pp * XAB, PB = al / pp * XAB;
         S[x][0][0] = sqrt(M_PI / pp) * exp(-al * be / pp * XAB * XAB);
 #pragma unroll
         for (int j = 0; j < LB + 2; ++j)
@@ -283,10 +282,11 @@ __global__ void __launch_bounds__(64) onee_v_kernel(OneEArgs a) {
       const double cf = a.sh.coef[a.sh.poff[s1] + i1] * a.sh.coef[a.sh.poff[s2] + j1] *
                         exp(-al * be / pp * (AB[0] * AB[0] + AB[1] * AB[1] + AB[2] * AB[2])) *
                         2.0 * M_PI / pp;
-      const double P[3] = {(al * A[0] + be * B[0]) / pp, (al * A[1] + be * B[1]) / pp,
-                           (al * A[2] + be * B[2]) / pp};
+      // P - A = b (B - A) / p, P - C = (P - A) + (A - C): exact for concentric centres
+      const double PA[3] = {-be / pp * AB[0], -be / pp * AB[1], -be / pp * AB[2]};
       for (int c = 0; c < a.natom; ++c) {
-        const double PC[3] = {P[0] - a.xyz[3 * c], P[1] - a.xyz[3 * c + 1], P[2] - a.xyz[3 * c + 2]};
+        const double PC[3] = {PA[0] + (A[0] - a.xyz[3 * c]), PA[1] + (A[1] - a.xyz[3 * c + 1]),
+                              PA[2] + (A[2] - a.xyz[3 * c + 2])};
         const double T = pp * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
         const double z = -a.Z[c] * cf;
         const RysPoint<NR> rp(tab, T);
@@ -298,7 +298,7 @@ __global__ void __launch_bounds__(64) onee_v_kernel(OneEArgs a) {
           double H[3][LA + 1][LB + 1];
 #pragma unroll
           for (int x = 0; x < 3; ++x) {
-            const double C00 = (P[x] - A[x]) - u * PC[x];
+            const double C00 = PA[x] - u * PC[x];
             double G[E + 1];
             G[0] = (x == 2) ? w * z : 1.0;
 #pragma unroll

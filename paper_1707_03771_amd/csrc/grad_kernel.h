@@ -94,14 +94,14 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_grad_kernel(const GradArgs g
         const double be = UNITB ? 0.0 : a.S.exps[spo + jp];
         const double cb = UNITB ? 1.0 : a.S.coef[spo + jp];
         const double pp_ = al + be, ip_ = 1.0 / pp_;
-        const double P0 = (al * A0 + be * B0) * ip_, P1 = (al * A1 + be * B1) * ip_, P2 = (al * A2 + be * B2) * ip_;
+        const double bp = be * ip_;  // P - A = b (B - A) / p, as in the ERI kernel
         const double Kab = UNITB ? 1.0 : exp(-al * be * ip_ * rAB2);
-        const double PA0 = P0 - A0, PA1 = P1 - A1, PA2 = P2 - A2;
+        const double PA0 = -bp * AB0, PA1 = -bp * AB1, PA2 = -bp * AB2;
         const double ex2 = 2.0 * (WHICH == 0 ? al : be);  // 2 x the moved primitive's exponent
         for (int kp = 0; kp < nkp; ++kp) {
           const double q = a.K.exps[kpo + kp], cc = a.K.coef[kpo + kp];
           const double pq = pp_ + q, ipq = 1.0 / pq;
-          const double PC0 = P0 - C0, PC1 = P1 - C1, PC2 = P2 - C2;
+          const double PC0 = PA0 + (A0 - C0), PC1 = PA1 + (A1 - C1), PC2 = PA2 + (A2 - C2);
           const double rho = pp_ * q * ipq;
           const double T = rho * (PC0 * PC0 + PC1 * PC1 + PC2 * PC2);
           const double pref = TWO_PI_52 / (pp_ * q * sqrt(pq)) * Kab * ca * cb * cc;

@@ -166,9 +166,10 @@ __global__ void __launch_bounds__(64) onee_grad_kernel(OneEGradArgs g) {
         const double pp_ = al + be;
         const double cf = g.sh.coef[g.sh.poff[s1] + i1] * g.sh.coef[g.sh.poff[s2] + j1] *
                           exp(-al * be / pp_ * rab2) * 2.0 * M_PI / pp_;
-        const double P[3] = {(al * A[0] + be * B[0]) / pp_, (al * A[1] + be * B[1]) / pp_,
-                             (al * A[2] + be * B[2]) / pp_};
-        const double PC[3] = {P[0] - g.xyz[3 * c], P[1] - g.xyz[3 * c + 1], P[2] - g.xyz[3 * c + 2]};
+        // P - A = b (B - A) / p, P - C = (P - A) + (A - C): exact for concentric centres
+        const double PA[3] = {-be / pp_ * AB[0], -be / pp_ * AB[1], -be / pp_ * AB[2]};
+        const double PC[3] = {PA[0] + (A[0] - g.xyz[3 * c]), PA[1] + (A[1] - g.xyz[3 * c + 1]),
+                              PA[2] + (A[2] - g.xyz[3 * c + 2])};
         const double Tb = pp_ * (PC[0] * PC[0] + PC[1] * PC[1] + PC[2] * PC[2]);
         const double z = -g.Z[c] * cf;
         const RysPoint<NR> rp(tab, Tb);
@@ -182,7 +183,7 @@ __global__ void __launch_bounds__(64) onee_grad_kernel(OneEGradArgs g) {
           double H[3][LA + 2][LB + 2];
 #pragma unroll
           for (int x = 0; x < 3; ++x) {
-            const double C00 = (P[x] - A[x]) - u * PC[x];
+            const double C00 = PA[x] - u * PC[x];
             double G[E + 1];
             G[0] = (x == 2) ? w * z : 1.0;
 #pragma unroll
