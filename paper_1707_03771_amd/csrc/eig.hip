@@ -11,9 +11,12 @@
 //   1. ej_pair_kernel: per pair (a, b), one workgroup loads the 64 x 64
 //      principal submatrix of blocks a and b into LDS and runs one cyclic
 //      Jacobi sweep over it (63 rounds of 32 disjoint rotations, each
-//      rotation zeroing its element exactly), accumulating the orthogonal
-//      U with U^T S U the reduced submatrix.  S goes back in place, U to a
-//      buffer.
+//      rotation zeroing its element exactly; a round updates S by 2 x 2
+//      blocks, one thread per block, so rows and columns need no barrier in
+//      between), accumulating the orthogonal U with U^T S U the reduced
+//      submatrix.  S goes back in place, U to a buffer.  One local sweep per
+//      visit converges in as many outer sweeps as solving the pair problem
+//      to the end (measured in a CPU model of the scheme).
 //   2. ej_apply_kernel: the off-diagonal 64 x 64 blocks between pairs,
 //      A_IJ <- U_I^T A_IJ U_J (one workgroup per block I > J, writing both
 //      A_IJ and A_JI), and the eigenvector columns V_:I <- V_:I U_I.
@@ -67,10 +70,12 @@ __global__ void ej_init_kernel(const double* __restrict__ A, int n, int N, doubl
 }
 
 __global__ void __launch_bounds__(EJT) ej_pair_kernel(double* __restrict__ A, int N, const int2* __restrict__ pr,
-                                                      double* __restrict__ Ub, int* __restrict__ nrot) {
+                                                      double* __restrict__ Ub, int* __restrict__ nrot,
+                                                      int* __restrict__ moved) {
   __shared__ double S[EJP][EJP + 1];
-  __shared__ double Ut[EJP][EJP];  // Ut[r][k] = U[k][r]: its rows rotate like those of S
-  __shared__ double cs_c[EJP / 2], cs_s[EJP / 2];
+  __shared__ double Ut[EJP][EJP + 1];  // Ut[r][k] = U[k][r]: its rows rotate like those of S
+  __shared__ double cs_c[EJP / 2], cs_s[EJP / 2], d_p[EJP / 2], d_q[EJP / 2];
+  __shared__ unsigned char lp[EJP - 1][EJP / 2], lq[EJP - 1][EJP / 2];  // the local pairs of every round
   __shared__ int any;
   const int2 ab = pr[blockIdx.x];
   const int t = threadIdx.x;
@@ -79,69 +84,108 @@ __global__ void __launch_bounds__(EJT) ej_pair_kernel(double* __restrict__ A, in
     S[i][j] = A[(int64_t)ej_g(i, ab) * N + ej_g(j, ab)];
     Ut[i][j] = i == j ? 1.0 : 0.0;
   }
+  for (int e = t; e < (EJP - 1) * (EJP / 2); e += EJT) {
+    int p, q;
+    ej_local_pair(e / (EJP / 2), e % (EJP / 2), p, q);
+    lp[e / (EJP / 2)][e % (EJP / 2)] = (unsigned char)p;
+    lq[e / (EJP / 2)][e % (EJP / 2)] = (unsigned char)q;
+  }
   if (t == 0) any = 0;
   __syncthreads();
   for (int r = 0; r < EJP - 1; ++r) {
-    // the rotation of local pair t (threads 0..31 keep its values for the diagonal update)
-    int p = 0, q = 0;
-    double tt = 0.0, app = 0.0, aqq = 0.0, apq = 0.0;
-    bool rot = false;
+    // the rotation of local pair t, and its rotated diagonal
     if (t < EJP / 2) {
-      ej_local_pair(r, t, p, q);
-      apq = S[p][q];
-      app = S[p][p];
-      aqq = S[q][q];
-      double c = 1.0, s = 0.0;
+      const int p = lp[r][t], q = lq[r][t];
+      const double apq = S[p][q], app = S[p][p], aqq = S[q][q];
+      double c = 1.0, s = 0.0, dp = app, dq = aqq;
       if (apq != 0.0 && fabs(apq) > EJ_TOL * sqrt(fabs(app * aqq))) {
         const double th = (aqq - app) / (2.0 * apq);
-        tt = 1.0 / (fabs(th) + sqrt(1.0 + th * th));
+        double tt = 1.0 / (fabs(th) + sqrt(1.0 + th * th));
         if (th < 0.0) tt = -tt;
         c = 1.0 / sqrt(1.0 + tt * tt);
         s = tt * c;
-        rot = true;
+        dp = app - tt * apq;
+        dq = aqq + tt * apq;
         any = 1;  // every writer stores the same value
       }
       cs_c[t] = c;
       cs_s[t] = s;
+      d_p[t] = dp;
+      d_q[t] = dq;
     }
     __syncthreads();
-    // rows p, q of S and of U^T: row_p <- c row_p - s row_q, row_q <- s row_p + c row_q
-    for (int e = t; e < (EJP / 2) * EJP; e += EJT) {
-      const int k = e / EJP, j = e % EJP;
-      const double s = cs_s[k];
-      if (s != 0.0) {
-        int pp, qq;
-        ej_local_pair(r, k, pp, qq);
-        const double c = cs_c[k];
-        const double x = S[pp][j], y = S[qq][j];
-        S[pp][j] = c * x - s * y;
-        S[qq][j] = s * x + c * y;
-        const double u = Ut[pp][j], v = Ut[qq][j];
-        Ut[pp][j] = c * u - s * v;
-        Ut[qq][j] = s * u + c * v;
+    // S <- J^T S J as 2 x 2 blocks (rows p_k, q_k) x (columns p_k2, q_k2): every
+    // element is read and written by one thread, so rows and columns need no
+    // barrier between them; the diagonal blocks take the exact rotated values.
+    // Thread t takes the column pair k2 = t % 32 and the row pairs t / 32 + 8 m,
+    // and issues all its loads before its stores.
+    {
+      const int k2 = t % (EJP / 2);
+      const double c2 = cs_c[k2], s2 = cs_s[k2];
+      const int p2 = lp[r][k2], q2 = lq[r][k2];
+      int pk[4], qk[4];
+      double ck[4], sk[4], x[4][4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int k = t / (EJP / 2) + 8 * m;
+        pk[m] = lp[r][k];
+        qk[m] = lq[r][k];
+        ck[m] = cs_c[k];
+        sk[m] = cs_s[k];
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        x[m][0] = S[pk[m]][p2];
+        x[m][1] = S[pk[m]][q2];
+        x[m][2] = S[qk[m]][p2];
+        x[m][3] = S[qk[m]][q2];
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int k = t / (EJP / 2) + 8 * m;
+        const int p = pk[m], q = qk[m];
+        if (k == k2) {
+          if (s2 != 0.0) {
+            S[p][p] = d_p[k];
+            S[q][q] = d_q[k];
+            S[p][q] = 0.0;
+            S[q][p] = 0.0;
+          }
+          continue;
+        }
+        const double c1 = ck[m], s1 = sk[m];
+        if (s1 == 0.0 && s2 == 0.0) continue;
+        // rows: J_k^T x, then columns: y J_k2
+        const double ypp = c1 * x[m][0] - s1 * x[m][2], ypq = c1 * x[m][1] - s1 * x[m][3];
+        const double yqp = s1 * x[m][0] + c1 * x[m][2], yqq = s1 * x[m][1] + c1 * x[m][3];
+        S[p][p2] = c2 * ypp - s2 * ypq;
+        S[p][q2] = s2 * ypp + c2 * ypq;
+        S[q][p2] = c2 * yqp - s2 * yqq;
+        S[q][q2] = s2 * yqp + c2 * yqq;
       }
     }
-    __syncthreads();
-    // columns p, q of S
-    for (int e = t; e < (EJP / 2) * EJP; e += EJT) {
-      const int k = e / EJP, i = e % EJP;
-      const double s = cs_s[k];
-      if (s != 0.0) {
-        int pp, qq;
-        ej_local_pair(r, k, pp, qq);
-        const double c = cs_c[k];
-        const double x = S[i][pp], y = S[i][qq];
-        S[i][pp] = c * x - s * y;
-        S[i][qq] = s * x + c * y;
+    // rows p, q of U^T: thread t takes column j = t % 64 of the pairs t / 64 + 4 m
+    {
+      const int j = t % EJP;
+      int pk[8], qk[8];
+      double u[8], v[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int k = t / EJP + 4 * m;
+        pk[m] = lp[r][k];
+        qk[m] = lq[r][k];
+        u[m] = Ut[pk[m]][j];
+        v[m] = Ut[qk[m]][j];
       }
-    }
-    __syncthreads();
-    // the rotated 2 x 2 block exactly
-    if (rot) {
-      S[p][q] = 0.0;
-      S[q][p] = 0.0;
-      S[p][p] = app - tt * apq;
-      S[q][q] = aqq + tt * apq;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int k = t / EJP + 4 * m;
+        const double s = cs_s[k];
+        if (s == 0.0) continue;
+        const double c = cs_c[k];
+        Ut[pk[m]][j] = c * u[m] - s * v[m];
+        Ut[qk[m]][j] = s * u[m] + c * v[m];
+      }
     }
     __syncthreads();
   }
@@ -150,14 +194,18 @@ __global__ void __launch_bounds__(EJT) ej_pair_kernel(double* __restrict__ A, in
     A[(int64_t)ej_g(i, ab) * N + ej_g(j, ab)] = S[i][j];
     Ub[(int64_t)blockIdx.x * EJP * EJP + e] = Ut[j][i];  // U[i][j]
   }
-  if (t == 0 && any) atomicAdd(nrot, 1);
+  if (t == 0) {
+    moved[blockIdx.x] = any;  // 0: U is exactly the identity
+    if (any) atomicAdd(nrot, 1);
+  }
 }
 
 // blockIdx.x < ntri: off-diagonal block (I, J), I > J, of the pairs, A_IJ <- U_I^T A_IJ U_J
 // (and A_JI its transpose); else the eigenvector columns of pair I over 64 rows of V.
+// Pairs whose U is exactly the identity (moved[I] == 0) leave their blocks as they are.
 __global__ void __launch_bounds__(EJT) ej_apply_kernel(double* __restrict__ A, double* __restrict__ V, int N,
                                                        const int2* __restrict__ pr, const double* __restrict__ Ub,
-                                                       int np, int ntri) {
+                                                       const int* __restrict__ moved, int np, int ntri) {
   __shared__ double X[EJP][EJP + 1];
   __shared__ double U[EJP][EJP + 1];
   const int t = threadIdx.x;
@@ -169,6 +217,7 @@ __global__ void __launch_bounds__(EJT) ej_apply_kernel(double* __restrict__ A, d
     while (I * (I - 1) / 2 > b) --I;
     while ((I + 1) * I / 2 <= b) ++I;
     const int J = b - I * (I - 1) / 2;
+    if (!moved[I] && !moved[J]) return;
     const int2 pI = pr[I], pJ = pr[J];
     for (int e = t; e < EJP * EJP; e += EJT) {
       const int i = e / EJP, j = e % EJP;
@@ -229,6 +278,7 @@ __global__ void __launch_bounds__(EJT) ej_apply_kernel(double* __restrict__ A, d
   // eigenvectors: rows [64 s, 64 s + 64) of V, columns of pair I: V_:I <- V_:I U_I
   const int b = blockIdx.x - ntri;
   const int I = b % np, strip = b / np;
+  if (!moved[I]) return;
   const int2 pI = pr[I];
   for (int e = t; e < EJP * EJP; e += EJT) {
     const int i = e / EJP, k = e % EJP;
@@ -291,7 +341,8 @@ size_t sym_eig_work_bytes(int n) {
   const EjDims d = ej_dims(std::max(n, 1));
   auto a = [](size_t x) { return (x + 255) / 256 * 256; };
   return 2 * a(8 * (size_t)d.N * d.N) + a(8 * (size_t)d.np * EJP * EJP) +
-         a(sizeof(int) * 2 * (size_t)(d.nb - 1) * d.np) + a(8 * (size_t)d.N) + a(sizeof(int) * (size_t)d.N) + 256;
+         a(sizeof(int) * 2 * (size_t)(d.nb - 1) * d.np) + a(8 * (size_t)d.N) + a(sizeof(int) * (size_t)d.N) +
+         a(sizeof(int) * (size_t)d.np) + 512;
 }
 
 int sym_eig(double* A, int n, double* w, hipStream_t st) {
@@ -314,7 +365,8 @@ int sym_eig(double* A, int n, double* w, hipStream_t st) {
       prh[2 * ((size_t)r * np + k)] = std::min(a, b);
       prh[2 * ((size_t)r * np + k) + 1] = std::max(a, b);
     }
-  DevMem prd = upload(prh, st), cnt(sizeof(int)), dg(8 * (size_t)N), idxd(sizeof(int) * (size_t)N);
+  DevMem prd = upload(prh, st), cnt(sizeof(int)), dg(8 * (size_t)N), idxd(sizeof(int) * (size_t)N),
+      mv(sizeof(int) * (size_t)np);
   const int64_t NN = (int64_t)N * N;
   hipLaunchKernelGGL(ej_init_kernel, dim3((unsigned)((NN + 255) / 256)), dim3(256), 0, st, A, n, N,
                      Aw.as<double>(), V.as<double>());
@@ -326,9 +378,9 @@ int sym_eig(double* A, int n, double* w, hipStream_t st) {
     for (int r = 0; r < nb - 1; ++r) {
       const int2* pr = reinterpret_cast<const int2*>(prd.as<int>() + 2 * (size_t)r * np);
       hipLaunchKernelGGL(ej_pair_kernel, dim3(np), dim3(EJT), 0, st, Aw.as<double>(), N, pr, Ub.as<double>(),
-                         cnt.as<int>());
+                         cnt.as<int>(), mv.as<int>());
       hipLaunchKernelGGL(ej_apply_kernel, dim3(ntri + nstrip * np), dim3(EJT), 0, st, Aw.as<double>(),
-                         V.as<double>(), N, pr, Ub.as<double>(), np, ntri);
+                         V.as<double>(), N, pr, Ub.as<double>(), mv.as<int>(), np, ntri);
     }
     ++sweeps;
     int h = 0;

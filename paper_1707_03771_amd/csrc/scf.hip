@@ -301,6 +301,46 @@ DevCtx& thread_ctx() {
   return c;
 }
 
+// Newton-Schulz square roots: Y = S / c, Z = I
+__global__ void ns_init_kernel(const double* __restrict__ Sm, int n, double inv_c, double* __restrict__ Y,
+                               double* __restrict__ Z) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  Y[e] = Sm[e] * inv_c;
+  Z[e] = (e / n == e % n) ? 1.0 : 0.0;
+}
+
+// T = (3 I - P) / 2 with P = Z Y; P <- P - I, whose largest element is the residual
+__global__ void ns_t_kernel(double* __restrict__ P, int n, double* __restrict__ T) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (int64_t)n * n) return;
+  const double d = (e / n == e % n) ? 1.0 : 0.0;
+  const double p = P[e];
+  T[e] = 1.5 * d - 0.5 * p;
+  P[e] = p - d;
+}
+
+__global__ void scale_kernel(double* __restrict__ A, int64_t cnt, double a) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < cnt) A[e] *= a;
+}
+
+// y = A x (n x n), one workgroup per row, fixed-order reduction
+__global__ void matvec_kernel(const double* __restrict__ A, int n, const double* __restrict__ x,
+                              double* __restrict__ y) {
+  __shared__ double red[256];
+  const int i = blockIdx.x;
+  double s = 0.0;
+  for (int j = threadIdx.x; j < n; j += 256) s = fma(A[(int64_t)i * n + j], x[j], s);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) y[i] = red[0];
+}
+
 // ---- driver ---------------------------------------------------------------------------
 struct Scf {
   hipStream_t st{};
@@ -341,6 +381,69 @@ struct Scf {
     g.alpha = alpha; g.beta = beta; g.batch = 1;
     dgemm_sk(g, gw.p ? gw.as<double>() : nullptr, (int64_t)(gw.n / sizeof(double)), st);
   }
+  // S^-1/2 and S^1/2 of the symmetric positive definite n x n matrix Sm by the
+  // coupled Newton-Schulz iteration (N. J. Higham, "Functions of Matrices",
+  // SIAM 2008, sec. 6.7): with c >= lambda_max(S) (the largest Gershgorin
+  // bound), Y0 = S / c, Z0 = I, T = (3 I - Z Y) / 2, Y <- Y T, Z <- T Z; then
+  // Y -> (S / c)^1/2 and Z -> (S / c)^-1/2 for any spectrum in (0, c].  Once
+  // max |I - Z Y| < 1e-8 one more step reaches the rounding level.  buf: four
+  // n x n buffers; on return isq = S^-1/2 and sq = S^1/2 point into them, and
+  // lmin estimates lambda_min(S) as 1 / |S^-1/2|_2^2 from 40 power steps
+  // (an upper estimate: the power iteration approaches the norm from below).
+  // Returns false if S is not numerically positive definite (no convergence
+  // in 100 steps, or a non-finite residual).  Synchronous.
+  bool inv_sqrt(const double* Sm, int nn, double* const buf[4], double*& isq, double*& sq, double& lmin,
+                int& steps) {
+    const int64_t n2 = (int64_t)nn * nn;
+    DevMem lh(16 * (size_t)nn), vw(16 * (size_t)nn + 16);
+    double b[2];
+    hipLaunchKernelGGL(gersh_kernel, dim3(nn), dim3(256), 0, st, Sm, nn, lh.as<double>(), lh.as<double>() + nn);
+    hipLaunchKernelGGL(minmax_kernel, dim3(1), dim3(256), 0, st, lh.as<double>(), lh.as<double>() + nn, nn,
+                       part.as<double>());
+    DFX_HIP(hipMemcpyAsync(b, part.p, sizeof b, hipMemcpyDeviceToHost, st));
+    DFX_HIP(hipStreamSynchronize(st));
+    const double c = b[1];
+    if (!(c > 0.0) || !std::isfinite(c)) return false;
+    double *Y = buf[0], *Z = buf[1], *T = buf[2], *P = buf[3];
+    hipLaunchKernelGGL(ns_init_kernel, dim3(nblk(n2)), dim3(256), 0, st, Sm, nn, 1.0 / c, Y, Z);
+    bool last = false, ok = false;
+    for (steps = 0; steps < 100; ++steps) {
+      gemm(nn, nn, nn, Z, nn, false, Y, nn, false, P, nn);  // Z Y
+      hipLaunchKernelGGL(ns_t_kernel, dim3(nblk(n2)), dim3(256), 0, st, P, nn, T);
+      const double r = reduce_max(P, n2);
+      if (!std::isfinite(r)) return false;
+      if (last) {
+        ok = r < 1e-10;
+        break;
+      }
+      gemm(nn, nn, nn, Y, nn, false, T, nn, false, P, nn);  // Y T
+      std::swap(Y, P);
+      gemm(nn, nn, nn, T, nn, false, Z, nn, false, P, nn);  // T Z
+      std::swap(Z, P);
+      if (r < 1e-8) last = true;
+    }
+    if (!ok) return false;
+    hipLaunchKernelGGL(scale_kernel, dim3(nblk(n2)), dim3(256), 0, st, Z, n2, 1.0 / std::sqrt(c));
+    hipLaunchKernelGGL(scale_kernel, dim3(nblk(n2)), dim3(256), 0, st, Y, n2, std::sqrt(c));
+    isq = Z;
+    sq = Y;
+    // |S^-1/2|_2 by power steps from a seeded start
+    double* v = vw.as<double>();
+    double* w = v + nn;
+    hipLaunchKernelGGL(rand_fill_kernel, dim3(nblk(nn)), dim3(256), 0, st, v, (int64_t)nn, (uint64_t)0x2545F4914F6CDD1Dull);
+    double nrm = 0.0;
+    for (int k = 0; k < 40; ++k) {
+      const double vv = reduce_sum(v, v, nullptr, nn);
+      if (!(vv > 0.0)) return false;
+      hipLaunchKernelGGL(scale_kernel, dim3(nblk(nn)), dim3(256), 0, st, v, (int64_t)nn, 1.0 / std::sqrt(vv));
+      hipLaunchKernelGGL(matvec_kernel, dim3(nn), dim3(256), 0, st, Z, nn, v, w);
+      nrm = std::sqrt(reduce_sum(w, w, nullptr, nn));
+      std::swap(v, w);
+    }
+    lmin = 1.0 / (nrm * nrm);
+    return true;
+  }
+
   // Occupied space of the symmetric m x m matrix F (the nocc lowest levels) by
   // trace-correcting purification: P0 = (e_max I - F) / (e_max - e_min) with
   // Gershgorin bounds, then P <- P^2 or 2P - P^2, whichever moves tr P toward
@@ -420,6 +523,66 @@ struct Scf {
     if (eig_spans) eig_spans->end();
   }
 };
+
+// The orthogonaliser X (n x m, X^T S X = I) of the SCF's orthonormal basis.
+// Loewdin's X = S^-1/2 (m = n) by Newton-Schulz when the smallest eigenvalue of
+// S is at least 100 ortho_thresh: no function would be dropped, and the span is
+// that of every other choice.  Otherwise canonical orthogonalisation, X = U
+// s^-1/2 over the eigenvalues above ortho_thresh (the block Jacobi
+// eigensolver); with want_u, U gets those eigenvectors (n x m).
+struct Ortho {
+  DevMem X, U;
+  int m = 0;
+  bool lowdin = false;
+  double lmin = 0.0;
+  int ns_steps = 0;
+};
+
+static Ortho make_orthogonalizer(Scf& S, const double* Sm, int n, double thresh, bool want_u) {
+  Ortho r;
+  hipStream_t st = S.st;
+  const int64_t n2 = (int64_t)n * n;
+  {
+    DevMem b4[4];
+    double* buf[4];
+    for (int k = 0; k < 4; ++k) {
+      b4[k].alloc(8 * (size_t)n2);
+      buf[k] = b4[k].as<double>();
+    }
+    double *isq = nullptr, *sq = nullptr;
+    if (S.inv_sqrt(Sm, n, buf, isq, sq, r.lmin, r.ns_steps) && r.lmin >= 100.0 * thresh) {
+      for (int k = 0; k < 4; ++k)
+        if (buf[k] == isq) r.X = std::move(b4[k]);
+      r.m = n;
+      r.lowdin = true;
+      if (S.verbose)
+        std::fprintf(stderr, "dfx_scf: Loewdin orthogonaliser, %d Newton-Schulz steps, lambda_min(S) ~ %.3e\n",
+                     r.ns_steps, r.lmin);
+      return r;
+    }
+  }
+  DevMem W(8 * n2), sv(8 * (size_t)n);
+  DFX_HIP(hipMemcpyAsync(W.p, Sm, 8 * n2, hipMemcpyDeviceToDevice, st));
+  S.syevd(W.as<double>(), n, sv.as<double>());
+  std::vector<double> s_h(n);
+  DFX_HIP(hipMemcpyAsync(s_h.data(), sv.p, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
+  DFX_HIP(hipStreamSynchronize(st));
+  int ndrop = 0;
+  while (ndrop < n && s_h[ndrop] < thresh) ++ndrop;
+  r.m = n - ndrop;
+  r.lmin = s_h.empty() ? 0.0 : s_h[0];
+  if (r.m <= 0) return r;
+  r.X.alloc(8 * (size_t)n * r.m);
+  hipLaunchKernelGGL(build_x_kernel, dim3(nblk((int64_t)n * r.m)), dim3(256), 0, st, W.as<double>(),
+                     sv.as<double>(), n, ndrop, r.m, r.X.as<double>());
+  if (want_u) {
+    r.U.alloc(8 * (size_t)n * r.m);
+    hipLaunchKernelGGL(build_u_kernel, dim3(nblk((int64_t)n * r.m)), dim3(256), 0, st, W.as<double>(), n, ndrop,
+                       r.m, r.U.as<double>());
+  }
+  if (S.verbose) std::fprintf(stderr, "dfx_scf: canonical orthogonaliser, %d of %d functions kept\n", r.m, n);
+  return r;
+}
 
 // C_sel[mu][j] = W[idx[j]][mu] * scale[j]  (rows of W are eigenvectors)
 __global__ void gather_evec_kernel(const double* __restrict__ W, int n, const int* __restrict__ idx,
@@ -637,27 +800,12 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
                                    (A[2] - Bx[2]) * (A[2] - Bx[2]));
         Enuc += (double)geom->Z[a] * geom->Z[b] / r;
       }
-    DevMem W(8 * n2), sv(8 * (size_t)n);
-    DFX_HIP(hipMemcpyAsync(W.p, Sm.p, 8 * n2, hipMemcpyDeviceToDevice, st));
-    S.syevd(W.as<double>(), n, sv.as<double>());
-    std::vector<double> s_h(n);
-    DFX_HIP(hipMemcpyAsync(s_h.data(), sv.p, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
-    DFX_HIP(hipStreamSynchronize(st));
-    int ndrop = 0;
-    while (ndrop < n && s_h[ndrop] < o.ortho_thresh) ++ndrop;
-    const int m = n - ndrop;
+    Ortho orth = make_orthogonalizer(S, Sm.as<double>(), n, o.ortho_thresh, o.guess == DFX_GUESS_LEARNED);
+    const int m = orth.m;
     if (m < nocc) throw Error(DFX_EINVAL, "dfx_scf: basis too linearly dependent");
     S.m = m;
-    DevMem X(8 * (size_t)n * m);
-    hipLaunchKernelGGL(build_x_kernel, dim3(nblk((int64_t)n * m)), dim3(256), 0, st, W.as<double>(),
-                       sv.as<double>(), n, ndrop, m, X.as<double>());
-    DevMem Uk;
-    if (o.guess == DFX_GUESS_LEARNED) {
-      Uk.alloc(8 * (size_t)n * m);
-      hipLaunchKernelGGL(build_u_kernel, dim3(nblk((int64_t)n * m)), dim3(256), 0, st, W.as<double>(), n, ndrop,
-                         m, Uk.as<double>());
-    }
-    W.release();
+    DevMem X = std::move(orth.X), Uk = std::move(orth.U);
+    const bool lowdin = orth.lowdin;
 
     DevMem F(8 * n2), D(8 * n2), Jm(8 * n2), Km(8 * n2), t1(8 * n2), t2(8 * n2);
     DevMem Fp(8 * (size_t)m * m), eps(8 * (size_t)m), Cm(8 * (size_t)n * m), Cocc(8 * (size_t)n * nocc);
@@ -739,6 +887,9 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
         S.gemm(n, n, n, t1.as<double>(), n, false, Sm.as<double>(), n, false, t2.as<double>(), n);   // S D S
         S.gemm(m, n, n, X.as<double>(), m, true, t2.as<double>(), n, false, t1.as<double>(), n);     // X^T SDS
         S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Fp.as<double>(), m);
+      } else if (lowdin) {
+        // Loewdin density P = S^1/2 D S^1/2: with X = S^-1/2, X^T S D S X = P itself
+        DFX_HIP(hipMemcpyAsync(Fp.p, Di.p, 8 * n2, hipMemcpyDeviceToDevice, st));
       } else {
         // Loewdin density P = S^1/2 D S^1/2: X^T S D S X = U^T P U with X^T S^1/2 = U^T
         S.gemm(m, n, n, Uk.as<double>(), m, true, Di.as<double>(), n, false, t1.as<double>(), n);    // U^T P
@@ -1036,7 +1187,7 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     inf.purify_steps = purify_steps;
     inf.converged = converged ? 1 : 0;
     inf.n_mixed = n_mixed;
-    inf.ndropped = ndrop;
+    inf.ndropped = n - m;
     inf.nbf = n;
     inf.naux = B->naux;
     inf.nocc = nocc;
@@ -1143,21 +1294,11 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
                                    (A[2] - Bx[2]) * (A[2] - Bx[2]));
         Enuc += (double)geom->Z[a] * geom->Z[b] / r;
       }
-    DevMem W(8 * n2), sv(8 * (size_t)n);
-    DFX_HIP(hipMemcpyAsync(W.p, Sm.p, 8 * n2, hipMemcpyDeviceToDevice, st));
-    S.syevd(W.as<double>(), n, sv.as<double>());
-    std::vector<double> s_h(n);
-    DFX_HIP(hipMemcpyAsync(s_h.data(), sv.p, 8 * (size_t)n, hipMemcpyDeviceToHost, st));
-    DFX_HIP(hipStreamSynchronize(st));
-    int ndrop = 0;
-    while (ndrop < n && s_h[ndrop] < o.ortho_thresh) ++ndrop;
-    const int m = n - ndrop;
+    Ortho orth = make_orthogonalizer(S, Sm.as<double>(), n, o.ortho_thresh, false);
+    const int m = orth.m;
     if (m < na) throw Error(DFX_EINVAL, fn + ": basis too linearly dependent");
     S.m = m;
-    DevMem X(8 * (size_t)n * m);
-    hipLaunchKernelGGL(build_x_kernel, dim3(nblk((int64_t)n * m)), dim3(256), 0, st, W.as<double>(),
-                       sv.as<double>(), n, ndrop, m, X.as<double>());
-    W.release();
+    DevMem X = std::move(orth.X);
 
     // per spin: occupied orbitals, density, K, Fock matrix, DIIS error
     const int nocc_s[2] = {na, nb};
@@ -1389,7 +1530,7 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
     }
     inf.niter = std::min(it, o.max_iter);
     inf.converged = converged ? 1 : 0;
-    inf.ndropped = ndrop;
+    inf.ndropped = n - m;
     inf.nbf = n;
     inf.naux = B->naux;
     inf.nocc = na;
@@ -1434,12 +1575,31 @@ int dfx_lowdin(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dou
     Scf S;
     S.st = (hipStream_t)stream;
     hipStream_t st = S.st;
+    S.part.alloc(sizeof(double) * 512);
     DevMem W(8 * n2), Tm(8 * n2), Vm(8 * n2), sv(8 * (size_t)n);
     int1e_build(hb, geom, W.as<double>(), Tm.as<double>(), Vm.as<double>(), st);
-    S.syevd(W.as<double>(), n, sv.as<double>());                         // rows of W: eigenvectors
-    hipLaunchKernelGGL(scale_rows_sqrt_kernel, dim3(nblk(n2)), dim3(256), 0, st, W.as<double>(), sv.as<double>(), n,
-                       Tm.as<double>());
-    S.gemm(n, n, n, W.as<double>(), n, true, Tm.as<double>(), n, false, Vm.as<double>(), n);  // S^1/2
+    // S^1/2 by Newton-Schulz; by the eigen-decomposition where S is too close to singular for it
+    bool done = false;
+    {
+      DevMem b4[4];
+      double* buf[4];
+      for (int k = 0; k < 4; ++k) {
+        b4[k].alloc(8 * (size_t)n2);
+        buf[k] = b4[k].as<double>();
+      }
+      double *isq = nullptr, *sq = nullptr, lmin = 0.0;
+      int steps = 0;
+      if (S.inv_sqrt(W.as<double>(), n, buf, isq, sq, lmin, steps)) {
+        DFX_HIP(hipMemcpyAsync(Vm.p, sq, 8 * n2, hipMemcpyDeviceToDevice, st));
+        done = true;
+      }
+    }
+    if (!done) {
+      S.syevd(W.as<double>(), n, sv.as<double>());  // rows of W: eigenvectors
+      hipLaunchKernelGGL(scale_rows_sqrt_kernel, dim3(nblk(n2)), dim3(256), 0, st, W.as<double>(),
+                         sv.as<double>(), n, Tm.as<double>());
+      S.gemm(n, n, n, W.as<double>(), n, true, Tm.as<double>(), n, false, Vm.as<double>(), n);  // S^1/2
+    }
     DFX_HIP(hipMemcpyAsync(W.p, D, 8 * n2, hipMemcpyHostToDevice, st));
     S.gemm(n, n, n, Vm.as<double>(), n, false, W.as<double>(), n, false, Tm.as<double>(), n);  // S^1/2 D
     S.gemm(n, n, n, Tm.as<double>(), n, false, Vm.as<double>(), n, false, W.as<double>(), n);  // ... S^1/2

@@ -157,3 +157,29 @@ def test_run_log_records_every_call(dfx, h4_ref, tmp_path):
     assert lines[0]["E_hist"] == info["E_hist"] and len(lines[0]["err_hist"]) == info["niter"]
     assert lines[0]["natom"] == len(Z) and lines[0]["nbf"] == info["nbf"]
     assert lines[1]["n_mixed"] >= 1 and set(lines[1]["prec_hist"]) <= {0, 1, 2}
+
+
+def test_orthogonaliser_paths(dfx, h4_ref):
+    """The orthonormal basis: Loewdin's S^-1/2 by Newton-Schulz when no function
+    is near the drop threshold (the default runs above), canonical
+    orthogonalisation on the block Jacobi eigen-decomposition otherwise.  With
+    a threshold between the second and third eigenvalues of S two functions
+    are dropped, as in the oracle with the same threshold; with one just below
+    the smallest eigenvalue none is, and the energy is the default one."""
+    xyz, Z, sh, ax, nocc, ref = h4_ref
+    s = np.linalg.eigvalsh(O.int1e(O.Basis(sh), xyz, Z)[0])
+    conv = dict(conv_dE=1e-11, conv_err=1e-9)
+    E0, _, _, i0 = dfx.scf(xyz, Z, sh, ax, **conv)
+    assert i0["ndropped"] == 0
+    th = float(np.sqrt(s[1] * s[2]))
+    ref2, _ = O.df_rhf(Z, xyz, sh, ax, nocc, ortho_thresh=th, conv_dE=1e-11, conv_err=1e-9)
+    assert ref2.converged and ref2.ndropped == 2
+    E2, _, eps2, i2 = dfx.scf(xyz, Z, sh, ax, ortho_thresh=th, **conv)
+    assert i2["ndropped"] == 2
+    assert abs(E2 - ref2.E) <= 1e-8, (E2, ref2.E)
+    assert np.allclose(eps2[:nocc], ref2.eps[:nocc], atol=1e-6)
+    E3, _, _, i3 = dfx.scf(xyz, Z, sh, ax, ortho_thresh=0.5 * float(s[0]), **conv)
+    assert i3["ndropped"] == 0
+    print(f"orthogonalisers: default {E0:.12f}, canonical without drops {E3:.12f}, "
+          f"two dropped {E2:.12f} (oracle {ref2.E:.12f})")
+    assert abs(E3 - E0) <= 1e-10
