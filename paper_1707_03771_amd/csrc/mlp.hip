@@ -9,50 +9,64 @@
 
 namespace dfx {
 
-// ---- tiled SGEMM: C = op(A) op(B) (+ C), row-major, 64x64 tiles, 4x4 per thread
+// ---- tiled SGEMM on FP32 matrix cores: C = op(A) op(B) (+ C), row-major.
+// A workgroup owns a 64 x 64 tile of C; its four waves own 32 x 32 quarters,
+// each as 2 x 2 tiles of v_mfma_f32_16x16x4f32 (FP32 products, FP32 sums).
+// K goes through LDS in slices of 16.  MFMA operands: lane (li, lk) = (lane %
+// 16, lane / 16) gives A[row li][k lk] and B[k lk][col li]; the result's
+// element r of that lane is C[row 4 lk + r][col li].
 constexpr int SG = 64, SK = 16;
+typedef float v4f __attribute__((ext_vector_type(4)));
 template <bool TA, bool TB>
 __global__ void __launch_bounds__(256) sgemm_kernel(int M, int N, int K, const float* __restrict__ A, int lda,
                                                    const float* __restrict__ B, int ldb, float* __restrict__ C,
                                                    int ldc, int accumulate) {
-  __shared__ float As[SK][SG + 1];
-  __shared__ float Bs[SK][SG + 1];
+  __shared__ float As[SG][SK + 1];  // As[m][k]
+  __shared__ float Bs[SK][SG + 1];  // Bs[k][n]
   const int m0 = blockIdx.y * SG, n0 = blockIdx.x * SG;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  float acc[4][4] = {};
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+  v4f acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < K; k0 += SK) {
     for (int e = threadIdx.x; e < SG * SK; e += 256) {
       const int mm = e / SK, kk = e % SK;
       const int m = m0 + mm, k = k0 + kk;
-      As[kk][mm] = (m < M && k < K) ? (TA ? A[(int64_t)k * lda + m] : A[(int64_t)m * lda + k]) : 0.0f;
+      As[mm][kk] = (m < M && k < K) ? (TA ? A[(int64_t)k * lda + m] : A[(int64_t)m * lda + k]) : 0.0f;
       const int nn = e / SK, n = n0 + nn;
       Bs[kk][nn] = (n < N && k < K) ? (TB ? B[(int64_t)n * ldb + k] : B[(int64_t)k * ldb + n]) : 0.0f;
     }
     __syncthreads();
 #pragma unroll
-    for (int kk = 0; kk < SK; ++kk) {
-      float a[4], b[4];
+    for (int kk = 0; kk < SK; kk += 4) {
+      float fa[2], fb[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+      for (int a = 0; a < 2; ++a) fa[a] = As[wm + a * 16 + li][kk + lk];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
+      for (int b = 0; b < 2; ++b) fb[b] = Bs[kk + lk][wn + b * 16 + li];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int a = 0; a < 2; ++a)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], acc[a][b], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int m = m0 + ty * 4 + i, n = n0 + tx * 4 + j;
-      if (m < M && n < N) {
-        float* c = C + (int64_t)m * ldc + n;
-        *c = accumulate ? *c + acc[i][j] : acc[i][j];
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + a * 16 + 4 * lk + r, n = n0 + wn + b * 16 + li;
+        if (m < M && n < N) {
+          float* c = C + (int64_t)m * ldc + n;
+          *c = accumulate ? *c + acc[a][b][r] : acc[a][b][r];
+        }
       }
-    }
 }
 
 static void sgemm(bool ta, bool tb, int M, int N, int K, const float* A, int lda, const float* B, int ldb, float* C,
