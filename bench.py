@@ -585,6 +585,10 @@ def main():
         "E": E,
         "niter": info["niter"],
         "n_mixed": info["n_mixed"],
+        # per iteration of the timed step: precision of K (0 FP64, 1 FP32, 2 BF16),
+        # energy and largest DIIS error element
+        "iterations": [{"prec": int(p), "E": e, "err": float(r)}
+                       for p, e, r in zip(info["prec_hist"], info["E_hist"], info["err_hist"])],
         "t_guess_s": round(info["t_guess"], 4),
         "floor_est": info["floor_est"],
         "learned_guess": learned,

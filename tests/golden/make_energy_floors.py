@@ -16,7 +16,22 @@ Per workload (seeded geometry, Schwarz 1e-12, core guess, DIIS(8), converged to
                roundings of the metric give;
   d_explicit   the same difference for B = (L^-1) raw with L^-1 formed
                explicitly (one triangular solve against the identity), the
-               other common way to apply the fit.
+               other common way to apply the fit;
+  d_integrals  the same difference for the metric and the raw integrals each
+               perturbed element-wise by 2e-15 relative (seeds 10..13), the
+               accuracy of two independent exact integral algorithms (the Rys
+               root and weight tables agree with 60-digit values to 2.2e-15
+               relative); integral_floor = max |d_integrals|;
+  d_hilo       the same difference for B stored as two FP32 words, hi =
+               fl32(B) and lo = fl32(B - hi), as the GPU holds it (about 2^-48
+               relative);
+  d_order      the same difference with the auxiliary functions taken in
+               reverse order (metric and raw rows permuted, then the same
+               Cholesky and solve): an exact symmetry of the fit, so the
+               difference is rounding alone, as any other order of the
+               factorisation's operations would give it;
+  spread       max of floor, integral_floor, |d_hilo| and |d_order|: how far
+               apart equally valid FP64 evaluations of this energy lie.
 
     python tests/golden/make_energy_floors.py water2 water3 alkane
 """
@@ -73,6 +88,30 @@ def run(name):
         deltas.append(energy_at(dfp, h, C, Enuc) - E0)
         del dfp
         print(f"  metric perturbation {seed}: dE = {deltas[-1]:.3e}", flush=True)
+    d_int = []
+    for seed in range(10, 14):
+        rng = np.random.default_rng(seed)
+        R = rng.uniform(-1.0, 1.0, size=J2.shape)
+        Lp = sla.cholesky(J2 * (1.0 + 2e-15 * (R + R.T) / 2.0), lower=True)
+        del R
+        rawp = raw * (1.0 + 2e-15 * rng.uniform(-1.0, 1.0, size=raw.shape))
+        dfp = O.DF(bas, aux, scr, sla.solve_triangular(Lp, rawp, lower=True), Lp)
+        del rawp
+        d_int.append(energy_at(dfp, h, C, Enuc) - E0)
+        del dfp
+        print(f"  integral-level perturbation {seed}: dE = {d_int[-1]:.3e}", flush=True)
+    perm = np.arange(aux.nbf)[::-1]
+    Lr = sla.cholesky(J2[np.ix_(perm, perm)], lower=True)
+    dfr = O.DF(bas, aux, scr, sla.solve_triangular(Lr, raw[perm], lower=True), Lr)
+    d_order = energy_at(dfr, h, C, Enuc) - E0
+    del dfr, Lr
+    print(f"  auxiliary functions reversed: dE = {d_order:.3e}", flush=True)
+    hi = B.astype(np.float32)
+    B2 = hi.astype(np.float64) + (B - hi.astype(np.float64)).astype(np.float32).astype(np.float64)
+    del hi
+    d_hilo = energy_at(O.DF(bas, aux, scr, B2, L), h, C, Enuc) - E0
+    del B2
+    print(f"  hi + lo FP32 words: dE = {d_hilo:.3e}", flush=True)
     Linv = sla.solve_triangular(L, np.eye(aux.nbf), lower=True)
     dfi = O.DF(bas, aux, scr, Linv @ raw, L)
     d_explicit = energy_at(dfi, h, C, Enuc) - E0
@@ -83,17 +122,23 @@ def run(name):
             "E_at_Dstar": E0, "niter": res.niter, "converged": bool(res.converged), "tau": 1e-12,
             "conv": {"dE": 1e-10, "err": 1e-8}, "kappa": float(w[-1] / w[0]),
             "deltas": deltas, "floor": float(max(abs(d) for d in deltas)), "d_explicit": d_explicit,
+            "d_hilo": d_hilo, "d_order": d_order, "d_integrals": d_int,
+            "integral_floor": float(max(abs(d) for d in d_int)),
+            "spread": float(max([abs(d) for d in deltas] + [abs(d) for d in d_int] + [abs(d_hilo), abs(d_order)])),
             "oracle_seconds": round(time.time() - t0, 1),
             "source": "oracle (McMurchie-Davidson integrals, scipy Cholesky and triangular solve, DIIS RHF)"}
 
 
 def main():
     names = sys.argv[1:] or ["water2", "water3", "alkane"]
-    data = json.load(open(OUT)) if os.path.exists(OUT) else {}
     for n in names:
-        data[n] = run(n)
-        json.dump(data, open(OUT, "w"), indent=1)
-        print(json.dumps(data[n]), flush=True)
+        row = run(n)
+        # re-read before writing: several workloads may run in parallel processes
+        data = json.load(open(OUT)) if os.path.exists(OUT) else {}
+        data[n] = row
+        json.dump(data, open(OUT + f".{n}.tmp", "w"), indent=1)
+        os.replace(OUT + f".{n}.tmp", OUT)
+        print(json.dumps(row), flush=True)
 
 
 if __name__ == "__main__":
