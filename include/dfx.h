@@ -333,8 +333,9 @@ typedef struct {
   int32_t purify;        /* 1 (default): after the first iteration, the occupied orbitals of
                             X^T F X come from trace-correcting purification (Niklasson,
                             Phys. Rev. B 66, 155115 (2002)) and a Cholesky QR of the
-                            projector times the previous ones; dsyevd where it does not
-                            settle.  0: dsyevd every iteration.  C and eps are the
+                            projector times the previous ones; the full eigen-decomposition
+                            (dfx_eigh's block Jacobi) where it does not settle.  0: the
+                            eigen-decomposition every iteration.  C and eps are the
                             eigenvectors and eigenvalues of the last X^T F X either way */
   double level_shift;    /* dfx_uhf / dfx_rohf only (dfx_scf: must be 0): b >= 0 added to the
                             virtual levels before each diagonalisation (Saunders and Hillier,
@@ -374,7 +375,7 @@ typedef struct {
   double t_j;            /* all J builds */
   double t_kx;           /* all K half-transforms X_Q = B_Q C_occ */
   double t_ksyrk;        /* all K contractions sum_Q X_Q X_Q^T (incl. reduction) */
-  double t_eig;          /* all occupied-space updates (X^T F X, purification or dsyevd,
+  double t_eig;          /* all occupied-space updates (X^T F X, purification or eigen-decomposition,
                             C_occ and D) and the overlap eigensolve */
   int32_t n_jk;          /* J/K builds performed */
   int32_t n_kx_launch;   /* half-transform kernel launches */
@@ -394,7 +395,7 @@ typedef struct {
                              used instead; 2 no convergence from it in max_iter, restarted
                              from the core guess (niter and the histories count both passes) */
   int32_t n_purified;    /* occupied-space updates by purification */
-  int32_t n_eigh;        /* occupied-space updates by dsyevd (the final C/eps solve excluded) */
+  int32_t n_eigh;        /* occupied-space updates by eigen-decomposition (the final C/eps solve excluded) */
   int32_t purify_steps;  /* purification steps (matrix squarings) over all updates */
   double t_trsm_update;  /* the B transform's block update products alone (inside t_trsm) */
   double trsm_update_flops;
@@ -468,7 +469,7 @@ int dfx_grad_plan(const dfx_shell* shells, int nsh, const dfx_shell* aux, int na
  *   D_s = C_s,occ C_s,occ^T,  F_s = h + J[D_alpha + D_beta] - K[D_s]  (s = alpha, beta),
  *   E = 1/2 sum_s tr D_s (h + F_s) + E_nn,
  * one Pulay DIIS over both spins (error overlaps summed, both Fock matrices
- * extrapolated with the same coefficients), aufbau per spin with dsyevd, start
+ * extrapolated with the same coefficients), aufbau per spin (block Jacobi eigen-decomposition), start
  * from the core Hamiltonian for both spins.  FP64 J and K throughout.
  *   opts          as for dfx_scf; guess must be DFX_GUESS_CORE and schedule
  *                 DFX_SCHED_FP64 (DFX_EINVAL otherwise); the purification, learned

@@ -209,10 +209,13 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_kernel(const Eri3Args a) {
 }
 
 // number of ket solid-harmonic components per kernel instantiation: keep the
-// accumulator block near 64 doubles per lane
+// accumulator block near ERI_ACC doubles per lane
+#ifndef ERI_ACC
+#define ERI_ACC 32
+#endif
 __host__ __device__ constexpr int eri_group(int LA, int LB, int LC) {
   const int nab = ncart(LA) * ncart(LB);
-  int g = 64 / nab;
+  int g = ERI_ACC / nab;
   if (g < 1) g = 1;
   if (g > 2 * LC + 1) g = 2 * LC + 1;
   return g;

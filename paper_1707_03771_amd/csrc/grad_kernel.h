@@ -198,11 +198,22 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_grad_kernel(const GradArgs g
   if (live) ga.pbuf[(int64_t)blockIdx.y * a.npairs + p] = glane;
 }
 
+// ket solid-harmonic components per derivative kernel: the accumulator block
+// near 64 doubles per lane (the kernels keep one weighted sum per lane, so the
+// block is live only within a ket shell)
+__host__ __device__ constexpr int grad_group(int LA, int LB, int LC) {
+  const int nab = ncart(LA) * ncart(LB);
+  int g = 64 / nab;
+  if (g < 1) g = 1;
+  if (g > 2 * LC + 1) g = 2 * LC + 1;
+  return g;
+}
+
 // Every ket group writes its own partial sums for the same lanes and ket
 // shells: group k of a class launch writes at pbuf + k pstride, kbuf + k kstride.
 template <int LA, int LB, int LC, bool UNITB, int WHICH, int AXIS, int M0 = 0>
 void grad_launch_groups(GradArgs ga, dim3 grid, int64_t pstride, int64_t kstride, hipStream_t st) {
-  constexpr int G = eri_group(LA, LB, LC);
+  constexpr int G = grad_group(LA, LB, LC);
   constexpr int NS = 2 * LC + 1;
   constexpr int GN = (M0 + G <= NS) ? G : NS - M0;
   hipLaunchKernelGGL((eri3_grad_kernel<LA, LB, LC, M0, GN, UNITB, WHICH, AXIS>), grid, dim3(ERI_THREADS), 0, st, ga);
@@ -215,7 +226,7 @@ void grad_launch_groups(GradArgs ga, dim3 grid, int64_t pstride, int64_t kstride
 
 // number of ket groups of a class (the number of partial-sum slices it writes)
 __host__ __device__ constexpr int grad_groups_of(int LA, int LB, int LC) {
-  const int G = eri_group(LA, LB, LC);
+  const int G = grad_group(LA, LB, LC);
   return (2 * LC + 1 + G - 1) / G;
 }
 

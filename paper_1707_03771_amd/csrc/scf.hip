@@ -12,8 +12,10 @@
 // The occupied space of X^T F X comes from trace-correcting purification
 // (Niklasson, Phys. Rev. B 66, 155115 (2002)) -- FP64 matrix products only --
 // followed by a Cholesky QR (applied twice) of the projector times the previous
-// occupied orbitals; rocSOLVER's dsyevd serves the starting guess, the final
-// orbitals and energies, and any purification that does not converge.
+// occupied orbitals; the library's block Jacobi eigensolver (eig.hip) serves
+// the first update from the core guess, the final orbitals and energies, and
+// any purification that does not converge.  The orthonormal basis is Loewdin's
+// S^-1/2 by Newton-Schulz where no function is near the drop threshold.
 
 #include <algorithm>
 #include <chrono>
@@ -818,7 +820,7 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
 
     // occupied orbitals of a Fock-like matrix F: Cocc = X Y with Y the nocc lowest
     // levels of F' = X^T F X (kept in Fq), D = Cocc Cocc^T.  Purification when a
-    // previous Y exists, else (or if it fails) dsyevd, which also gives C and eps.
+    // previous Y exists, else (or if it fails) the full eigen-decomposition, which also gives C and eps.
     DevMem Fq(8 * (size_t)m * m), Yo(8 * (size_t)m * nocc), Zo(8 * (size_t)m * nocc),
         Go(8 * (size_t)nocc * nocc), lohi(16 * (size_t)m);
     bool have_y = false, cm_valid = false, fq_valid = false;
@@ -840,7 +842,7 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
         ++n_purified;
         purify_steps += steps;
       } else {
-        if (tried && o.verbose) std::fprintf(stderr, "dfx_scf purification failed (%s), dsyevd\n", why);
+        if (tried && o.verbose) std::fprintf(stderr, "dfx_scf purification failed (%s), eigen-decomposition\n", why);
         DFX_HIP(hipMemcpyAsync(Fp.p, Fq.p, 8 * (size_t)m * m, hipMemcpyDeviceToDevice, st));
         S.syevd(Fp.as<double>(), m, eps.as<double>());
         S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm.as<double>(), m);  // X V
@@ -896,7 +898,7 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
         S.gemm(m, m, n, t1.as<double>(), n, false, Uk.as<double>(), m, false, Fp.as<double>(), m);
       }
       // the top nocc eigenvectors span the occupied space of the lowest levels of
-      // -P': purified from a seeded random start, else dsyevd
+      // -P': purified from a seeded random start, else the full eigen-decomposition
       bool done = false;
       if (o.purify) {
         const int64_t mm = (int64_t)m * m, mo = (int64_t)m * nocc;
@@ -1320,7 +1322,7 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
       Fh[k].alloc(8 * n2);
       Eh[k].alloc(8 * (size_t)m * m);
     }
-    // occupied orbitals of spin s2 from a Fock-like matrix (dsyevd of X^T F X)
+    // occupied orbitals of spin s2 from a Fock-like matrix (eigen-decomposition of X^T F X)
     auto diag = [&](int s2, const double* Fx) {
       S.gemm(m, n, n, X.as<double>(), m, true, Fx, n, false, t1.as<double>(), n);
       S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Fp.as<double>(), m);

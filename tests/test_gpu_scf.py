@@ -43,7 +43,7 @@ def test_restart_from_converged_orbitals(dfx, h4_ref):
 
 @pytest.mark.parametrize("purify", [0, 1])
 def test_density_guess(dfx, h4_ref, purify):
-    """The converged density as the start: its occupied space by dsyevd or by
+    """The converged density as the start: its occupied space by the eigen-decomposition or by
     purification from a seeded random start converges at once."""
     xyz, Z, sh, ax, nocc, ref = h4_ref
     E, _, _, info = dfx.scf(xyz, Z, sh, ax, init=ref.D, guess=dfx.GUESS_DENSITY, purify=purify)
@@ -92,7 +92,7 @@ def test_multi_class_molecule(dfx):
 @pytest.mark.parametrize("system", ["h4", "mixed"])
 def test_purification_matches_eigensolver(dfx, h4_ref, system):
     """The occupied space from trace-correcting purification + Cholesky QR gives
-    the energy, density and final orbital energies of dsyevd every iteration."""
+    the energy, density and final orbital energies of a full eigen-decomposition every iteration."""
     if system == "h4":
         xyz, Z, sh, ax, nocc, _ = h4_ref
     else:
