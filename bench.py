@@ -528,7 +528,9 @@ def main():
         log(f"{tag}: E = {E:.10f}  iters {info['niter']} (mixed {info['n_mixed']})  "
             f"wall {dt:.2f} s  guess {info['t_guess']:.3f} eri {info['t_eri']:.3f} trsm {info['t_trsm']:.3f} "
             f"(updates {info['t_trsm_update']:.3f}) "
-            f"j {info['t_j']:.3f} kx {info['t_kx']:.3f} ksyrk {info['t_ksyrk']:.3f} eig {info['t_eig']:.3f}")
+            f"j {info['t_j']:.3f} kx {info['t_kx']:.3f} ksyrk {info['t_ksyrk']:.3f} eig {info['t_eig']:.3f} "
+            f"(purification {info['t_purify']:.3f} over {info['n_purified']} updates, "
+            f"{info['purify_steps']} squarings)")
         pn = {0: "d", 1: "s", 2: "b"}
         log("   history: " + " ".join(f"{pn.get(p, '?')}{e:.1e}" for p, e in zip(info["prec_hist"], info["err_hist"])))
         eh = info["E_hist"]
@@ -595,7 +597,12 @@ def main():
         "context_core_guess": context,
         "eri_per_s": info["nintegrals"] / info["t_eri"] if info["t_eri"] > 0 else None,
         "phases_s": {k: round(info[k], 4) for k in ("t_setup", "t_scf", "t_eri", "t_metric", "t_trsm",
-                                                     "t_trsm_update", "t_j", "t_kx", "t_ksyrk", "t_eig")},
+                                                     "t_trsm_update", "t_j", "t_kx", "t_ksyrk", "t_eig",
+                                                     "t_purify")},
+        # occupied-space updates by purification: count, squarings and GPU time each
+        "purification": {"updates": info["n_purified"], "squarings": info["purify_steps"],
+                         "ms_per_update": round(1e3 * info["t_purify"] / info["n_purified"], 3)
+                         if info["n_purified"] else None},
         "roofline": roofline(info, nbf, naux, nocc),
         "plain_fp64": plain,
     }

@@ -400,6 +400,8 @@ typedef struct {
   double t_trsm_update;  /* the B transform's block update products alone (inside t_trsm) */
   double trsm_update_flops;
   int32_t n_trsm_update; /* their launches */
+  double t_purify;       /* the purifications of the occupied-space updates alone (inside t_eig;
+                            failed attempts included), seconds */
 } dfx_scf_info;
 
 void dfx_scf_default_opts(dfx_scf_opts* o);

@@ -93,7 +93,7 @@ class ScfInfo(ctypes.Structure):
                 ("floor_est", ctypes.c_double * 3), ("guess_fallback", ctypes.c_int32),
                 ("n_purified", ctypes.c_int32), ("n_eigh", ctypes.c_int32), ("purify_steps", ctypes.c_int32),
                 ("t_trsm_update", ctypes.c_double), ("trsm_update_flops", ctypes.c_double),
-                ("n_trsm_update", ctypes.c_int32)]
+                ("n_trsm_update", ctypes.c_int32), ("t_purify", ctypes.c_double)]
 
 
 class Eri3Sizes(ctypes.Structure):

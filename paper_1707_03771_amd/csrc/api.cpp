@@ -328,13 +328,11 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     const int nbf = B->nbf, naux = B->naux;
     B->ncols_t = tiled_cols(nbf);
     // What outlives this call first, at the bottom of a caller's workspace: B's
-    // two words (zeroed: tile elements of screened pairs stay zero), then the
-    // metric and its factor when kept.  Everything allocated after them is
-    // released before returning, into one contiguous free block.
+    // two words (every element written by the split below), then the metric and
+    // its factor when kept.  Everything allocated after them is released before
+    // returning, into one contiguous free block.
     B->hi.alloc(sizeof(float) * (size_t)naux * B->ncols_t);
     B->lo.alloc(sizeof(float) * (size_t)naux * B->ncols_t);
-    DFX_HIP(hipMemsetAsync(B->hi.p, 0, B->hi.n, st));
-    DFX_HIP(hipMemsetAsync(B->lo.p, 0, B->lo.n, st));
     B->J2.alloc(sizeof(double) * naux * (size_t)naux);
     if (flags & DFX_KEEP_METRIC) B->L.alloc(sizeof(double) * naux * (size_t)naux);
     GpuTimer tm(st);
@@ -581,12 +579,17 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     }
     cw.release();
 
-    // -- B = L^-1 raw over raw's columns, split into FP32 hi / lo and scattered
-    // to the tiled layout: raw column -> its tile position (r >= c), plus the
-    // mirror position inside a diagonal tile; of the duplicate columns (i, j)
-    // and (j, i) of a diagonal shell pair only i >= j is stored.  Tile elements
-    // of screened pairs stay zero.
-    std::vector<int64_t> cmap(B->ncols_p), cmap2(B->ncols_p);
+    // -- B = L^-1 raw over raw's columns, split into FP32 hi / lo in the tiled
+    // layout.  src[t] is the raw column that tile element t takes: a pair block's
+    // element (mu, nu) goes to row max, column min of its lower tile, and inside
+    // a diagonal tile also to the mirror position; of the duplicate columns (i, j)
+    // and (j, i) of a diagonal shell pair only i >= j is used.  Elements of
+    // screened pairs and of the padding take none (zero).
+    std::vector<int64_t> src(B->ncols_t, -1);
+    auto take = [&](int64_t t, int64_t col) {
+      if (src[t] >= 0) throw Error(DFX_EINVAL, "eri3: two pair columns map to one tile element");
+      src[t] = col;
+    };
     for (int cls = 0; cls < 16; ++cls) {
       const int SA = 2 * (cls / 4) + 1, SB = 2 * (cls % 4) + 1;
       const int64_t npc = (int64_t)cf[cls].size();
@@ -596,18 +599,15 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
           for (int mb = 0; mb < SB; ++mb) {
             const int64_t col = B->cls_base[cls] + p * (SA * SB) + (ma * SB + mb);
             const int mu = B->bas.foff[f] + ma, nu = B->bas.foff[sh] + mb;
-            if (f == sh && mu < nu) {  // the other triangle of a diagonal block: a duplicate
-              cmap[col] = cmap2[col] = -1;
-              continue;
-            }
+            if (f == sh && mu < nu) continue;  // the other triangle of a diagonal block: a duplicate
             const int r = std::max(mu, nu), c = std::min(mu, nu);
             const int I = r >> 5, J = c >> 5;
-            cmap[col] = tile_base(I, J) + ((r & 31) << 5) + (c & 31);
-            cmap2[col] = (I == J && r != c) ? tile_base(I, J) + ((c & 31) << 5) + (r & 31) : -1;
+            take(tile_base(I, J) + ((r & 31) << 5) + (c & 31), col);
+            if (I == J && r != c) take(tile_base(I, J) + ((c & 31) << 5) + (r & 31), col);
           }
       }
     }
-    DevMem cmap_d = upload(cmap, st), cmap2_d = upload(cmap2, st);
+    DevMem src_d = upload(src, st);
     // B = L^-1 raw by blocked forward substitution, in place (on a copy when the
     // raw integrals are kept), then split into the two FP32 words.  The timed
     // span holds these launches and nothing else; the update products are also
@@ -628,8 +628,7 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     GpuTimer tt(st);
     tt.start();
     const TrsmStats ts = trsm_solve(Lp, naux, Bw, B->ncols_p, st, &ut);
-    split_scatter(Bw, naux, B->ncols_p, B->hi.as<float>(), B->lo.as<float>(), B->ncols_t, cmap_d.as<int64_t>(),
-                  cmap2_d.as<int64_t>(), st);
+    tile_split(Bw, naux, B->ncols_p, src_d.as<int64_t>(), B->hi.as<float>(), B->lo.as<float>(), B->ncols_t, st);
     DFX_HIP(hipGetLastError());
     tt.stop();
     B->info.trsm_seconds = tt.seconds();

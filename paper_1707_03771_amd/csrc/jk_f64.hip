@@ -383,4 +383,26 @@ void k_build_f64(const JKArgs& a, const double* C, int nocc, double* K, void* wo
   sym_from_lower(K, a.nbf, st);
 }
 
+// C = A A^T (n x n, both triangles) for a row-major n x k matrix A with an even
+// row stride lda, on the exchange build's SYRK: lower 128 x 128 tiles, eight
+// k-slices (one per XCD), summed in FP64 in a fixed order, then mirrored.
+// For a symmetric A this is A^2 at half the FLOPs of a general product.
+// work: syrk_f64_work_elems(n) doubles.
+size_t syrk_f64_work_elems(int n) { return (size_t)8 * n * n; }
+
+void syrk_f64(const double* A, int64_t lda, int n, int64_t k, double* C, double* work, hipStream_t st) {
+  if (n <= 0) return;
+  if ((lda & 1) || lda < k || (reinterpret_cast<uintptr_t>(A) & 15))
+    throw Error(-1, "syrk_f64: A needs an even row stride >= k and 16-byte alignment");
+  const int mt = (n + 127) / 128;
+  const int ntl = mt * (mt + 1) / 2;
+  const int ns = 8;
+  const int64_t kslice = ((k + ns - 1) / ns + S64 - 1) / S64 * S64;
+  const int64_t n2 = (int64_t)n * n;
+  hipLaunchKernelGGL(syrk64_kernel, dim3((unsigned)(ns * ntl)), dim3(SY_T), 0, st, A, lda, n, kslice, k, ns, ntl,
+                     work);
+  hipLaunchKernelGGL(k_reduce64_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, work, ns, n, C, 0);
+  sym_from_lower(C, n, st);
+}
+
 }  // namespace dfx

@@ -71,10 +71,10 @@ TrsmStats trsm_solve(const double* L, int n, double* raw, int64_t ncols, hipStre
 // X = L^-T X in place (n x ncols, row stride ncols) by blocked back
 // substitution with the lower-triangular L: the transpose of trsm_solve.
 void trsm_solve_t(const double* L, int n, double* X, int64_t ncols, hipStream_t st);
-// hi = fl32(B), lo = fl32(B - hi) of B (n x ncols) into rows of length ld_out at
-// the columns cmap (and cmap2 where >= 0)
-void split_scatter(const double* B, int n, int64_t ncols, float* hi, float* lo, int64_t ld_out, const int64_t* cmap,
-                   const int64_t* cmap2, hipStream_t st);
+// hi = fl32(B), lo = fl32(B - hi) of B (n x ncols) into rows of length ld_out (whole
+// 32 x 32 tiles): element t of each row from column src[t] of B, zero where src[t] < 0
+void tile_split(const double* B, int n, int64_t ncols, const int64_t* src, float* hi, float* lo, int64_t ld_out,
+                hipStream_t st);
 
 // Blocked Cholesky J = L L^T in place (lower), then Linv = L^-1.  Returns via
 // *info (device int) the first non-positive pivot + 1, or 0; a pivot below
@@ -135,6 +135,10 @@ double mp2_energy(const JKArgs& a, const double* C, int nmo, const double* eps, 
                   hipStream_t st);
 void k_build_f64(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st,
                  KTimer* timer);
+// C = A A^T (both triangles) for a row-major n x k A, even row stride lda,
+// 16-byte aligned (jk_f64.hip); work: syrk_f64_work_elems(n) doubles
+size_t syrk_f64_work_elems(int n);
+void syrk_f64(const double* A, int64_t lda, int n, int64_t k, double* C, double* work, hipStream_t st);
 // reduced-precision K (jk_mixed.hip), dispatched by k_build for PREC_FP32 / PREC_BF16
 size_t k_work_bytes_mixed(const JKArgs& a, int nocc);
 void k_build_mixed(const JKArgs& a, const double* C, int nocc, double* K, void* work, hipStream_t st,

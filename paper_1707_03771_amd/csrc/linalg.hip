@@ -358,25 +358,38 @@ __global__ void __launch_bounds__(TS_T) trsv64t_cols_kernel(const double* __rest
   for (int i = TS_R - 1; i >= 0; --i) X[(int64_t)(FULL ? i : min(i, nr - 1)) * ldx + c] = x[i];
 }
 
-// hi = fl32(B), lo = fl32(B - hi) scattered to the tile layout: packed column c
-// goes to column cmap[c] of a row of length ld_out (none if negative), and also
-// to cmap2[c] when that is >= 0 (the mirror position inside a diagonal tile)
-__global__ void split_scatter_kernel(const double* __restrict__ B, int64_t ncols, const int64_t* __restrict__ cmap,
-                                     const int64_t* __restrict__ cmap2, float* __restrict__ hi,
-                                     float* __restrict__ lo, int64_t ld_out) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= ncols) return;
-  const int64_t q = blockIdx.y;
-  const double v = B[q * ncols + c];
-  const float h = (float)v, l = (float)(v - (double)h);
-  const int64_t t = cmap[c], t2 = cmap2[c];
-  if (t >= 0) {
-    hi[q * ld_out + t] = h;
-    lo[q * ld_out + t] = l;
-  }
-  if (t2 >= 0) {
-    hi[q * ld_out + t2] = h;
-    lo[q * ld_out + t2] = l;
+// hi = fl32(B), lo = fl32(B - hi) in the tile layout, gathered: element t of a
+// tiled row takes packed column src[t] of the same row of B, or zero where
+// src[t] < 0 (tile padding, screened pairs), so every element of the tiled rows
+// is written.  One workgroup per 32 x 32 tile and SPLIT_Q rows: thread i takes
+// tile elements i, i + 256, i + 512, i + 768, so a wave writes two whole tile
+// rows (coalesced), while the workgroup reads the few contiguous pair blocks of
+// B the tile draws on, with their reuse in one XCD's L2.
+constexpr int SPLIT_Q = 4;
+__global__ void __launch_bounds__(256) tile_split_kernel(const double* __restrict__ B, int64_t ncols, int nrows,
+                                                         const int64_t* __restrict__ src, float* __restrict__ hi,
+                                                         float* __restrict__ lo, int64_t ld_out) {
+  const int64_t t0 = (int64_t)blockIdx.x * 1024 + threadIdx.x;
+  int64_t s[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) s[j] = src[t0 + 256 * j];
+  const int q0 = blockIdx.y * SPLIT_Q;
+  double v[SPLIT_Q][4];
+#pragma unroll
+  for (int k = 0; k < SPLIT_Q; ++k)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      v[k][j] = (q0 + k < nrows && s[j] >= 0) ? B[(int64_t)(q0 + k) * ncols + s[j]] : 0.0;
+#pragma unroll
+  for (int k = 0; k < SPLIT_Q; ++k) {
+    if (q0 + k >= nrows) break;
+    const int64_t o = (int64_t)(q0 + k) * ld_out + t0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float h = (float)v[k][j];
+      hi[o + 256 * j] = h;
+      lo[o + 256 * j] = (float)(v[k][j] - (double)h);
+    }
   }
 }
 
@@ -486,13 +499,14 @@ TrsmStats trsm_solve(const double* L, int n, double* raw, int64_t ncols, hipStre
   return z;
 }
 
-void split_scatter(const double* B, int n, int64_t ncols, float* hi, float* lo, int64_t ld_out, const int64_t* cmap,
-                   const int64_t* cmap2, hipStream_t st) {
-  if (ncols <= 0 || n <= 0) return;
-  for (int q0 = 0; q0 < n; q0 += 65535) {
-    const int nq = std::min(65535, n - q0);
-    const dim3 g((unsigned)((ncols + 255) / 256), nq);
-    hipLaunchKernelGGL(split_scatter_kernel, g, dim3(256), 0, st, B + (int64_t)q0 * ncols, ncols, cmap, cmap2,
+void tile_split(const double* B, int n, int64_t ncols, const int64_t* src, float* hi, float* lo, int64_t ld_out,
+                hipStream_t st) {
+  if (n <= 0 || ld_out <= 0) return;
+  if (ld_out % 1024) throw Error(-1, "tile_split: the tiled row length must be whole 32 x 32 tiles");
+  for (int q0 = 0; q0 < n; q0 += 65535 * SPLIT_Q) {
+    const int nq = std::min(65535 * SPLIT_Q, n - q0);
+    const dim3 g((unsigned)(ld_out / 1024), (unsigned)((nq + SPLIT_Q - 1) / SPLIT_Q));
+    hipLaunchKernelGGL(tile_split_kernel, g, dim3(256), 0, st, B + (int64_t)q0 * ncols, ncols, nq, src,
                        hi + (int64_t)q0 * ld_out, lo + (int64_t)q0 * ld_out, ld_out);
   }
 }

@@ -446,6 +446,14 @@ struct Scf {
     return true;
   }
 
+  // P2 = P P^T, which is P^2 for the symmetric P: the symmetric product (half the
+  // FLOPs) where the row stride allows it, else the general product
+  void square_sym(const double* P, double* P2) {
+    if (m % 2 == 0 && gw.n >= sizeof(double) * syrk_f64_work_elems(m))
+      syrk_f64(P, m, m, m, P2, gw.as<double>(), st);
+    else
+      gemm(m, m, m, P, m, false, P, m, false, P2, m);
+  }
   // Occupied space of the symmetric m x m matrix F (the nocc lowest levels) by
   // trace-correcting purification: P0 = (e_max I - F) / (e_max - e_min) with
   // Gershgorin bounds, then P <- P^2 or 2P - P^2, whichever moves tr P toward
@@ -473,7 +481,7 @@ struct Scf {
     int settled = 0;
     bool ok = false;
     for (steps = 0; steps < 100; ++steps) {
-      gemm(m, m, m, P, m, false, P, m, false, P2, m);
+      square_sym(P, P2);
       hipLaunchKernelGGL(trace2_kernel, dim3(1), dim3(256), 0, st, P, P2, m, part.as<double>());
       DFX_HIP(hipMemcpyAsync(b, part.p, sizeof b, hipMemcpyDeviceToHost, st));
       DFX_HIP(hipStreamSynchronize(st));
@@ -778,10 +786,10 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
     S.n = n;
     S.nocc = nocc;
     S.part.alloc(sizeof(double) * 512);
-    S.gw.alloc(sizeof(double) * 4 * (size_t)n * n);
+    S.gw.alloc(sizeof(double) * std::max<size_t>(4 * (size_t)n * n, syrk_f64_work_elems(n)));
     S.verbose = o.verbose;
-    EventSpans sp_eig_all;
-    sp_eig_all.st = S.st;
+    EventSpans sp_eig_all, sp_pur;
+    sp_eig_all.st = sp_pur.st = S.st;
     S.eig_spans = &sp_eig_all;
     const int64_t n2 = (int64_t)n * n;
 
@@ -834,8 +842,14 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
       int steps = 0;
       const char* why = "";
       const bool tried = o.purify && have_y;
-      if (tried && S.purify_occ(Fq.as<double>(), t1.as<double>(), t2.as<double>(), Yo.as<double>(),
-                                Zo.as<double>(), Go.as<double>(), lohi.as<double>(), steps, why)) {
+      bool purified = false;
+      if (tried) {
+        sp_pur.begin();
+        purified = S.purify_occ(Fq.as<double>(), t1.as<double>(), t2.as<double>(), Yo.as<double>(), Zo.as<double>(),
+                                Go.as<double>(), lohi.as<double>(), steps, why);
+        sp_pur.end();
+      }
+      if (purified) {
         if (o.verbose) std::fprintf(stderr, "dfx_scf purification: %d steps\n", steps);
         S.gemm(n, nocc, m, X.as<double>(), m, false, Yo.as<double>(), nocc, false, Cocc.as<double>(), nocc);
         cm_valid = false;
@@ -1219,6 +1233,7 @@ int dfx_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
       inf.n_kx_launch += inf.n_kx_launch_p[k];
     }
     inf.t_eig = S.eig_spans ? S.eig_spans->seconds() : 0.0;
+    inf.t_purify = sp_pur.seconds();
     inf.n_jk = sp_j.count();
     inf.nintegrals = B->info.nintegrals;
     inf.ncols = B->info.ncols;
@@ -1276,7 +1291,7 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
     S.n = n;
     S.nocc = na;
     S.part.alloc(sizeof(double) * 512);
-    S.gw.alloc(sizeof(double) * 4 * (size_t)n * n);
+    S.gw.alloc(sizeof(double) * std::max<size_t>(4 * (size_t)n * n, syrk_f64_work_elems(n)));
     const int64_t n2 = (int64_t)n * n;
 
     // setup: fitted integrals, one-electron matrices, E_nn, canonical orthogonaliser

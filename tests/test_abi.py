@@ -161,3 +161,32 @@ def test_undersized_workspace_is_enomem_before_device_work():
     for fn in (lib.dfx_uhf, lib.dfx_rohf):
         assert fn(ctypes.byref(g.g), s.arr, s.n, a.arr, a.n, ctypes.byref(o), 1, ctypes.byref(E), None, None,
                   None) == dfx.ENOMEM
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every ctypes structure of the binding has the size and field offsets of
+    the C struct it mirrors, as a C compiler lays the header out."""
+    import shutil
+    import subprocess
+    import paper_1707_03771_amd as dfx
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    pairs = [(dfx.Shell, "dfx_shell"), (dfx.Geom, "dfx_geom"), (dfx.Eri3Opts, "dfx_eri3_opts"),
+             (dfx.BInfo, "dfx_B_info"), (dfx.Eri3Sizes, "dfx_eri3_sizes"), (dfx.ScfOpts, "dfx_scf_opts"),
+             (dfx.ScfInfo, "dfx_scf_info"), (dfx.GradInfo, "dfx_grad_info"), (dfx.GuessSpec, "dfx_guess_spec")]
+    lines = ["#include <stddef.h>", "#include <stdio.h>", '#include "dfx.h"', "int main(void) {"]
+    want = []
+    for cls, cname in pairs:
+        lines.append(f'  printf("%zu\\n", sizeof({cname}));')
+        want.append(ctypes.sizeof(cls))
+        for f in cls._fields_:
+            lines.append(f'  printf("%zu\\n", offsetof({cname}, {f[0]}));')
+            want.append(getattr(cls, f[0]).offset)
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split()]
+    assert got == want
