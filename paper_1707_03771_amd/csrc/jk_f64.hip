@@ -9,6 +9,7 @@
 #include <algorithm>
 
 #include <string>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -152,13 +153,15 @@ __global__ void __launch_bounds__(KX_T) kx64_kernel(const float* __restrict__ hi
 // one XCD so that the slice of X is fetched from HBM once per XCD L2.  Eight
 // waves in a 2 x 4 grid of 64 x 32 sub-tiles; on a diagonal tile the two waves
 // whose sub-tiles lie wholly above the diagonal load and synchronise but skip
-// their MFMAs.
+// their MFMAs.  Two LDS buffers alternate, so each stage needs one barrier:
+// stage t's buffer was last read in stage t - 2, which every wave finished
+// before the barrier of stage t - 1.
 constexpr int SY_T = 512;
 __global__ void __launch_bounds__(SY_T) syrk64_kernel(const double* __restrict__ X, int64_t ldx, int nbf,
                                                       int64_t kslice, int64_t kdim, int nslices, int ntl,
                                                       double* __restrict__ P) {
-  __shared__ double As[128][S64 + PA];
-  __shared__ double Bs[128][S64 + PA];
+  __shared__ double As[2][128][S64 + PA];
+  __shared__ double Bs[2][128][S64 + PA];
   const int bid = blockIdx.x;
   const int xcd = bid & 7, local = bid >> 3;
   const int s = xcd + 8 * (local / ntl);
@@ -212,30 +215,41 @@ __global__ void __launch_bounds__(SY_T) syrk64_kernel(const double* __restrict__
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  if (k0s < k1s) load(k0s);
-  for (int64_t k0 = k0s; k0 < k1s; k0 += S64) {
-    __syncthreads();
+  auto stage = [&](auto bufc) {
+    constexpr int BUF = decltype(bufc)::value;
+#pragma unroll
+    for (int kk = 0; kk < S64; kk += 4) {
+      double fa[4], fb[2];
+#pragma unroll
+      for (int a = 0; a < 4; ++a) fa[a] = As[BUF][wm + a * 16 + li][kk + lk];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) fb[b] = Bs[BUF][wn + b * 16 + li][kk + lk];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
+    }
+  };
+  auto put = [&](int buf) {
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-      As[r][kq + e] = va[e];
-      Bs[r][kq + e] = vb[e];
+      As[buf][r][kq + e] = va[e];
+      Bs[buf][r][kq + e] = vb[e];
     }
+  };
+
+  if (k0s < k1s) load(k0s);
+  for (int64_t k0 = k0s; k0 < k1s; k0 += 2 * S64) {
+    put(0);
     __syncthreads();
     if (k0 + S64 < k1s) load(k0 + S64);
-    if (active) {
-#pragma unroll
-      for (int kk = 0; kk < S64; kk += 4) {
-        double fa[4], fb[2];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) fa[a] = As[wm + a * 16 + li][kk + lk];
-#pragma unroll
-        for (int b = 0; b < 2; ++b) fb[b] = Bs[wn + b * 16 + li][kk + lk];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-            acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb[b], acc[a][b], 0, 0, 0);
-      }
+    if (active) stage(std::integral_constant<int, 0>{});
+    if (k0 + S64 < k1s) {
+      put(1);
+      __syncthreads();
+      if (k0 + 2 * S64 < k1s) load(k0 + 2 * S64);
+      if (active) stage(std::integral_constant<int, 1>{});
     }
   }
   if (!active) return;

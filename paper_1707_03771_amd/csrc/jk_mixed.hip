@@ -8,6 +8,7 @@
 // (Q, i) index: FP32 MFMA sums of KT products, added up in FP64, reduced over
 // the slices in FP64 in a fixed order.
 #include <string>
+#include <type_traits>
 
 #include "kernels.h"
 
@@ -179,16 +180,21 @@ __global__ void __launch_bounds__(256) kx_mixed_kernel(const float* __restrict__
 // slice to one XCD so that the slice of X is fetched from HBM once per XCD L2.
 // Eight waves in a 2 x 4 grid of 64 x 32 sub-tiles.  The MFMAs accumulate one
 // k-stage (KT products) in FP32; each stage's sums are added into FP64
-// registers, so no FP32 accumulator sums more than KT products.  On a diagonal
-// tile the two waves whose sub-tiles lie above the diagonal skip their MFMAs.
+// registers, so no FP32 accumulator sums more than KT products.  A block's sums
+// are added at the start of the next stage, just before its first MFMA (which
+// starts from zero), so the additions overlap the other blocks' MFMAs.  Two LDS
+// buffers alternate, one barrier per stage: stage t's buffer was last read in
+// stage t - 2, which every wave finished before the barrier of stage t - 1.  On
+// a diagonal tile the two waves whose sub-tiles lie above the diagonal skip
+// their MFMAs.
 constexpr int SYM_T = 512;
 template <class Tr>
 __global__ void __launch_bounds__(SYM_T) syrk_mixed_kernel(const typename Tr::E* __restrict__ X, int64_t ldx,
                                                            int nbf, int64_t kslice, int64_t kdim, int nslices,
                                                            int ntl, double* __restrict__ P) {
   using E = typename Tr::E;
-  __shared__ __align__(16) E As[128][KT + lpad<E>()];
-  __shared__ __align__(16) E Bs[128][KT + lpad<E>()];
+  __shared__ __align__(16) E As[2][128][KT + lpad<E>()];
+  __shared__ __align__(16) E Bs[2][128][KT + lpad<E>()];
   // blockIdx.x -> (slice, lower tile)
   const int bid = blockIdx.x;
   const int xcd = bid & 7, local = bid >> 3;
@@ -238,36 +244,55 @@ __global__ void __launch_bounds__(SYM_T) syrk_mixed_kernel(const typename Tr::E*
 #pragma unroll
       for (int q = 0; q < 4; ++q) sum[a][b][q] = 0.0;
 
+  // acc starts at zero, so adding it before the first stage changes nothing
+  v4f acc[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
+  auto stage = [&](auto bufc) {
+    constexpr int BUF = decltype(bufc)::value;
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += Tr::KM)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          v4f c = acc[a][b];
+          if (kk == 0) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) sum[a][b][q] += (double)acc[a][b][q];
+            c = v4f{0.f, 0.f, 0.f, 0.f};
+          }
+          acc[a][b] = Tr::mma(&As[BUF][wm + a * 16 + li][kk + Tr::koff(lk)],
+                              &Bs[BUF][wn + b * 16 + li][kk + Tr::koff(lk)], c);
+        }
+  };
+  auto put = [&](int buf) {
+    st8(&As[buf][r][k8], va);
+    st8(&Bs[buf][r][k8], vb);
+  };
+
   if (k0s < k1s) load(k0s);
-  for (int64_t k0 = k0s; k0 < k1s; k0 += KT) {
-    __syncthreads();  // every wave is done with the previous stage
-    st8(&As[r][k8], va);
-    st8(&Bs[r][k8], vb);
+  for (int64_t k0 = k0s; k0 < k1s; k0 += 2 * KT) {
+    put(0);
     __syncthreads();
     if (k0 + KT < k1s) load(k0 + KT);  // in flight during the MFMAs below
-    if (active) {
-      v4f acc[4][2];
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int kk = 0; kk < KT; kk += Tr::KM)
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-            acc[a][b] = Tr::mma(&As[wm + a * 16 + li][kk + Tr::koff(lk)], &Bs[wn + b * 16 + li][kk + Tr::koff(lk)],
-                                acc[a][b]);
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) sum[a][b][q] += (double)acc[a][b][q];
+    if (active) stage(std::integral_constant<int, 0>{});
+    if (k0 + KT < k1s) {
+      put(1);
+      __syncthreads();
+      if (k0 + 2 * KT < k1s) load(k0 + 2 * KT);
+      if (active) stage(std::integral_constant<int, 1>{});
     }
   }
   if (!active) return;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) sum[a][b][q] += (double)acc[a][b][q];
   double* __restrict__ Ps = P + (int64_t)s * nbf * nbf;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
