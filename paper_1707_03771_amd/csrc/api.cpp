@@ -277,9 +277,10 @@ dfx::Eri3Need dfx::eri3_need(const HostShells& b, const HostShells& a, int flags
   z.bottom = shells_bytes(b) + shells_bytes(a) + z.bytes_B + m2 + ((flags & DFX_KEEP_METRIC) ? m2 : 0) +
              ((flags & DFX_KEEP_RAW) ? raw : 0);
   const int64_t lists = 16 * npall + 25 * npall + 20 * nauxsh + 256 * 256;
-  // raw itself, or its working copy when raw is kept; L when not kept
+  // raw itself, or its working copy when raw is kept; L when not kept; the
+  // Cholesky work (also the solve's packed diagonal blocks) and the tile map
   z.setup = lists + raw + ((flags & DFX_KEEP_METRIC) ? 0 : m2) +
-            pad256(8 * (int64_t)cholesky_work_elems((int)naux)) + 256 + 2 * pad256(8 * ncb);
+            pad256(8 * (int64_t)cholesky_work_elems((int)naux)) + 256 + std::max(2 * pad256(8 * ncb), pad256(8 * nct));
   z.jk = jk_need((int)nbf, (int)naux, nct);
   const int64_t top = std::max(z.setup, z.jk + pad256(8 * ncb));
   z.total = z.bottom + top + top / 64 + ((int64_t)16 << 20);
@@ -577,7 +578,6 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
       const auto mm = std::minmax_element(diag.begin(), diag.end());
       B->info.kappa_lb = (*mm.second / *mm.first) * (*mm.second / *mm.first);
     }
-    cw.release();
 
     // -- B = L^-1 raw over raw's columns, split into FP32 hi / lo in the tiled
     // layout.  src[t] is the raw column that tile element t takes: a pair block's
@@ -627,7 +627,9 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     ut.sp.st = st;
     GpuTimer tt(st);
     tt.start();
-    const TrsmStats ts = trsm_solve(Lp, naux, Bw, B->ncols_p, st, &ut);
+    // the Cholesky work (at least 65 naux doubles) holds the packed diagonal blocks
+    if (cw.n < sizeof(double) * trsm_work_elems(naux)) throw Error(-1, "eri3: Cholesky work too small for the solve");
+    const TrsmStats ts = trsm_solve(Lp, naux, Bw, B->ncols_p, cw.as<double>(), st, &ut);
     tile_split(Bw, naux, B->ncols_p, src_d.as<int64_t>(), B->hi.as<float>(), B->lo.as<float>(), B->ncols_t, st);
     DFX_HIP(hipGetLastError());
     tt.stop();
@@ -635,6 +637,7 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     B->info.trsm_update_seconds = ut.sp.seconds();
     B->info.trsm_update_flops = ts.update_flops;
     B->info.trsm_update_launches = ts.update_launches;
+    cw.release();
     if (!(flags & DFX_KEEP_METRIC)) B->J2.release();
     if (!(flags & DFX_KEEP_RAW)) B->raw.release();
     DFX_HIP(hipStreamSynchronize(st));

@@ -56,7 +56,9 @@ void dgemm_sk(const GemmF64& g, double* work, int64_t work_elems, hipStream_t st
 
 // B = L^-1 raw in place over raw (n x ncols, FP64, row stride ncols), by
 // blocked forward substitution with the lower-triangular L (n x n): backward
-// stable, unlike a product with an explicit inverse.
+// stable, unlike a product with an explicit inverse.  work: trsm_work_elems(n)
+// doubles (packed copies of L's 64 x 64 diagonal blocks), free once the last
+// launch on st has run.
 struct TrsmStats {
   double update_flops = 0.0;  // 2 M K N of every update product
   int update_launches = 0;
@@ -67,7 +69,9 @@ struct TrsmTimer {
   virtual void end() = 0;
   virtual ~TrsmTimer() = default;
 };
-TrsmStats trsm_solve(const double* L, int n, double* raw, int64_t ncols, hipStream_t st, TrsmTimer* timer = nullptr);
+size_t trsm_work_elems(int n);
+TrsmStats trsm_solve(const double* L, int n, double* raw, int64_t ncols, double* work, hipStream_t st,
+                     TrsmTimer* timer = nullptr);
 // X = L^-T X in place (n x ncols, row stride ncols) by blocked back
 // substitution with the lower-triangular L: the transpose of trsm_solve.
 void trsm_solve_t(const double* L, int n, double* X, int64_t ncols, hipStream_t st);

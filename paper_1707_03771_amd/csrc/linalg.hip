@@ -312,6 +312,60 @@ __global__ void __launch_bounds__(TS_T) trsv64_cols_kernel(const double* __restr
   for (int i = TS_R - 1; i >= 0; --i) X[(int64_t)(FULL ? i : min(i, nr - 1)) * ldx + c] = x[i];
 }
 
+// The same substitution for a full 64-row block, L given as a packed k-major
+// copy of the block (pack_diag_kernel: row k holds L_ik, i >= k, zeros before).
+// Every lane needs the same L_ik at the same step: read from global memory at
+// wave-uniform addresses (one base, constant offsets), they come through the
+// scalar cache into SGPRs, which the FMAs take directly, instead of every lane
+// reading them from LDS (whose return bandwidth bounds the kernel above).  Same
+// operations in the same order, so the same results bit for bit.
+__global__ void __launch_bounds__(TS_T) trsv64_sym_kernel(const double* __restrict__ Lk, double* __restrict__ X,
+                                                          int64_t ldx, int ncols) {
+  const int c = blockIdx.x * TS_T + threadIdx.x;
+  const bool own = c < ncols;
+  const int cc = own ? c : ncols - 1;  // lanes past the end repeat the last column and store nothing
+  double x[TS_R];
+#pragma unroll
+  for (int g = 0; g < TS_R; g += TS_G) {
+    double s[TS_G];
+#pragma unroll
+    for (int r = 0; r < TS_G; ++r) s[r] = X[(int64_t)(g + r) * ldx + cc];
+#pragma unroll
+    for (int k = 0; k < g; ++k) {
+      double l[TS_G];
+#pragma unroll
+      for (int r = 0; r < TS_G; ++r) l[r] = Lk[k * TS_R + g + r];
+#pragma unroll
+      for (int r = 0; r < TS_G; ++r) s[r] = fma(-l[r], x[k], s[r]);
+      // a compiler-only fence: the loads of L are invariant and would otherwise all be
+      // hoisted to the top, far beyond the SGPR budget
+      asm volatile("" ::: "memory");
+    }
+#pragma unroll
+    for (int r = 0; r < TS_G; ++r) {
+#pragma unroll
+      for (int k = 0; k < r; ++k) s[r] = fma(-Lk[(g + k) * TS_R + g + r], x[g + k], s[r]);
+      x[g + r] = s[r] / Lk[(g + r) * TS_R + g + r];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (own) {
+#pragma unroll
+    for (int i = 0; i < TS_R; ++i) X[(int64_t)i * ldx + c] = x[i];
+  }
+}
+
+// Packed k-major copies of the full 64 x 64 diagonal blocks of L (row stride n),
+// one workgroup per block: P[b][k][i] = L_(64b + i),(64b + k) for i >= k, else 0.
+__global__ void pack_diag_kernel(const double* __restrict__ L, int n, double* __restrict__ P) {
+  const int64_t o = (int64_t)blockIdx.x * TS_R * n + (int64_t)blockIdx.x * TS_R;
+  double* __restrict__ Pb = P + (int64_t)blockIdx.x * TS_R * TS_R;
+  for (int e = threadIdx.x; e < TS_R * TS_R; e += blockDim.x) {
+    const int k = e / TS_R, i = e % TS_R;
+    Pb[e] = i >= k ? L[o + (int64_t)i * n + k] : 0.0;
+  }
+}
+
 // L^T x = b for the nr <= 64 rows of every column of X (the diagonal block L of
 // the back substitution B = L^-T R): x_i = (b_i - sum_k>i L_ki x_k) / L_ii,
 // rows from the last, in groups of 8 as in trsv64_cols_kernel.  Rows beyond nr
@@ -393,14 +447,17 @@ __global__ void __launch_bounds__(256) tile_split_kernel(const double* __restric
   }
 }
 
+// Lk: for a full block (nr == 64), its packed k-major copy (pack_diag_kernel)
 static void trsv64_cols(const double* L, int64_t ldl, int nr, double* X, int64_t ldx, int64_t ncols,
-                        hipStream_t st) {
+                        hipStream_t st, const double* Lk = nullptr) {
   // columns in slabs whose indices fit the kernel's 32-bit column offsets
   const int64_t slab = (int64_t)TS_T * 1048576;
   for (int64_t c0 = 0; c0 < ncols; c0 += slab) {
     const int nc = (int)std::min<int64_t>(slab, ncols - c0);
     const dim3 g((unsigned)((nc + TS_T - 1) / TS_T));
-    if (nr == TS_R)
+    if (Lk && nr == TS_R)
+      hipLaunchKernelGGL(trsv64_sym_kernel, g, dim3(TS_T), 0, st, Lk, X + c0, ldx, nc);
+    else if (nr == TS_R)
       hipLaunchKernelGGL(trsv64_cols_kernel<true>, g, dim3(TS_T), 0, st, L, ldl, nr, X + c0, ldx, nc);
     else
       hipLaunchKernelGGL(trsv64_cols_kernel<false>, g, dim3(TS_T), 0, st, L, ldl, nr, X + c0, ldx, nc);
@@ -472,10 +529,17 @@ static double trsm_update(const double* A, int64_t lda, int M, int K, const doub
   return 2.0 * M * (double)K * (double)ncols;
 }
 
-TrsmStats trsm_solve(const double* L, int n, double* raw, int64_t ncols, hipStream_t st, TrsmTimer* timer) {
+size_t trsm_work_elems(int n) { return (size_t)(n / TS_R) * TS_R * TS_R; }
+
+TrsmStats trsm_solve(const double* L, int n, double* raw, int64_t ncols, double* work, hipStream_t st,
+                     TrsmTimer* timer) {
   TrsmStats z{};
   if (ncols <= 0) return z;
   constexpr int TB = 2 * TS_R;
+  // packed copies of the full diagonal blocks for the scalar-load substitution
+  const int nfull = n / TS_R;
+  if (nfull > 0) hipLaunchKernelGGL(pack_diag_kernel, dim3((unsigned)nfull), dim3(256), 0, st, L, n, work);
+  auto packed = [&](int r) { return r + TS_R <= nfull * TS_R ? work + (int64_t)(r / TS_R) * TS_R * TS_R : nullptr; };
   for (int r0 = 0; r0 < n; r0 += TB) {
     const int rb = std::min(TB, n - r0);
     if (r0 > 0) {
@@ -485,7 +549,7 @@ TrsmStats trsm_solve(const double* L, int n, double* raw, int64_t ncols, hipStre
       ++z.update_launches;
     }
     const int h1 = std::min(TS_R, rb);
-    trsv64_cols(L + (int64_t)r0 * n + r0, n, h1, raw + (int64_t)r0 * ncols, ncols, ncols, st);
+    trsv64_cols(L + (int64_t)r0 * n + r0, n, h1, raw + (int64_t)r0 * ncols, ncols, ncols, st, packed(r0));
     if (rb > TS_R) {
       const int r1 = r0 + TS_R;
       if (timer) timer->begin();
@@ -493,7 +557,7 @@ TrsmStats trsm_solve(const double* L, int n, double* raw, int64_t ncols, hipStre
                                     raw + (int64_t)r1 * ncols, ncols, st);
       if (timer) timer->end();
       ++z.update_launches;
-      trsv64_cols(L + (int64_t)r1 * n + r1, n, rb - TS_R, raw + (int64_t)r1 * ncols, ncols, ncols, st);
+      trsv64_cols(L + (int64_t)r1 * n + r1, n, rb - TS_R, raw + (int64_t)r1 * ncols, ncols, ncols, st, packed(r1));
     }
   }
   return z;
