@@ -107,12 +107,19 @@ __global__ void __launch_bounds__(256) kx_mixed_kernel(const float* __restrict__
 #pragma unroll
     for (int b = 0; b < NCB; ++b) acc[a][b] = v4f{0.f, 0.f, 0.f, 0.f};
 
-  for (int J = 0; J < nt; ++J) {
+  // tile J's operands are loaded into registers while the MFMAs of tile J - 1 run
+  const int half = tid >> 7, t = tid & 127;
+  const int I = I0 + half;
+  constexpr int NCH = NP * KT / 8;  // 8-element chunks of Ct's stage
+  constexpr int NCV = (NCH + 255) / 256;
+  float4 va0, va1;
+  W8<E> vb[NCV];
+  bool direct = false;
+  auto load = [&](int J) {
     // A: rows m0..m0+63 = row tiles I0 and I0 + 1, columns of tile J
-    float4 va0 = make_float4(0.f, 0.f, 0.f, 0.f), va1 = va0;
-    const int half = tid >> 7, t = tid & 127;
-    const int I = I0 + half;
-    const bool direct = I >= J;
+    va0 = make_float4(0.f, 0.f, 0.f, 0.f);
+    va1 = va0;
+    direct = I >= J;
     if (I < nt) {
       const float4* src = reinterpret_cast<const float4*>(
           row + (direct ? tile_base(I, J) : tile_base(J, I)) + (t >> 2) * 32 + (t & 3) * 8);
@@ -120,14 +127,16 @@ __global__ void __launch_bounds__(256) kx_mixed_kernel(const float* __restrict__
       va1 = src[1];
     }
     // B: Ct[:, 32J .. 32J+31], 8 elements per chunk
-    constexpr int NCH = NP * KT / 8;
-    W8<E> vb[(NCH + 255) / 256];
 #pragma unroll
-    for (int c = 0; c < (NCH + 255) / 256; ++c) {
+    for (int c = 0; c < NCV; ++c) {
       const int ch = tid + c * 256;
       if (ch < NCH) vb[c] = ld8(Ct + (int64_t)(ch >> 2) * nbfp + J * KT + (ch & 3) * 8);
     }
-    __syncthreads();
+  };
+
+  if (nt > 0) load(0);
+  for (int J = 0; J < nt; ++J) {
+    __syncthreads();  // the MFMAs of tile J - 1 have read their operands
     if (direct) {  // tile row (t >> 2) is mu, elements are nu
       const int r = half * 32 + (t >> 2), k0 = (t & 3) * 8;
       st8(&As[r][k0], pack8<E>(va0, va1));
@@ -143,11 +152,12 @@ __global__ void __launch_bounds__(256) kx_mixed_kernel(const float* __restrict__
       As[r0 + 7][k] = cvt<E>(va1.w);
     }
 #pragma unroll
-    for (int c = 0; c < (NCH + 255) / 256; ++c) {
+    for (int c = 0; c < NCV; ++c) {
       const int ch = tid + c * 256;
       if (ch < NCH) st8(&Bs[ch >> 2][(ch & 3) * 8], vb[c]);
     }
     __syncthreads();
+    if (J + 1 < nt) load(J + 1);
 #pragma unroll
     for (int kk = 0; kk < KT; kk += Tr::KM) {
 #pragma unroll
@@ -160,7 +170,6 @@ __global__ void __launch_bounds__(256) kx_mixed_kernel(const float* __restrict__
         }
       }
     }
-    __syncthreads();
   }
   // store: element (4 lk + r, li) of each 16x16 block
 #pragma unroll

@@ -89,12 +89,18 @@ def test_multi_class_molecule(dfx):
     assert abs(E - res.E) <= 1e-8
 
 
-@pytest.mark.parametrize("system", ["h4", "mixed"])
+@pytest.mark.parametrize("system", ["h4", "h4_odd", "mixed"])
 def test_purification_matches_eigensolver(dfx, h4_ref, system):
     """The occupied space from trace-correcting purification + Cholesky QR gives
-    the energy, density and final orbital energies of a full eigen-decomposition every iteration."""
+    the energy, density and final orbital energies of a full eigen-decomposition
+    every iteration.  h4 and mixed (even orbital counts) square P on the
+    symmetric product; h4_odd (one more s function, 25 orbitals) on the general
+    product, its odd row stride ruling out the symmetric kernel's vector loads."""
     if system == "h4":
         xyz, Z, sh, ax, nocc, _ = h4_ref
+    elif system == "h4_odd":
+        xyz, Z, sh, ax, nocc, _ = h4_ref
+        sh = list(sh) + [systems.shell(xyz[0], 0, [0.35])]
     else:
         xyz, Z, sh, ax = systems.mixed_molecule(seed=3, natom=6, lorb=2, laux=3)
         Z = np.array([1] * len(Z), np.int32)
