@@ -54,8 +54,8 @@ __global__ void __launch_bounds__(KX_T) kx64_kernel(const float* __restrict__ hi
   static_assert(NCL * 2 * KX_T == S64 * NP, "C stage must split evenly");
   static_assert(TPR * EP == 32 * S64, "A stage must split evenly");
   typedef float vfa __attribute__((ext_vector_type(EP)));
-  __shared__ double As[MR][S64 + PA];
-  __shared__ double Bs[S64][NP + PB];
+  __shared__ double As[2][MR][S64 + PA];
+  __shared__ double Bs[2][S64][NP + PB];
   const int Q = q0 + blockIdx.y;
   const int m0 = blockIdx.x * MR;
   const int I0 = m0 >> 5;
@@ -90,22 +90,25 @@ __global__ void __launch_bounds__(KX_T) kx64_kernel(const float* __restrict__ hi
 #pragma unroll
     for (int c = 0; c < NCL; ++c) cr[c] = cs[tid + KX_T * c];
   };
+  // stage s goes to LDS buffer s & 1: one barrier per stage, since stage s's
+  // buffer was last read in stage s - 2, which every wave finished before the
+  // barrier of stage s - 1
   auto store = [&](int stage) {
-    const int J = stage >> 1;
+    const int J = stage >> 1, b = stage & 1;
     if (I >= J) {
       const int r = half * 32 + t / DK, k0 = (t % DK) * EP;
 #pragma unroll
-      for (int e = 0; e < EP; ++e) As[r][k0 + e] = (double)ah[e] + (double)al[e];
+      for (int e = 0; e < EP; ++e) As[b][r][k0 + e] = (double)ah[e] + (double)al[e];
     } else {
       const int k = t / TM, r0 = half * 32 + (t % TM) * EP;
 #pragma unroll
-      for (int e = 0; e < EP; ++e) As[r0 + e][k] = (double)ah[e] + (double)al[e];
+      for (int e = 0; e < EP; ++e) As[b][r0 + e][k] = (double)ah[e] + (double)al[e];
     }
 #pragma unroll
     for (int c = 0; c < NCL; ++c) {
       const int e = 2 * (tid + KX_T * c);  // NP is even: a pair never straddles rows
-      Bs[e / NP][e % NP] = cr[c].x;
-      Bs[e / NP][e % NP + 1] = cr[c].y;
+      Bs[b][e / NP][e % NP] = cr[c].x;
+      Bs[b][e / NP][e % NP + 1] = cr[c].y;
     }
   };
 
@@ -115,25 +118,32 @@ __global__ void __launch_bounds__(KX_T) kx64_kernel(const float* __restrict__ hi
 #pragma unroll
     for (int b = 0; b < NCB; ++b) acc[a][b] = v4d{0.0, 0.0, 0.0, 0.0};
 
-  const int nstage = 2 * nt;
-  load(0);
-  for (int s = 0; s < nstage; ++s) {
-    __syncthreads();  // every wave is done with the previous stage
-    store(s);
-    __syncthreads();
-    if (s + 1 < nstage) load(s + 1);  // in flight during the MFMAs below
+  auto mma = [&](auto bufc) {
+    constexpr int BUF = decltype(bufc)::value;
 #pragma unroll
     for (int kk = 0; kk < S64; kk += 4) {
       double fa[WA];
 #pragma unroll
-      for (int a = 0; a < WA; ++a) fa[a] = As[wr + a * 16 + li][kk + lk];
+      for (int a = 0; a < WA; ++a) fa[a] = As[BUF][wr + a * 16 + li][kk + lk];
 #pragma unroll
       for (int b = 0; b < NCB; ++b) {
-        const double fb = Bs[kk + lk][wc + b * 16 + li];
+        const double fb = Bs[BUF][kk + lk][wc + b * 16 + li];
 #pragma unroll
         for (int a = 0; a < WA; ++a) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[a], fb, acc[a][b], 0, 0, 0);
       }
     }
+  };
+  const int nstage = 2 * nt;  // even: the stages pair up over the two buffers
+  load(0);
+  for (int s = 0; s < nstage; s += 2) {
+    store(s);
+    __syncthreads();
+    load(s + 1);  // in flight during the MFMAs below
+    mma(std::integral_constant<int, 0>{});
+    store(s + 1);
+    __syncthreads();
+    if (s + 2 < nstage) load(s + 2);
+    mma(std::integral_constant<int, 1>{});
   }
   // f64 MFMA output: element r of lane (li, lk) is row 4 r + lk, column li
 #pragma unroll
