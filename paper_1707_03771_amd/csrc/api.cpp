@@ -474,9 +474,12 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
     // The (class, l_C) launches write disjoint blocks of raw: they run on NSTR
     // streams forked from and joined back to st, most expensive first, each on
     // the least loaded stream, so that short launches fill the others' tails.
+    // Three: HIP's default of four hardware queues per process, with the
+    // caller's stream on one, leaves three; a fourth side stream shared a queue
+    // with another and ran serialised behind it.
     // The side streams and events belong to the calling thread on this device,
     // made on first use and kept until the process ends.
-    constexpr int NSTR = 4;
+    constexpr int NSTR = 3;
     struct ForkRes {
       hipStream_t s[NSTR] = {};
       hipEvent_t ev[NSTR + 1] = {};
@@ -524,7 +527,7 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
       }
     }
     std::sort(launches.begin(), launches.end(), [](const Launch& x, const Launch& y) { return x.cost > y.cost; });
-    double load[NSTR] = {0.0, 0.0, 0.0, 0.0};
+    double load[NSTR] = {};
     for (const Launch& L : launches) {
       const int cls = L.cls, lc = L.lc;
       const int k = (int)(std::min_element(load, load + NSTR) - load);
