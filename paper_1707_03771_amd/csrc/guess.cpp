@@ -4,7 +4,9 @@
 // a local frame; blocks are rotated back to the laboratory frame with
 // real-solid-harmonic rotation matrices and assembled.
 // The networks are trained on converged densities of the method itself.  The
-// MLP arithmetic runs in the FP32 kernels of mlp.hip; geometry work is host C++.
+// MLP arithmetic runs in the FP32 kernels of mlp.hip; geometry work (local
+// frames, descriptors, rotations) is host C++, spread over a few host threads,
+// one sample at a time each, so the results do not depend on the thread count.
 #include <algorithm>
 #include <array>
 #include <cmath>
@@ -15,6 +17,11 @@
 #include <memory>
 #include <numeric>
 #include <random>
+#include <atomic>
+#include <cstdlib>
+#include <exception>
+#include <mutex>
+#include <thread>
 
 #include "host.h"
 #include "mlp.h"
@@ -30,6 +37,45 @@ static int channel(int Z) {
   for (int i = 0; i < NCH; ++i)
     if (ELEM[i] == Z) return i;
   throw Error(DFX_EUNSUPPORTED, "learned guess: element Z = " + std::to_string(Z) + " has no descriptor channel");
+}
+
+// f(i) for i in [0, n) on up to 16 host threads (fewer if OMP_NUM_THREADS or the
+// hardware says so), in chunks taken in order; each i is independent.  The first
+// exception thrown is rethrown after all threads have joined.
+template <class Fn>
+static void parallel_for(size_t n, Fn f) {
+  unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  if (const char* e = std::getenv("OMP_NUM_THREADS")) {
+    const int v = std::atoi(e);
+    if (v >= 1) nt = std::min<unsigned>(nt, (unsigned)v);
+  }
+  const size_t chunk = 16;
+  if (nt <= 1 || n <= chunk) {
+    for (size_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  nt = (unsigned)std::min<size_t>(nt, (n + chunk - 1) / chunk);
+  std::atomic<size_t> next{0};
+  std::exception_ptr err;
+  std::mutex mu;
+  auto work = [&] {
+    try {
+      for (;;) {
+        const size_t i0 = next.fetch_add(chunk);
+        if (i0 >= n) break;
+        for (size_t i = i0; i < std::min(n, i0 + chunk); ++i) f(i);
+      }
+    } catch (...) {
+      std::lock_guard<std::mutex> lk(mu);
+      if (!err) err = std::current_exception();
+      next.store(n);
+    }
+  };
+  std::vector<std::thread> th;
+  for (unsigned t = 1; t < nt; ++t) th.emplace_back(work);
+  work();
+  for (auto& t : th) t.join();
+  if (err) std::rethrow_exception(err);
 }
 
 // ---- geometry helpers -------------------------------------------------------------------
@@ -427,15 +473,15 @@ static std::vector<std::vector<double>> predict_blocks(dfx_guess* g, const GeomV
     if (!T.normalised) throw Error(DFX_EINVAL, "learned guess: model is not trained");
     const int n = (int)kv.second.size();
     std::vector<float> X((size_t)n * T.nin);
-    std::vector<double> f(T.nin);
-    for (int k = 0; k < n; ++k) {
+    parallel_for((size_t)n, [&](size_t k) {
       const Sample& s = S[kv.second[k]];
+      std::vector<double> f(T.nin);
       double F[3][3];
       pair_features(v.r, v.Z, s.a, s.b, g->rc, g->rc_env, f.data(), F);
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) frames[kv.second[k]][i * 3 + j] = F[i][j];
-      for (int i = 0; i < T.nin; ++i) X[(size_t)k * T.nin + i] = (float)((f[i] - T.fmean[i]) / T.fstd[i]);
-    }
+      for (int i = 0; i < T.nin; ++i) X[k * T.nin + i] = (float)((f[i] - T.fmean[i]) / T.fstd[i]);
+    });
     ensure_device(T);
     DevMem Xd(sizeof(float) * X.size()), Yd(sizeof(float) * (size_t)n * T.nout);
     DevMem work(sizeof(float) * mlp_work_floats(T.widths, n));
@@ -501,14 +547,20 @@ void guess_predict_density(const dfx_guess* gc, const dfx_geom* geom, double* D,
   const auto blocks = predict_blocks(g, v, S, frames, st);
   const int n = v.nbf;
   std::fill(D, D + (size_t)n * n, 0.0);
-  std::vector<double> M;
-  for (size_t i = 0; i < S.size(); ++i) {
+  // lab-frame blocks in parallel, then assembled in sample order
+  std::vector<std::vector<double>> Ms(S.size());
+  parallel_for(S.size(), [&](size_t i) {
     const int a = S[i].a, b = S[i].b;
     double F[3][3];
     for (int p = 0; p < 3; ++p)
       for (int q = 0; q < 3; ++q) F[p][q] = frames[i][p * 3 + q];
     const int na = atom_nbf(g, v.Z[a]), nb = atom_nbf(g, v.Z[b]);
-    rotate_out(atom_rotation(g, v.Z[a], F), na, blocks[i], atom_rotation(g, v.Z[b], F), nb, M);
+    rotate_out(atom_rotation(g, v.Z[a], F), na, blocks[i], atom_rotation(g, v.Z[b], F), nb, Ms[i]);
+  });
+  for (size_t i = 0; i < S.size(); ++i) {
+    const int a = S[i].a, b = S[i].b;
+    const int na = atom_nbf(g, v.Z[a]), nb = atom_nbf(g, v.Z[b]);
+    const std::vector<double>& M = Ms[i];
     // homonuclear pairs appear in both directions: each contributes half
     const double w = (a != b && v.Z[a] == v.Z[b]) ? 0.5 : 1.0;
     for (int p = 0; p < na; ++p)
@@ -563,31 +615,39 @@ int dfx_guess_add(dfx_guess* g, const dfx_geom* geom, const double* D) {
     const GeomView v = view(g, geom);
     const std::vector<Sample> S = samples_of(g, v, true);
     const int n = v.nbf;
-    std::vector<double> f;
-    for (const Sample& s : S) {
-      GuessType& T = g->types[s.type];
-      if (T.normalised) throw Error(DFX_EINVAL, "dfx_guess_add: model already trained");
-      f.resize(T.nin);
+    for (const Sample& s : S)
+      if (g->types[s.type].normalised) throw Error(DFX_EINVAL, "dfx_guess_add: model already trained");
+    // descriptors and local blocks per sample in parallel, stored in sample order
+    std::vector<std::vector<double>> fs(S.size()), Ps(S.size());
+    parallel_for(S.size(), [&](size_t i) {
+      const Sample& s = S[i];
+      std::vector<double>& f = fs[i];
+      f.resize(g->types[s.type].nin);
       double F[3][3];
       pair_features(v.r, v.Z, s.a, s.b, g->rc, g->rc_env, f.data(), F);
       const int na = atom_nbf(g, v.Z[s.a]), nb = atom_nbf(g, v.Z[s.b]);
       const auto Ua = atom_rotation(g, v.Z[s.a], F), Ub = atom_rotation(g, v.Z[s.b], F);
       // local block U_a^T D^{ab} U_b
-      std::vector<double> t((size_t)na * nb, 0.0), P((size_t)na * nb, 0.0);
+      std::vector<double> t((size_t)na * nb, 0.0);
+      std::vector<double>& P = Ps[i];
+      P.assign((size_t)na * nb, 0.0);
       for (int k = 0; k < na; ++k)
         for (int j = 0; j < nb; ++j) {
           double x = 0.0;
           for (int q = 0; q < nb; ++q) x += D[(size_t)(v.off[s.a] + k) * n + v.off[s.b] + q] * Ub[(size_t)q * nb + j];
           t[(size_t)k * nb + j] = x;
         }
-      for (int i = 0; i < na; ++i)
+      for (int ii = 0; ii < na; ++ii)
         for (int j = 0; j < nb; ++j) {
           double x = 0.0;
-          for (int k = 0; k < na; ++k) x += Ua[(size_t)k * na + i] * t[(size_t)k * nb + j];
-          P[(size_t)i * nb + j] = x;
+          for (int k = 0; k < na; ++k) x += Ua[(size_t)k * na + ii] * t[(size_t)k * nb + j];
+          P[(size_t)ii * nb + j] = x;
         }
-      T.X.insert(T.X.end(), f.begin(), f.end());
-      T.T.insert(T.T.end(), P.begin(), P.end());
+    });
+    for (size_t i = 0; i < S.size(); ++i) {
+      GuessType& T = g->types[S[i].type];
+      T.X.insert(T.X.end(), fs[i].begin(), fs[i].end());
+      T.T.insert(T.T.end(), Ps[i].begin(), Ps[i].end());
       ++T.nsamp;
     }
   });
