@@ -137,3 +137,24 @@ def test_import_save_load_round_trip(tmp_path):
     got = m2.export(0, widths)
     for x, y in zip(got, (th, fm, fs, tm, ts)):
         assert np.array_equal(x, y)
+
+
+def test_stored_samples_do_not_depend_on_thread_count(monkeypatch):
+    """The training samples are computed on a pool of host threads, one sample
+    at a time each and stored in sample order: one thread and eight store the
+    same descriptors and blocks, bit for bit, in the same order."""
+    elems, xyz = W.water_cluster(side=3, seed=5)
+    Z = W.charges(elems)
+    _, n = L.offsets(Z, WATER)
+    A = np.random.default_rng(2).normal(size=(n, n))
+    P = A + A.T
+    got = []
+    for nt in ("1", "8"):
+        monkeypatch.setenv("OMP_NUM_THREADS", nt)
+        m = model()
+        m.add(xyz, Z, P)
+        got.append([m.samples(t) for t in range(len(m.types()))])
+    assert len(got[0]) == len(got[1])
+    for (X1, T1), (X8, T8) in zip(*got):
+        assert X1.shape[0] > 16
+        assert np.array_equal(X1, X8) and np.array_equal(T1, T8)
