@@ -451,9 +451,9 @@ std::unique_ptr<dfx_B> dfx::build_B(HostShells bas, HostShells auxs, double tau_
         }
     }
 
-    // -- raw (mu nu|P), aux-major, packed pair columns (screened triplets stay zero)
+    // -- raw (mu nu|P), aux-major, packed pair columns; every element is written
+    // by the class launches below (screened triplets as zeros), so no clearing
     B->raw.alloc(sizeof(double) * (size_t)naux * B->ncols_p);
-    DFX_HIP(hipMemsetAsync(B->raw.p, 0, B->raw.n, st));
     std::vector<DevMem> qcl_d(5);
     for (int l = 0; l <= 4; ++l) {
       std::vector<double> q;

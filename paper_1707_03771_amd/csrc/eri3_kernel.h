@@ -105,7 +105,9 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_kernel(const Eri3Args a) {
   const int c0 = blockIdx.y * a.kchunk;
   const int c1 = min(c0 + a.kchunk, a.nk);
   for (int ci = c0; ci < c1; ++ci) {
-    if (MODE == STORE_CLASS && !(qab * a.kq[ci] >= a.tau)) continue;  // screened: stays zero
+    // a screened triplet stores its block of zeros (the raw tensor is not cleared
+    // beforehand: every one of its elements is written by exactly one lane)
+    const bool keep = MODE != STORE_CLASS || qab * a.kq[ci] >= a.tau;
     const int kc = a.kl[ci];
     const double C0 = a.K.ctr[3 * kc], C1 = a.K.ctr[3 * kc + 1], C2 = a.K.ctr[3 * kc + 2];
     const int nkp = a.K.nprim[kc], kpo = a.K.poff[kc];
@@ -113,7 +115,8 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_kernel(const Eri3Args a) {
     double acc[NA][NB][GN];
     sfor<NA>([&](auto i) { sfor<NB>([&](auto j) { sfor<GN>([&](auto g) { acc[i][j][g] = 0.0; }); }); });
 
-    for (int ip = 0; ip < nfp; ++ip) {
+    const int nfp_keep = keep ? nfp : 0;
+    for (int ip = 0; ip < nfp_keep; ++ip) {
       const double al = a.F.exps[fpo + ip], ca = a.F.coef[fpo + ip];
       for (int jp = 0; jp < nsp; ++jp) {
         const double be = UNITB ? 0.0 : a.S.exps[spo + jp];
