@@ -294,8 +294,8 @@ def eval_alkane(dfx):
     BF16 -> FP32 -> FP64), each |dE| against the oracle's stored energy."""
     elems, xyz, sh, ax = W.workload("alkane", seed=0)
     Z = W.charges(elems)
-    gold = os.path.join(ROOT, "tests", "golden", "alkane_df_rhf.json")
-    E_or = json.load(open(gold))["E"] if os.path.exists(gold) else None
+    gold = os.path.join(ROOT, "tests", "golden", "df_rhf_floors.json")
+    E_or = json.load(open(gold))["alkane"]["E"] if os.path.exists(gold) else None
     conv = dict(conv_dE=1e-9, conv_err=1e-7)
     dfx.scf(xyz, Z, sh, ax, want_c=False, **conv)                                     # warm-up
     runs = {}
@@ -322,6 +322,9 @@ def eval_mp2(dfx, workloads=("alkane", "water4")):
         elems, xyz, sh, ax = W.workload(wl, seed=0) if wl == "alkane" else W.workload(wl)
         Z = W.charges(elems)
         E, C, eps, info = dfx.scf(xyz, Z, sh, ax, conv_dE=1e-9, conv_err=1e-7)
+        # the SCF's cached workspace back to the device: B and MP2's work need it
+        dfx.release_scf_workspace()
+        torch.cuda.empty_cache()
         nocc, nbf, naux = info["nocc"], info["nbf"], info["naux"]
         nmo = nbf - info["ndropped"]
         nfrozen = sum(1 for z in Z if z > 2)  # 1s cores of C and O
@@ -385,11 +388,15 @@ def eval_grad(dfx, workloads=("alkane", "water4")):
     """DF-RHF analytic nuclear gradient (FP64) after a converged plain FP64 SCF
     at full size: wall and GPU times of its phases, the translational and
     torque sum rules, and the largest component."""
+    import torch
     rows = []
     for wl in workloads:
         elems, xyz, sh, ax = W.workload(wl, seed=0) if wl == "alkane" else W.workload(wl)
         Z = W.charges(elems)
         E, C, eps, info = dfx.scf(xyz, Z, sh, ax, conv_dE=1e-9, conv_err=1e-7)
+        # the SCF's cached workspace back to the device for the gradient's own
+        dfx.release_scf_workspace()
+        torch.cuda.empty_cache()
         nocc = info["nocc"]
         dfx.rhf_grad(xyz, Z, sh, ax, C[:, :nocc], eps[:nocc])                     # warm-up
         t0 = time.perf_counter()
