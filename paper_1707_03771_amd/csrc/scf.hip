@@ -1337,20 +1337,58 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
       Fh[k].alloc(8 * n2);
       Eh[k].alloc(8 * (size_t)m * m);
     }
-    // occupied orbitals of spin s2 from a Fock-like matrix (eigen-decomposition of X^T F X)
+    // occupied orbitals of spin s2 from a Fock-like matrix F: the nocc lowest levels
+    // of F' = X^T F X (kept in Fq[s2]).  UHF takes them by purification, as RHF
+    // does, once a previous occupied space Y of that spin exists (every
+    // iteration after the first); otherwise, or if it fails, by the full
+    // eigen-decomposition, which also gives the orbitals and levels C, eps.
+    DevMem Fq[2], Yo[2], Zo, Go, lohi;
+    bool have_y[2] = {false, false}, cm_valid[2] = {false, false};
+    int n_purified = 0, n_eigh = 0, purify_steps = 0;
+    if (!restricted) {
+      const int nmax = std::max(1, std::max(na, nb));
+      for (int s2 = 0; s2 < 2; ++s2) {
+        Fq[s2].alloc(8 * (size_t)m * m);
+        Yo[s2].alloc(8 * (size_t)m * std::max(1, nocc_s[s2]));
+      }
+      Zo.alloc(8 * (size_t)m * nmax);
+      Go.alloc(8 * (size_t)nmax * nmax);
+      lohi.alloc(16 * (size_t)m);
+    }
     auto diag = [&](int s2, const double* Fx) {
+      const int no = nocc_s[s2];
       S.gemm(m, n, n, X.as<double>(), m, true, Fx, n, false, t1.as<double>(), n);
-      S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Fp.as<double>(), m);
+      S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Fq[s2].as<double>(), m);
+      if (no == 0) {
+        DFX_HIP(hipMemsetAsync(D[s2].p, 0, 8 * n2, st));
+        cm_valid[s2] = false;
+        return;
+      }
+      if (o.purify && have_y[s2]) {
+        int steps = 0;
+        const char* why = "";
+        S.nocc = no;
+        if (S.purify_occ(Fq[s2].as<double>(), t1.as<double>(), t2.as<double>(), Yo[s2].as<double>(),
+                         Zo.as<double>(), Go.as<double>(), lohi.as<double>(), steps, why)) {
+          S.gemm(n, no, m, X.as<double>(), m, false, Yo[s2].as<double>(), no, false, Cocc[s2].as<double>(), no);
+          S.gemm(n, n, no, Cocc[s2].as<double>(), no, false, Cocc[s2].as<double>(), no, true, D[s2].as<double>(), n);
+          cm_valid[s2] = false;
+          ++n_purified;
+          purify_steps += steps;
+          return;
+        }
+        if (o.verbose) std::fprintf(stderr, "%s purification failed (%s), eigen-decomposition\n", fn.c_str(), why);
+      }
+      DFX_HIP(hipMemcpyAsync(Fp.p, Fq[s2].p, 8 * (size_t)m * m, hipMemcpyDeviceToDevice, st));
       S.syevd(Fp.as<double>(), m, eps[s2].as<double>());
       S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm[s2].as<double>(), m);
-      if (nocc_s[s2] > 0) {
-        hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc_s[s2])), dim3(256), 0, st,
-                           Cm[s2].as<double>(), m, n, nocc_s[s2], Cocc[s2].as<double>(), nocc_s[s2]);
-        S.gemm(n, n, nocc_s[s2], Cocc[s2].as<double>(), nocc_s[s2], false, Cocc[s2].as<double>(), nocc_s[s2], true,
-               D[s2].as<double>(), n);
-      } else {
-        DFX_HIP(hipMemsetAsync(D[s2].p, 0, 8 * n2, st));
-      }
+      hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * no)), dim3(256), 0, st, Cm[s2].as<double>(), m, n,
+                         no, Cocc[s2].as<double>(), no);
+      hipLaunchKernelGGL(rows_to_cols_kernel, dim3(nblk((int64_t)m * no)), dim3(256), 0, st, Fp.as<double>(), m, 0, no,
+                         Yo[s2].as<double>());
+      S.gemm(n, n, no, Cocc[s2].as<double>(), no, false, Cocc[s2].as<double>(), no, true, D[s2].as<double>(), n);
+      have_y[s2] = cm_valid[s2] = true;
+      ++n_eigh;
     };
     // ROHF: eigenvectors of an m x m matrix of the orthonormal basis; rows of Fp
     // (the eigenvectors) are kept as the current orbitals V, C = X V^T
@@ -1528,6 +1566,15 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
     DFX_HIP(hipStreamSynchronize(st));
     const auto t2c = clk::now();
     *E_out = E;
+    // UHF spins whose last occupied space came from purification: their orbitals
+    // and levels from one eigen-decomposition of the same F'
+    for (int s2 = 0; s2 < 2 && !restricted && (C_out || eps_out); ++s2)
+      if (!cm_valid[s2]) {
+        DFX_HIP(hipMemcpyAsync(Fp.p, Fq[s2].p, 8 * (size_t)m * m, hipMemcpyDeviceToDevice, st));
+        S.syevd(Fp.as<double>(), m, eps[s2].as<double>());
+        S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm[s2].as<double>(), m);
+        DFX_HIP(hipStreamSynchronize(st));
+      }
     // the orbitals whose densities gave E: [nbf][nbf] per set, the first m columns
     // X V^T and the rest zero; levels [nbf], zero beyond m
     const int nset = restricted ? 1 : 2;
@@ -1547,6 +1594,9 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
     }
     inf.niter = std::min(it, o.max_iter);
     inf.converged = converged ? 1 : 0;
+    inf.n_purified = n_purified;
+    inf.n_eigh = n_eigh;
+    inf.purify_steps = purify_steps;
     inf.ndropped = n - m;
     inf.nbf = n;
     inf.naux = B->naux;

@@ -128,3 +128,24 @@ def test_h2_triplet_single_determinant(dfx, method):
     Ed = sum(h[i, i] for i in range(2)) + 0.5 * sum(Gm[i, i, j, j] - Gm[i, j, j, i] for i in range(2)
                                                     for j in range(2))
     assert abs(E - (Ed + 1.0 / g["R_bohr"])) <= 1e-8   # exact fit up to kappa u, kappa = 2.8e7
+
+
+@pytest.mark.parametrize("charge,mult", [(1, 2), (0, 3)])
+def test_uhf_purification_matches_eigensolver(dfx, charge, mult):
+    """From the second iteration on, each spin's occupied space comes from
+    trace-correcting purification (purify = 1, the default): the energy, the spin
+    densities and the occupied levels equal those of a run with an
+    eigen-decomposition of both Fock matrices every iteration."""
+    xyz, Z, sh, ax = _mixed()
+    na, nb = _spins(Z, charge, mult)
+    kw = dict(conv_dE=1e-10, conv_err=1e-8, max_iter=200)
+    E0, C0, e0, i0 = dfx.uhf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, purify=0, **kw)
+    E1, C1, e1, i1 = dfx.uhf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, purify=1, **kw)
+    assert i0["converged"] and i1["converged"]
+    assert i0["n_purified"] == 0 and i1["n_purified"] >= 2
+    assert abs(E1 - E0) <= 1e-10
+    for s_, n_ in enumerate((na, nb)):
+        D0, D1 = C0[s_][:, :n_] @ C0[s_][:, :n_].T, C1[s_][:, :n_] @ C1[s_][:, :n_].T
+        assert np.abs(D1 - D0).max() <= 1e-7 * max(1.0, np.abs(D0).max())
+        assert np.abs(e1[s_][:n_] - e0[s_][:n_]).max(initial=0.0) <= 1e-7
+    print(f"q={charge} 2S+1={mult}: {i1['n_purified']} purified spin updates, {i1['n_eigh']} eigen-decompositions")
