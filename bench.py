@@ -215,7 +215,9 @@ def train_guess(dfx, n27=8, n8=16, epochs=80, batch=128, seed=5, sigma=0.04):
 def profile_jk(dfx, torch, sh, ax, nocc, prec):
     """One J/K build on the workload's B with a seeded orthonormal C_occ, then a
     copy of 2^28 floats (1 GiB read, 1 GiB written) whose counters calibrate
-    the per-dispatch HBM byte counts."""
+    the per-dispatch HBM byte counts.  B is built twice: the first build loads
+    the integral kernels' code objects, the second is the one to read."""
+    dfx.eri3(sh, ax).free()
     B = dfx.eri3(sh, ax)
     C = torch.tensor(W.random_orthonormal(B.nbf, nocc, seed=1), device="cuda")
     J, K = dfx.jk(B, C, precision=prec)

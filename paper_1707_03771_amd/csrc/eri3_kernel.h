@@ -80,15 +80,41 @@ __device__ __forceinline__ void rys_2d(double C00, double D00, double B10, doubl
   }
 }
 
+// LDS written by some lanes of a wave and read by others: LDS operations of one
+// wave complete in issue order, so only the compiler has to keep them in place
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <int LA, int LB, int LC, int M0, int GN, bool UNITB, int MODE>
 __global__ void __launch_bounds__(ERI_THREADS) eri3_kernel(const Eri3Args a) {
   constexpr int NR = (LA + LB + LC) / 2 + 1;
   constexpr int NA = ncart(LA), NB = ncart(LB), NC = ncart(LC);
   constexpr int SA = 2 * LA + 1, SB = UNITB ? 1 : 2 * LB + 1;
+  // STORE_CLASS: for one ket function a wave's results are one contiguous run
+  // of 64 SA SB columns, pair by pair.  Where the workgroup's copy of that run
+  // and the Rys table fit in a quarter of the CU's 160 KB of LDS (so that LDS
+  // never holds the class below two waves per SIMD) the run goes out through
+  // LDS, consecutive lanes storing consecutive columns; otherwise each lane
+  // stores its own pair's block.
+  constexpr int SASB = SA * SB;
+  static_assert(MODE == STORE_CLASS || UNITB, "dense stores are for the two-centre metric");
+  constexpr bool STAGE =
+      MODE == STORE_CLASS && (ERI_THREADS * SASB + rys_dev_size(NR)) * (int)sizeof(double) <= 40 * 1024;
+  constexpr int NSTG = STAGE ? 64 * SASB : 1;
   __shared__ double tab[rys_dev_size(NR)];
+  __shared__ double stg[ERI_THREADS / 64][NSTG];
   rys_stage<NR>(tab, a.rys);
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= a.npairs) return;
+  const int lane = threadIdx.x & 63;
+  const int p0 = blockIdx.x * blockDim.x + (threadIdx.x - lane);  // first pair of the wave
+  if (p0 >= a.npairs) return;  // the whole wave
+  // lanes past the end of the class list evaluate nothing; in STORE_CLASS they
+  // stay for the stores, which they share with the other lanes
+  const bool live = p0 + lane < a.npairs;
+  if (MODE != STORE_CLASS && !live) return;
+  const int p = live ? p0 + lane : a.npairs - 1;
   const int f = a.pf[p];
   const int s = UNITB ? f : a.ps[p];
   const double A0 = a.F.ctr[3 * f], A1 = a.F.ctr[3 * f + 1], A2 = a.F.ctr[3 * f + 2];
@@ -107,7 +133,7 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_kernel(const Eri3Args a) {
   for (int ci = c0; ci < c1; ++ci) {
     // a screened triplet stores its block of zeros (the raw tensor is not cleared
     // beforehand: every one of its elements is written by exactly one lane)
-    const bool keep = MODE != STORE_CLASS || qab * a.kq[ci] >= a.tau;
+    const bool keep = MODE != STORE_CLASS || (live && qab * a.kq[ci] >= a.tau);
     const int kc = a.kl[ci];
     const double C0 = a.K.ctr[3 * kc], C1 = a.K.ctr[3 * kc + 1], C2 = a.K.ctr[3 * kc + 2];
     const int nkp = a.K.nprim[kc], kpo = a.K.poff[kc];
@@ -191,23 +217,51 @@ __global__ void __launch_bounds__(ERI_THREADS) eri3_kernel(const Eri3Args a) {
       });
       return v;
     };
-    // STORE_CLASS: the lanes of a wave hold consecutive pairs of the class, so
-    // the SA SB stores of one ket function fill one contiguous block of columns
-    sfor<SA>([&](auto mai) {
-      constexpr int ma = decltype(mai)::value;
-      sfor<SB>([&](auto mbi) {
-        constexpr int mb = decltype(mbi)::value;
+    if constexpr (STAGE) {
+      // the lanes of a wave hold consecutive pairs of the class: per ket
+      // function, 64 SA SB consecutive columns from the wave's first pair on
+      double* const sw = stg[threadIdx.x >> 6];
+      const int nval = min(64, a.npairs - p0) * SASB;
+      sfor<GN>([&](auto ig) {
+        constexpr int g = decltype(ig)::value;
+        sfor<SA>([&](auto mai) {
+          constexpr int ma = decltype(mai)::value;
+          sfor<SB>([&](auto mbi) {
+            constexpr int mb = decltype(mbi)::value;
+            sw[lane * SASB + ma * SB + mb] = bra(mai, mbi, ig);
+          });
+        });
+        wave_lds_sync();
+        double* const o = out + (int64_t)(kfo + M0 + g) * a.ld + a.cbase + (int64_t)p0 * SASB;
+        // a loop rather than an unrolled sequence: unrolled, the compiler
+        // keeps every store's lane mask live across the ket loop
+#pragma unroll 1
+        for (int e = lane; e < nval; e += 64) o[e] = sw[e];
+        wave_lds_sync();
+      });
+    } else if constexpr (MODE == STORE_CLASS) {
+      if (live) {
+        sfor<SA>([&](auto mai) {
+          constexpr int ma = decltype(mai)::value;
+          sfor<SB>([&](auto mbi) {
+            constexpr int mb = decltype(mbi)::value;
+            sfor<GN>([&](auto ig) {
+              constexpr int g = decltype(ig)::value;
+              out[(int64_t)(kfo + M0 + g) * a.ld + a.cbase + (int64_t)p * SASB + (ma * SB + mb)] =
+                  bra(mai, mbi, ig);
+            });
+          });
+        });
+      }
+    } else {
+      sfor<SA>([&](auto mai) {
+        constexpr int ma = decltype(mai)::value;
         sfor<GN>([&](auto ig) {
           constexpr int g = decltype(ig)::value;
-          const double v = bra(mai, mbi, ig);
-          if constexpr (MODE == STORE_CLASS) {
-            out[(int64_t)(kfo + M0 + g) * a.ld + a.cbase + (int64_t)p * (SA * SB) + (ma * SB + mb)] = v;
-          } else {
-            out[(int64_t)(foffF + ma) * a.ld + kfo + M0 + g] = v;
-          }
+          out[(int64_t)(foffF + ma) * a.ld + kfo + M0 + g] = bra(mai, std::integral_constant<int, 0>{}, ig);
         });
       });
-    });
+    }
   }
 }
 
