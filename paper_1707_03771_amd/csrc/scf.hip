@@ -40,16 +40,31 @@ __global__ void uhf_fock_kernel(const double* h, const double* J, const double* 
   if (i < n2) F[i] = h[i] + J[i] - K[i];
 }
 
-// Roothaan's effective Fock matrix in the orbital basis from F_alpha and F_beta
-// there: core (k < nb), open (nb <= k < na), virtual; core-open blocks F_beta,
-// open-virtual F_alpha, all others (F_alpha + F_beta) / 2
-__global__ void rohf_blocks_kernel(const double* Fa, const double* Fb, int m, int nb, int na, double* R) {
+// Roothaan's effective Fock matrix in the orthonormal basis from F_alpha',
+// F_beta' and the projectors P_a, P_b onto the alpha and beta occupied spaces
+// (core P_c = P_b, open P_o = P_a - P_b, virtual P_v = I - P_a): core-open
+// blocks take F_beta, open-virtual F_alpha, all others A = (F_alpha + F_beta) / 2.
+// With Delta = (F_alpha - F_beta) / 2 that is R = A + Z + Z^T, Z = P_o Delta (P_v - P_c).
+// Step 1: Delta and P_o.
+__global__ void rohf_delta_kernel(const double* Fa, const double* Fb, const double* Pa, const double* Pb,
+                                  double* Dl, double* Po, int64_t m2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= m2) return;
+  Dl[i] = 0.5 * (Fa[i] - Fb[i]);
+  Po[i] = Pa[i] - Pb[i];
+}
+// Step 2: P_v - P_c = I - P_a - P_b.
+__global__ void rohf_vc_kernel(const double* Pa, const double* Pb, double* Q, int m) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)m * m) return;
+  Q[i] = (i / m == i % m ? 1.0 : 0.0) - Pa[i] - Pb[i];
+}
+// Step 3: R = A + Z + Z^T.
+__global__ void rohf_feff_kernel(const double* Fa, const double* Fb, const double* Z, double* R, int m) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= (int64_t)m * m) return;
   const int r = (int)(i / m), c = (int)(i % m);
-  const int sr = r < nb ? 0 : (r < na ? 1 : 2), sc = c < nb ? 0 : (c < na ? 1 : 2);
-  const int lo = sr < sc ? sr : sc, hi = sr < sc ? sc : sr;
-  R[i] = (lo == 0 && hi == 1) ? Fb[i] : (lo == 1 && hi == 2) ? Fa[i] : 0.5 * (Fa[i] + Fb[i]);
+  R[i] = 0.5 * (Fa[i] + Fb[i]) + Z[i] + Z[(int64_t)c * m + r];
 }
 
 // F += b (S - T): the level shift of one UHF spin, T = S D_s S
@@ -1338,17 +1353,18 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
       Eh[k].alloc(8 * (size_t)m * m);
     }
     // occupied orbitals of spin s2 from a Fock-like matrix F: the nocc lowest levels
-    // of F' = X^T F X (kept in Fq[s2]).  UHF takes them by purification, as RHF
-    // does, once a previous occupied space Y of that spin exists (every
-    // iteration after the first); otherwise, or if it fails, by the full
-    // eigen-decomposition, which also gives the orbitals and levels C, eps.
+    // of F' = X^T F X (kept in Fq[s2]; for ROHF the one effective matrix, both
+    // counts).  They come by purification, as for RHF, once a previous occupied
+    // space Y of that spin exists (every iteration after the first); otherwise,
+    // or if it fails, by the full eigen-decomposition, which also gives the
+    // orbitals and levels C, eps.
     DevMem Fq[2], Yo[2], Zo, Go, lohi;
     bool have_y[2] = {false, false}, cm_valid[2] = {false, false};
     int n_purified = 0, n_eigh = 0, purify_steps = 0;
-    if (!restricted) {
+    {
       const int nmax = std::max(1, std::max(na, nb));
       for (int s2 = 0; s2 < 2; ++s2) {
-        Fq[s2].alloc(8 * (size_t)m * m);
+        if (!restricted || s2 == 0) Fq[s2].alloc(8 * (size_t)m * m);
         Yo[s2].alloc(8 * (size_t)m * std::max(1, nocc_s[s2]));
       }
       Zo.alloc(8 * (size_t)m * nmax);
@@ -1390,36 +1406,71 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
       have_y[s2] = cm_valid[s2] = true;
       ++n_eigh;
     };
-    // ROHF: eigenvectors of an m x m matrix of the orthonormal basis; rows of Fp
-    // (the eigenvectors) are kept as the current orbitals V, C = X V^T
+    // ROHF: the occupied spaces of one m x m matrix of the orthonormal basis, the
+    // na and nb lowest levels, kept as the projectors P_a, P_b (m x m); C = X V^T
+    // when the matrix was diagonalised
     const int64_t m2 = (int64_t)m * m;
-    DevMem Fo[2], tm, Rm, Feff, Dp;
+    DevMem Fo[2], tm, Rm, Feff, Dp, Pp[2];
     if (restricted) {
       for (auto& f : Fo) f.alloc(8 * m2);
+      for (auto& f : Pp) f.alloc(8 * m2);
       tm.alloc(8 * m2);
       Rm.alloc(8 * m2);
       Feff.alloc(8 * m2);
       Dp.alloc(8 * m2);
     }
-    auto diag_orth = [&](const double* Fm) {
-      DFX_HIP(hipMemcpyAsync(Fp.p, Fm, 8 * m2, hipMemcpyDeviceToDevice, st));
+    // densities, occupied orbitals and projectors from the columns Yo[s2]
+    auto from_y = [&]() {
+      for (int s2 = 0; s2 < 2; ++s2) {
+        const int no = nocc_s[s2];
+        if (no == 0) {
+          DFX_HIP(hipMemsetAsync(D[s2].p, 0, 8 * n2, st));
+          DFX_HIP(hipMemsetAsync(Pp[s2].p, 0, 8 * m2, st));
+          continue;
+        }
+        S.gemm(n, no, m, X.as<double>(), m, false, Yo[s2].as<double>(), no, false, Cocc[s2].as<double>(), no);
+        S.gemm(n, n, no, Cocc[s2].as<double>(), no, false, Cocc[s2].as<double>(), no, true, D[s2].as<double>(), n);
+        S.gemm(m, m, no, Yo[s2].as<double>(), no, false, Yo[s2].as<double>(), no, true, Pp[s2].as<double>(), m);
+      }
+    };
+    auto update_orth = [&](const double* Fm) {
+      DFX_HIP(hipMemcpyAsync(Fq[0].p, Fm, 8 * m2, hipMemcpyDeviceToDevice, st));
+      if (o.purify && have_y[0]) {
+        bool ok = true;
+        int steps_all = 0;
+        const char* why = "";
+        for (int s2 = 0; s2 < 2 && ok; ++s2) {
+          if (nocc_s[s2] == 0) continue;
+          int steps = 0;
+          S.nocc = nocc_s[s2];
+          ok = S.purify_occ(Fq[0].as<double>(), t1.as<double>(), t2.as<double>(), Yo[s2].as<double>(),
+                            Zo.as<double>(), Go.as<double>(), lohi.as<double>(), steps, why);
+          steps_all += steps;
+        }
+        if (ok) {
+          from_y();
+          cm_valid[0] = false;
+          ++n_purified;
+          purify_steps += steps_all;
+          return;
+        }
+        if (o.verbose) std::fprintf(stderr, "%s purification failed (%s), eigen-decomposition\n", fn.c_str(), why);
+      }
+      DFX_HIP(hipMemcpyAsync(Fp.p, Fq[0].p, 8 * m2, hipMemcpyDeviceToDevice, st));
       S.syevd(Fp.as<double>(), m, eps[0].as<double>());
       S.gemm(n, m, m, X.as<double>(), m, false, Fp.as<double>(), m, true, Cm[0].as<double>(), m);
-      for (int s2 = 0; s2 < 2; ++s2) {
-        if (nocc_s[s2] > 0) {
-          hipLaunchKernelGGL(copy_cols_kernel, dim3(nblk((int64_t)n * nocc_s[s2])), dim3(256), 0, st,
-                             Cm[0].as<double>(), m, n, nocc_s[s2], Cocc[s2].as<double>(), nocc_s[s2]);
-          S.gemm(n, n, nocc_s[s2], Cocc[s2].as<double>(), nocc_s[s2], false, Cocc[s2].as<double>(), nocc_s[s2],
-                 true, D[s2].as<double>(), n);
-        } else {
-          DFX_HIP(hipMemsetAsync(D[s2].p, 0, 8 * n2, st));
-        }
-      }
+      for (int s2 = 0; s2 < 2; ++s2)
+        if (nocc_s[s2] > 0)
+          hipLaunchKernelGGL(rows_to_cols_kernel, dim3(nblk((int64_t)m * nocc_s[s2])), dim3(256), 0, st,
+                             Fp.as<double>(), m, 0, nocc_s[s2], Yo[s2].as<double>());
+      from_y();
+      have_y[0] = cm_valid[0] = true;
+      ++n_eigh;
     };
     if (restricted) {
       S.gemm(m, n, n, X.as<double>(), m, true, h.as<double>(), n, false, t1.as<double>(), n);
       S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Feff.as<double>(), m);
-      diag_orth(Feff.as<double>());
+      update_orth(Feff.as<double>());
     } else {
       diag(0, h.as<double>());
       diag(1, h.as<double>());
@@ -1453,21 +1504,23 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
       E = 0.5 * sum + Enuc;
       emax = 0.0;
       if (restricted) {
-        // F_s' = V X^T F_s X V^T (orbital basis), R by blocks, F_eff' = V^T R V
+        // F_s' = X^T F_s X; F_eff' = A + Z + Z^T with Z = P_o Delta (P_v - P_c)
         for (int s2 = 0; s2 < 2; ++s2) {
           S.gemm(m, n, n, X.as<double>(), m, true, F[s2].as<double>(), n, false, t1.as<double>(), n);
           S.gemm(m, m, n, t1.as<double>(), n, false, X.as<double>(), m, false, Fo[s2].as<double>(), m);
-          S.gemm(m, m, m, Fp.as<double>(), m, false, Fo[s2].as<double>(), m, false, tm.as<double>(), m);
-          S.gemm(m, m, m, tm.as<double>(), m, false, Fp.as<double>(), m, true, Fo[s2].as<double>(), m);
         }
-        hipLaunchKernelGGL(rohf_blocks_kernel, dim3(nblk(m2)), dim3(256), 0, st, Fo[0].as<double>(),
-                           Fo[1].as<double>(), m, nb, na, Rm.as<double>());
-        S.gemm(m, m, m, Fp.as<double>(), m, true, Rm.as<double>(), m, false, tm.as<double>(), m);
-        S.gemm(m, m, m, tm.as<double>(), m, false, Fp.as<double>(), m, false, Feff.as<double>(), m);
-        // D' = V^T diag(occupations) V = V_a^T V_a + V_b^T V_b; e = F_eff' D' - D' F_eff'
-        S.gemm(m, m, na, Fp.as<double>(), m, true, Fp.as<double>(), m, false, Dp.as<double>(), m);
-        if (nb > 0)
-          S.gemm(m, m, nb, Fp.as<double>(), m, true, Fp.as<double>(), m, false, Dp.as<double>(), m, 1.0, 1.0);
+        hipLaunchKernelGGL(rohf_delta_kernel, dim3(nblk(m2)), dim3(256), 0, st, Fo[0].as<double>(),
+                           Fo[1].as<double>(), Pp[0].as<double>(), Pp[1].as<double>(), Rm.as<double>(),
+                           tm.as<double>(), m2);
+        S.gemm(m, m, m, tm.as<double>(), m, false, Rm.as<double>(), m, false, Feff.as<double>(), m);
+        hipLaunchKernelGGL(rohf_vc_kernel, dim3(nblk(m2)), dim3(256), 0, st, Pp[0].as<double>(),
+                           Pp[1].as<double>(), tm.as<double>(), m);
+        S.gemm(m, m, m, Feff.as<double>(), m, false, tm.as<double>(), m, false, Rm.as<double>(), m);
+        hipLaunchKernelGGL(rohf_feff_kernel, dim3(nblk(m2)), dim3(256), 0, st, Fo[0].as<double>(),
+                           Fo[1].as<double>(), Rm.as<double>(), Feff.as<double>(), m);
+        // D' = P_a + P_b; e = F_eff' D' - D' F_eff'
+        hipLaunchKernelGGL(add_kernel, dim3(nblk(m2)), dim3(256), 0, st, Pp[0].as<double>(), Pp[1].as<double>(),
+                           Dp.as<double>(), m2);
         S.gemm(m, m, m, Feff.as<double>(), m, false, Dp.as<double>(), m, false, tm.as<double>(), m);
         hipLaunchKernelGGL(antisym_kernel, dim3(nblk(m2)), dim3(256), 0, st, tm.as<double>(),
                            Eh[2 * hpos].as<double>(), m);
@@ -1545,7 +1598,7 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
                              o.level_shift, m);
           Fuse[0] = t1.as<double>();
         }
-        diag_orth(Fuse[0]);
+        update_orth(Fuse[0]);
         continue;
       }
       // diag overwrites t1 (X^T F): extrapolated alpha Fock matrix goes to F[0] first
@@ -1566,9 +1619,9 @@ static int open_shell_scf(const dfx_geom* geom, const dfx_shell* shells, int nsh
     DFX_HIP(hipStreamSynchronize(st));
     const auto t2c = clk::now();
     *E_out = E;
-    // UHF spins whose last occupied space came from purification: their orbitals
-    // and levels from one eigen-decomposition of the same F'
-    for (int s2 = 0; s2 < 2 && !restricted && (C_out || eps_out); ++s2)
+    // spins (UHF) or the one set (ROHF) whose last occupied space came from
+    // purification: orbitals and levels from one eigen-decomposition of the same F'
+    for (int s2 = 0; s2 < (restricted ? 1 : 2) && (C_out || eps_out); ++s2)
       if (!cm_valid[s2]) {
         DFX_HIP(hipMemcpyAsync(Fp.p, Fq[s2].p, 8 * (size_t)m * m, hipMemcpyDeviceToDevice, st));
         S.syevd(Fp.as<double>(), m, eps[s2].as<double>());

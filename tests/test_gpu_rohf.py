@@ -152,3 +152,25 @@ def test_open_shell_at_full_size(dfx):
     print(f"triplet: UHF {E_u:.9f} ({iu['niter']} it), ROHF {E_o:.9f} ({io['niter']} it)")
     assert iu["converged"] and io["converged"]
     assert iu["nbf"] == 730 and abs(E_o - E_u) < 0.05
+
+
+@pytest.mark.parametrize("charge,mult", [(1, 2), (0, 3)])
+def test_rohf_purification_matches_eigensolver(dfx, charge, mult):
+    """From the second iteration on, the core and core + open spaces come from
+    trace-correcting purification of the effective Fock matrix at n_beta and
+    n_alpha (purify = 1, the default): the energy, the spin densities and the
+    occupied levels equal those of a run with an eigen-decomposition every
+    iteration."""
+    xyz, Z, sh, ax = _system("mixed")
+    na, nb = _spins(Z, charge, mult)
+    kw = dict(conv_dE=1e-10, conv_err=1e-8, max_iter=200)
+    E0, C0, e0, i0 = dfx.rohf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, purify=0, **kw)
+    E1, C1, e1, i1 = dfx.rohf(xyz, Z, sh, ax, charge=charge, multiplicity=mult, purify=1, **kw)
+    assert i0["converged"] and i1["converged"]
+    assert i0["n_purified"] == 0 and i1["n_purified"] >= 2
+    assert abs(E1 - E0) <= 1e-10
+    for n_ in (na, nb):
+        D0, D1 = C0[:, :n_] @ C0[:, :n_].T, C1[:, :n_] @ C1[:, :n_].T
+        assert np.abs(D1 - D0).max() <= 1e-7 * max(1.0, np.abs(D0).max())
+    assert np.abs(e1[:na] - e0[:na]).max() <= 1e-7
+    print(f"q={charge} 2S+1={mult}: {i1['n_purified']} purified updates, {i1['n_eigh']} eigen-decompositions")
