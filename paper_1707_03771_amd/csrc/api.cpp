@@ -165,13 +165,17 @@ static const double RYS_COEFS[RYS_TABLE_SIZE] = RYS_TABLE_INIT;
 void rys_host_image(double* out) {
   int src = 0;
   for (int n = 1; n <= RYS_NMAX; ++n) {
-    const int nc = RYS_NINT[n] * 2 * n * (RYS_DEG + 1);
+    const int nc = 2 * n * (RYS_DEG + 1);  // coefficients of one interval
     double* dst = out + rys_dev_off(n);
-    std::memcpy(dst, RYS_COEFS + src, sizeof(double) * nc);
-    src += nc;
+    for (int k = 0; k < RYS_NINT[n]; ++k) {
+      std::memcpy(dst + (size_t)k * rys_blk(n), RYS_COEFS + src, sizeof(double) * nc);
+      for (int j = nc; j < rys_blk(n); ++j) dst[(size_t)k * rys_blk(n) + j] = 0.0;
+      src += nc;
+    }
+    double* lim = dst + (size_t)RYS_NINT[n] * rys_blk(n);
     for (int i = 0; i < n; ++i) {
-      dst[nc + i] = RYS_X2[n][i];
-      dst[nc + n + i] = RYS_W[n][i];
+      lim[i] = RYS_X2[n][i];
+      lim[n + i] = RYS_W[n][i];
     }
   }
 }

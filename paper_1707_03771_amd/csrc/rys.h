@@ -12,10 +12,17 @@
 
 namespace dfx {
 
-// Device table: for each n, [RYS_NINT[n] intervals][2n functions][RYS_DEG + 1]
-// coefficients, then n values x_i^2 and n values W_i of the large-T limit.
+// Device table: for each n, RYS_NINT[n] intervals of [2n functions][RYS_DEG + 1]
+// coefficients, each interval padded to an odd number of doubles (rys_blk), then
+// n values x_i^2 and n values W_i of the large-T limit.  The lanes of a wave read
+// the same coefficient of different intervals; with an even stride (2n (RYS_DEG
+// + 1) doubles) those reads fall on a few LDS banks, with an odd one they spread
+// over all of them.
+__host__ __device__ constexpr int rys_blk(int n) {
+  return (2 * n * (RYS_DEG + 1)) | 1;
+}
 __host__ __device__ constexpr int rys_dev_size(int n) {
-  return RYS_NINT[n] * 2 * n * (RYS_DEG + 1) + 2 * n;
+  return RYS_NINT[n] * rys_blk(n) + 2 * n;
 }
 __host__ __device__ constexpr int rys_dev_off(int n) {
   int s = 0;
@@ -37,12 +44,12 @@ struct RysPoint {
     constexpr double ih = 1.0 / RYS_HN[NR];
     asym = !(T < tmax);
     if (asym) {
-      blk = tab + RYS_NINT[NR] * 2 * NR * (RYS_DEG + 1);
+      blk = tab + RYS_NINT[NR] * rys_blk(NR);
       x = 1.0 / T;
       s = sqrt(x);
     } else {
       const int k = (int)(T * ih);
-      blk = tab + k * (2 * NR * (RYS_DEG + 1));
+      blk = tab + k * rys_blk(NR);
       x = (T - ((double)k * h + 0.5 * h)) * (2.0 * ih);
       s = 0.0;
     }
