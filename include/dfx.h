@@ -471,11 +471,13 @@ int dfx_grad_plan(const dfx_shell* shells, int nsh, const dfx_shell* aux, int na
  *   D_s = C_s,occ C_s,occ^T,  F_s = h + J[D_alpha + D_beta] - K[D_s]  (s = alpha, beta),
  *   E = 1/2 sum_s tr D_s (h + F_s) + E_nn,
  * one Pulay DIIS over both spins (error overlaps summed, both Fock matrices
- * extrapolated with the same coefficients), aufbau per spin (block Jacobi eigen-decomposition), start
+ * extrapolated with the same coefficients), aufbau per spin (from the second iteration
+ * on by purification, as for dfx_scf; the first update, a purification that does not
+ * settle and the returned orbitals by the block Jacobi eigen-decomposition), start
  * from the core Hamiltonian for both spins.  FP64 J and K throughout.
  *   opts          as for dfx_scf; guess must be DFX_GUESS_CORE and schedule
- *                 DFX_SCHED_FP64 (DFX_EINVAL otherwise); the purification, learned
- *                 guess and precision switches do not apply; level_shift applies
+ *                 DFX_SCHED_FP64 (DFX_EINVAL otherwise); the learned guess and
+ *                 precision switches do not apply; purify and level_shift apply
  *   multiplicity  2S + 1 >= 1; DFX_EINVAL if its parity does not match the electron
  *                 count, or if it exceeds nelec + 1
  *   E             host scalar out
@@ -501,10 +503,13 @@ int dfx_uhf(const dfx_geom* geom, const dfx_shell* shells, int nsh, const dfx_sh
  * F_s and E as for dfx_uhf.  The orbitals are the eigenvectors of Roothaan's
  * effective Fock matrix: in the basis of the current orbitals its core-open block
  * is that of F_beta, its open-virtual block that of F_alpha, every other block that
- * of (F_alpha + F_beta) / 2.  It is formed and diagonalised in the orthonormal
- * basis of X, and Pulay DIIS extrapolates it with the error F_eff D - D F_eff of
- * D = D_alpha + D_beta in that basis (zero exactly when the core-open, core-virtual
- * and open-virtual blocks are).  Arguments, options, errors and info as for
+ * of (F_alpha + F_beta) / 2.  It is formed in the orthonormal basis of X from the
+ * projectors onto the core, open and virtual spaces of the last update, and Pulay
+ * DIIS extrapolates it with the error F_eff D - D F_eff of D = D_alpha + D_beta in
+ * that basis (zero exactly when the core-open, core-virtual and open-virtual blocks
+ * are).  From the second iteration on the core and core + open spaces of the
+ * extrapolated matrix come by purification at n_beta and n_alpha (opts.purify);
+ * otherwise, and for the returned orbitals, by its eigen-decomposition.  Arguments, options, errors and info as for
  * dfx_uhf (err_max: the one error matrix), except that C is one set, host
  * [nbf][nbf] (core, open, virtual columns in that order), and eps host [nbf], the
  * eigenvalues of the effective Fock matrix last diagonalised (Roothaan's
